@@ -1,0 +1,109 @@
+"""Global Krylov (Lanczos) step on MPS (Sec. 2.2; readings A12, A13).
+
+Step i, given orthonormalised Krylov MPS v_0..v_i:
+  w_i = compressed H|v_i>                       (Sec. 3.2 / Algorithm 1)
+  h_ji = <v_j|w_i> for j <= i                   (eq. Krylov_H)
+  r = compress(w_i - sum_j h_ji v_j)             (Gram-Schmidt w.r.t. all previous)
+  beta_i = ||r||,  v_{i+1} = r / beta_i
+  S_{i+1,j} = <v_{i+1}|v_j>,  M_{i+1,l} = <v_{i+1}|w_l>
+Ritz values: (1) the tridiagonal (alpha_i = h_ii, beta_i) the paper assumes;
+(2) the generalised problem (H_sym, S) with H_sym = (M + M^T)/2, solved in
+the re-orthogonalised basis psi_a = sum_i C_ai v_i with C S C^T = I
+(eq. reortho, eq. eff_H): Cholesky, or canonical orthogonalisation when S is
+numerically singular.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import mps as M
+from .hamiltonian import apply_H, sum_compress
+
+S_EIG_FLOOR = 1e-10
+
+
+def ritz_tridiagonal(alpha, beta):
+    m = len(alpha)
+    T = np.diag(np.asarray(alpha, float))
+    for k in range(m - 1):
+        T[k, k + 1] = T[k + 1, k] = beta[k]
+    return np.linalg.eigvalsh(T)
+
+
+def ritz_generalized(Hm: np.ndarray, S: np.ndarray):
+    Hs = 0.5 * (Hm + Hm.T)
+    try:
+        Lc = np.linalg.cholesky(S)
+        Cm = np.linalg.inv(Lc)
+        return np.linalg.eigvalsh(Cm @ Hs @ Cm.T)
+    except np.linalg.LinAlgError:
+        s, U = np.linalg.eigh(S)
+        keep = s > S_EIG_FLOOR
+        X = U[:, keep] / np.sqrt(s[keep])
+        return np.linalg.eigvalsh(X.T @ Hs @ X)
+
+
+class KrylovState:
+    def __init__(self, v0, K: int):
+        nv = M.norm(v0)
+        self.v = [M.scale(v0, 1.0 / nv)]
+        self.w = []
+        self.K = K
+        self.Mm = np.zeros((K + 1, K + 1))
+        self.S = np.zeros((K + 1, K + 1))
+        self.S[0, 0] = M.overlap(self.v[0], self.v[0])
+        self.alpha = []
+        self.beta = []
+        self.breakdown = False
+
+    @property
+    def i(self):
+        return len(self.w)
+
+
+def krylov_step(st: KrylovState, t, chi, zeta, D, mode="tree", eps=M.CUTOFF, Hfun=None):
+    """One Lanczos step; returns (ritz_generalized, ritz_tridiagonal, beta_i)."""
+    i = st.i
+    vi = st.v[i]
+    wi = apply_H(vi, t, chi, zeta, D, mode=mode, eps=eps) if Hfun is None else Hfun(vi)
+    st.w.append(wi)
+    for j in range(i + 1):
+        st.Mm[j, i] = M.overlap(st.v[j], wi)
+    st.alpha.append(st.Mm[i, i])
+    coeffs = [1.0] + [-st.Mm[j, i] for j in range(i + 1)]
+    r = sum_compress(coeffs, [wi] + st.v[: i + 1], D, eps)
+    b = M.norm(r)
+    st.beta.append(b)
+    if b > 0.0 and i + 1 <= st.K:
+        v_new = M.scale(r, 1.0 / b)
+        st.v.append(v_new)
+        for j in range(i + 2):
+            st.S[i + 1, j] = st.S[j, i + 1] = M.overlap(v_new, st.v[j])
+        for l in range(i + 1):
+            st.Mm[i + 1, l] = M.overlap(v_new, st.w[l])
+    else:
+        st.breakdown = True
+    m = i + 1
+    rg = ritz_generalized(st.Mm[:m, :m], st.S[:m, :m])
+    rt = ritz_tridiagonal(st.alpha[:m], st.beta[: m - 1])
+    return rg, rt, b
+
+
+def dense_lanczos(Hmat_apply, v0: np.ndarray, K: int):
+    """Textbook Lanczos with full Gram-Schmidt on dense vectors (pin reference)."""
+    v = [v0 / np.linalg.norm(v0)]
+    Hv = []
+    ritz = []
+    for i in range(K):
+        w = Hmat_apply(v[i])
+        Hv.append(w)
+        r = w - sum((vj @ w) * vj for vj in v)
+        m = i + 1
+        Vm = np.stack(v)
+        Hp = Vm @ np.stack(Hv).T
+        ritz.append(np.linalg.eigvalsh(0.5 * (Hp + Hp.T)))
+        b = np.linalg.norm(r)
+        if b < 1e-12:
+            break
+        v.append(r / b)
+    return ritz
