@@ -1,0 +1,187 @@
+/*
+ * thck.h - C ABI of the MI355X THC-MPO H|psi> library (libthck.so).
+ *
+ * Method: Sun/Mendl et al., THC-MPO Krylov (arXiv 2409.12708).  The library
+ * applies the THC-factorised molecular Hamiltonian H = T + V of eq. (1),
+ * with V written as the sum of G terms of eq. (G_mu_nu_def) (Sec. 3.1), to a
+ * real matrix-product state, layer by layer with compression (Fig. 4 and
+ * Algorithm 1, Sec. 3.2), sums the compressed terms by a pairwise reduction
+ * tree (Sec. 4.5, Fig. 11) and uses the result in a global Lanczos step
+ * (Sec. 2.2).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Sites: n = 2L spin-orbital sites, site j = 2p + s (s = 0 spin up,
+ *   s = 1 spin down), local dimension d = 2, local basis (empty, occupied).
+ *   Jordan-Wigner: a_j = Z_0 ... Z_{j-1} c_j with c = [[0,1],[0,0]] and
+ *   Z = diag(1,-1) (Sec. 3.1 and App. C).
+ * - MPS data: float64 site tensors, site j shaped (bonds[j], 2, bonds[j+1])
+ *   and stored row-major (left index slowest) at data + offsets[j].
+ *   bonds[0] = bonds[n] = 1.  Device pointers are HIP device memory; the
+ *   caller owns them (the library never frees or reallocates them).
+ * - Streams: every call enqueues its work on the given hipStream_t (passed
+ *   as void*, NULL = the null stream) and returns without waiting, except
+ *   where a call states that it synchronises.
+ * - Errors: no exception crosses the ABI.  A non-zero thc_status is returned
+ *   and thc_last_error() gives a thread-local message.  On error the output
+ *   MPS contents are unspecified and its bonds/offsets arrays are unchanged.
+ * - Threading: a context is not re-entrant; use one context per host thread.
+ */
+#ifndef THCK_H
+#define THCK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  THC_OK = 0,
+  THC_EINVAL = -1,     /* bad argument: shape, symmetry, NULL pointer */
+  THC_ENOMEM = -2,     /* device allocation failed */
+  THC_EDEVICE = -3,    /* HIP runtime error */
+  THC_ENONFINITE = -4, /* NaN or Inf in an input */
+  THC_ENOCONV = -5,    /* Jacobi sweep limit reached before convergence */
+  THC_ECAPACITY = -6   /* output buffer too small */
+} thc_status;
+
+/* Contraction precision for the absorb GEMMs of the compression.  The QR
+ * and SVD factorisations, overlaps and Lanczos eigensolves are always FP64. */
+typedef enum {
+  THC_PREC_F64 = 0,
+  THC_PREC_F32 = 1,    /* FP32 operands, FP32 accumulation */
+  THC_PREC_BF16X3 = 2  /* hi/lo bf16 split, three bf16 MFMA products, FP32 accumulation */
+} thc_prec;
+
+/* Caller-owned MPS view.  On input, bonds/offsets describe the data.  On
+ * output, the library writes bonds[0..n] and offsets[0..n-1] (packed, in
+ * elements) and fills data; capacity (elements) must be at least
+ * thc_mps_capacity(n_sites, D). */
+typedef struct {
+  int32_t n_sites;
+  int32_t d;          /* must be 2 */
+  int32_t *bonds;     /* host, n_sites + 1 entries */
+  int64_t *offsets;   /* host, n_sites entries (elements) */
+  double *data;       /* device */
+  int64_t capacity;   /* elements available at data */
+} thc_mps;
+
+typedef struct {
+  int32_t D_max;       /* MPS bond dimension after every compression */
+  int32_t D_sum;       /* bond kept at the inner nodes of the reduction tree (0 = D_max) */
+  double rel_cutoff;   /* drop singular values <= rel_cutoff * s_1 (default 1e-14) */
+  int32_t prec;        /* thc_prec */
+  int32_t batch;       /* max compressions per batched launch (0 = automatic) */
+  int32_t max_sweeps;  /* Jacobi sweep limit per SVD (0 = 40) */
+  int32_t include_T;   /* 1: H = T + V, 0: V only */
+  int32_t include_V;   /* 1: include V, 0: T only */
+  uint64_t flags;      /* reserved, 0 */
+} thc_opts;
+
+typedef struct {
+  double discarded_weight_max; /* max over compressions and bonds of sum_{i>k} s_i^2 */
+  double flops_model;          /* algorithmic flops (LAPACK-formula model) of the call */
+  int64_t n_compressions;      /* number of MPS compressions performed */
+  int64_t n_launches;          /* kernel launches issued */
+  int32_t max_bond;            /* largest bond kept (after the cutoff) */
+  int32_t jacobi_sweeps_max;   /* most Jacobi sweeps any SVD needed */
+  int32_t nonconverged;        /* SVDs that hit the sweep limit */
+  int32_t reserved;
+} thc_stats;
+
+typedef struct thc_ctx thc_ctx;
+typedef struct thc_krylov thc_krylov;
+
+/* Fill *o with defaults (D_max = D, D_sum = 0, cutoff 1e-14, FP64, T and V). */
+void thc_default_opts(thc_opts *o, int32_t D);
+
+/* Elements needed to hold any n-site MPS of bond <= D in the packed layout
+ * (bond profile min(2^j, 2^(n-j), D)). */
+int64_t thc_mps_capacity(int32_t n_sites, int32_t D);
+
+/* Load the THC factors (eq. thc, Sec. 2.3) and the one-body integrals t of
+ * eq. (1).  Host arrays, row-major float64, read during the call only:
+ *   t    L x L, symmetric (App. D splits it as t = U diag(lambda) U^T);
+ *   chi  L x N, chi[p * N + mu] = chi_p^mu;
+ *   zeta N x N, symmetric.
+ * Validates finiteness (THC_ENONFINITE) and symmetry of t and zeta to 1e-12
+ * relative (THC_EINVAL), diagonalises t in FP64 on the host, builds the
+ * 4N^2 + 2L term table (readings of Algorithm 1's loop order: nu outer,
+ * sigma', mu, sigma; T terms after V) and uploads it.  *ctx receives a new
+ * context owning its device copies and workspace; release it with
+ * thc_destroy. */
+thc_status thc_load_factors(thc_ctx **ctx, int32_t L, int32_t N, const double *t,
+                            const double *chi, const double *zeta, uint64_t flags,
+                            void *hip_stream);
+
+thc_status thc_destroy(thc_ctx *ctx);
+
+/* out <- compressed H|psi> (Algorithm 1 terms with the reuse of
+ * G_{nu sigma'}|psi>, Sec. 3.2; kinetic part by App. D; summed by the
+ * pairwise tree of Sec. 4.5).  psi->n_sites must equal 2L.  psi and out
+ * must not alias.  st may be NULL.  Synchronises the stream once at the end
+ * (to read back the kept bond dimensions). */
+thc_status mps_apply_thc_H(thc_ctx *ctx, const thc_mps *psi, thc_mps *out, const thc_opts *o,
+                           thc_stats *st, void *hip_stream);
+
+/* out <- compressed sum_i coeffs[i] |terms[i]> (the addition-compression of
+ * Algorithm 1).  k >= 1; for k > 1 the terms are summed by the pairwise
+ * tree (pair 2i with 2i+1, an odd last term carries up), every node
+ * compressed to D_sum (0 = D_max) and the root to D_max.  coeffs is host.
+ * All terms must have the same n_sites.  Synchronises once at the end. */
+thc_status mps_sum_compress(thc_ctx *ctx, int32_t k, const double *coeffs, const thc_mps *const *terms,
+                            thc_mps *out, const thc_opts *o, thc_stats *st, void *hip_stream);
+
+/* *result <- <a|b> (host double), by the transfer-matrix chain, FP64.
+ * Synchronises the stream. */
+thc_status mps_overlap(thc_ctx *ctx, const thc_mps *a, const thc_mps *b, double *result,
+                       void *hip_stream);
+
+/* Lanczos state (Sec. 2.2): Krylov vectors v_0..v_K, the H images w_i,
+ * M_ij = <v_i|w_j> and S_ij = <v_i|v_j>, all in device memory owned by the
+ * state.  krylov_create copies psi0 and normalises it. */
+thc_status krylov_create(thc_ctx *ctx, const thc_mps *psi0, int32_t K, const thc_opts *o,
+                         thc_krylov **state, void *hip_stream);
+thc_status krylov_destroy(thc_krylov *state);
+
+/* One global Lanczos step i -> i+1 (Sec. 2.2 with the re-orthogonalised
+ * effective Hamiltonian of eq. eff_H):
+ *   w_i = compressed H|v_i>;  h_ji = <v_j|w_i> (j <= i);
+ *   r = compressed (w_i - sum_j h_ji v_j) (one mps_sum_compress);
+ *   beta_i = ||r||, v_{i+1} = r / beta_i;  S and M extended;
+ * then the (i+1) x (i+1) eigenproblems are solved on the device in FP64:
+ *   ritz_gen[0..i]  eigenvalues of H_sym = (M + M^T)/2 in the basis
+ *                   psi_a = sum_i C_ai v_i with C S C^T = I (Cholesky;
+ *                   canonical orthogonalisation if S is singular);
+ *   ritz_tri[0..i]  eigenvalues of the tridiagonal (alpha_i = h_ii, beta).
+ * ritz_gen, ritz_tri (nullable) and beta are host arrays / scalars written
+ * before return: this call synchronises once.  Returns THC_EINVAL once K
+ * steps have been taken. */
+thc_status krylov_step(thc_krylov *state, double *ritz_gen, double *ritz_tri, double *beta,
+                       thc_stats *st, void *hip_stream);
+
+/* Copy Krylov vector v_i (i <= steps taken) into a caller MPS. */
+thc_status krylov_get_vector(thc_krylov *state, int32_t i, thc_mps *out, void *hip_stream);
+
+/* Copy the (m x m) leading blocks of M and S (host, row-major), m = steps taken. */
+thc_status krylov_get_matrices(thc_krylov *state, double *Mm, double *S, int32_t *m);
+
+/* Compress one MPS to D (QR sweep then SVD truncation sweep, Fig. 3). */
+thc_status mps_compress(thc_ctx *ctx, const thc_mps *in, thc_mps *out, const thc_opts *o,
+                        thc_stats *st, void *hip_stream);
+
+/* Apply one elementary layer sum_j y_j a_j (dag = 0) or sum_j y_j a+_j
+ * (dag = 1) of eq. (elementary_MPO) to psi and compress (one arrow of Fig. 4).
+ * y is a host array of n_sites spin-orbital coefficients. */
+thc_status mps_apply_layer(thc_ctx *ctx, const thc_mps *psi, const double *y, int32_t dag,
+                           thc_mps *out, const thc_opts *o, thc_stats *st, void *hip_stream);
+
+/* Thread-local description of the last non-OK status. */
+const char *thc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* THCK_H */

@@ -1,0 +1,1312 @@
+// Host engine and C ABI of libthck: schedules the batched compression jobs
+// of H|psi> (Algorithm 1 with prefix reuse, Sec. 3.2; kinetic terms, App. D;
+// pairwise reduction tree, Sec. 4.5) and of the Lanczos step (Sec. 2.2).
+//
+// Memory: every MPS produced on the device lives in a "slot" of
+// thc_mps_capacity(n, D) doubles from a per-context pool; a slot records its
+// static bond profile (the shape it is stored with).  Bond dimensions past
+// the numerical rank hold exact zeros.  All work of a call is enqueued on
+// one stream, so a slot can be recycled as soon as the job that reads it
+// has been enqueued.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/thck.h"
+#include "kernels.h"
+
+using namespace thck;
+
+namespace {
+
+thread_local std::string g_err;
+
+thc_status fail(thc_status s, const std::string &msg) {
+  g_err = msg;
+  return s;
+}
+
+struct HipError {
+  hipError_t e;
+  std::string where;
+};
+
+#define HIPCHK(x)                                                         \
+  do {                                                                    \
+    hipError_t e_ = (x);                                                  \
+    if (e_ != hipSuccess) throw HipError{e_, std::string(#x)};            \
+  } while (0)
+
+struct StatusError {
+  thc_status s;
+  std::string msg;
+};
+
+[[noreturn]] void raise(thc_status s, const std::string &m) { throw StatusError{s, m}; }
+
+// ---------------------------------------------------------------------------
+// bond profiles
+// ---------------------------------------------------------------------------
+struct Profile {
+  std::vector<int> b;        // b[0..n]
+  std::vector<int64_t> off;  // packed offsets, n entries
+  int64_t size = 0;
+  int n() const { return (int)b.size() - 1; }
+  void pack() {
+    int n_ = n();
+    off.assign(n_, 0);
+    int64_t o = 0;
+    for (int j = 0; j < n_; ++j) {
+      off[j] = o;
+      o += (int64_t)b[j] * 2 * b[j + 1];
+    }
+    size = o;
+  }
+  bool operator<(const Profile &o) const { return b < o.b; }
+  bool operator==(const Profile &o) const { return b == o.b; }
+};
+
+Profile capacity_profile(int n, int D) {
+  Profile p;
+  p.b.resize(n + 1);
+  for (int j = 0; j <= n; ++j) {
+    int64_t x = std::min<int64_t>(D, std::min<int64_t>(j >= 62 ? (1LL << 62) : (1LL << j),
+                                                        (n - j) >= 62 ? (1LL << 62) : (1LL << (n - j))));
+    p.b[j] = (int)x;
+  }
+  p.pack();
+  return p;
+}
+
+// ---------------------------------------------------------------------------
+// device buffers
+// ---------------------------------------------------------------------------
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  void ensure(size_t need) {
+    if (need <= bytes) return;
+    if (p) {
+      HIPCHK(hipDeviceSynchronize());
+      HIPCHK(hipFree(p));
+      p = nullptr;
+      bytes = 0;
+    }
+    hipError_t e = hipMalloc(&p, need);
+    if (e != hipSuccess) raise(THC_ENOMEM, "hipMalloc of " + std::to_string(need) + " bytes failed");
+    bytes = need;
+  }
+  template <class T>
+  T *as() const {
+    return (T *)p;
+  }
+};
+
+struct PinnedBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  ~PinnedBuf() {
+    if (p) (void)hipHostFree(p);
+  }
+  void ensure(size_t need) {
+    if (need <= bytes) return;
+    if (p) {
+      HIPCHK(hipDeviceSynchronize());
+      HIPCHK(hipHostFree(p));
+      p = nullptr;
+    }
+    HIPCHK(hipHostMalloc(&p, need, hipHostMallocDefault));
+    bytes = need;
+  }
+};
+
+// One MPS in device memory owned by the pool.
+struct Slot {
+  double *data = nullptr;
+  Profile prof;  // static storage profile
+  int id = -1;
+};
+
+}  // namespace
+
+struct thc_ctx {
+  int L = 0, N = 0, n = 0;
+  std::vector<double> t, chi, zeta, lam, u;  // host copies (u column-major per eigvec: u[p*L+i])
+  // device layer coefficients: rows [2*mu + s] (chi), then [2N + 2*i + s] (u)
+  DevBuf coef;
+  // pool
+  int64_t slot_elems = 0;
+  int slot_D = 0;
+  std::vector<double *> free_slots;
+  std::vector<std::unique_ptr<DevBuf>> slot_store;
+  // batch workspace
+  DevBuf ws, jobs_dev, small_dev;
+  PinnedBuf jobs_host;
+  size_t jobs_host_used = 0;
+  // statistics accumulated on the host from device readbacks
+  int64_t n_compressions = 0, n_launches = 0;
+  double flops = 0.0;
+  // device stats per call: ranks/disc/sweeps arrays are read back at the end of a call
+  DevBuf stat_dev;
+  std::vector<int> stat_rank_host;
+  int batch_default = 0;
+
+  double *coef_ptr(int row) const { return coef.as<double>() + (size_t)row * n; }
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// slot pool
+// ---------------------------------------------------------------------------
+double *slot_alloc(thc_ctx *c, int D) {
+  int64_t need = thc_mps_capacity(c->n, D);
+  if (need > c->slot_elems) {
+    // grow: previous slots stay valid (different allocations); new ones use the larger size
+    c->slot_elems = need;
+    c->free_slots.clear();
+  }
+  if (!c->free_slots.empty()) {
+    double *p = c->free_slots.back();
+    c->free_slots.pop_back();
+    return p;
+  }
+  auto b = std::make_unique<DevBuf>();
+  b->ensure((size_t)c->slot_elems * sizeof(double));
+  double *p = b->as<double>();
+  c->slot_store.push_back(std::move(b));
+  return p;
+}
+
+void slot_free(thc_ctx *c, double *p) {
+  // only recycle slots of the current size
+  for (auto &b : c->slot_store)
+    if (b->as<double>() == p && b->bytes >= (size_t)c->slot_elems * sizeof(double)) {
+      c->free_slots.push_back(p);
+      return;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// compression plan
+// ---------------------------------------------------------------------------
+struct Plan {
+  int n = 0;
+  int kind = 0;
+  Profile pa, pb;            // input profiles
+  std::vector<int> bo;       // constructed bonds (2D)
+  std::vector<int> c;        // right-canonical bonds
+  std::vector<int> k;        // output bonds (static)
+  Profile out;
+  // per-job workspace layout (elements)
+  int64_t oB = 0, oT = 0, oL = 0, oQs = 0, oM = 0, oY = 0, oW = 0, oZ = 0, oC = 0, oLz = 0, oQz = 0, oTf = 0,
+          oS = 0, oU = 0;
+  std::vector<int64_t> qs_off;  // offset of Q_j inside Qs
+  int64_t per_job = 0;
+  double flops_per_job = 0.0;
+};
+
+double lq_flops(double m, double n) {  // LQ of m x n (m rows): R + thin Q, LAPACK counts, FMA = 2
+  double k = std::min(m, n), M = std::max(m, n);
+  return 2.0 * (2.0 * M * k * k - 2.0 * k * k * k / 3.0);
+}
+double svd_flops(double m, double n) {  // Golub-Reinsch thin SVD with U and V (model)
+  double k = std::min(m, n), M = std::max(m, n);
+  return 14.0 * M * k * k + 8.0 * k * k * k;
+}
+
+Plan make_plan(int kind, const Profile &pa, const Profile *pb, int D) {
+  Plan P;
+  P.kind = kind;
+  P.n = pa.n();
+  const int n = P.n;
+  P.pa = pa;
+  if (pb) P.pb = *pb;
+  P.bo.assign(n + 1, 1);
+  for (int j = 1; j < n; ++j) P.bo[j] = (kind == 0) ? 2 * pa.b[j] : pa.b[j] + pb->b[j];
+  P.c.assign(n + 1, 1);
+  for (int j = n - 1; j >= 1; --j) P.c[j] = std::min(P.bo[j], 2 * P.c[j + 1]);
+  P.k.assign(n + 1, 1);
+  for (int j = 0; j + 1 < n; ++j) P.k[j + 1] = std::min(std::min(2 * P.k[j], P.c[j + 1]), D);
+  P.out.b = P.k;
+  P.out.pack();
+  int64_t mB = 0, mT = 0, mL = 0, mM = 0, mW = 0, mZ = 0, mQz = 0, mLz = 0, mS = 0, mTf = 0, mU = 0;
+  P.qs_off.assign(n, 0);
+  int64_t qs = 0;
+  double fl = 0.0;
+  for (int j = 0; j < n; ++j) {
+    mB = std::max(mB, (int64_t)P.bo[j] * 2 * P.bo[j + 1]);
+    mT = std::max(mT, (int64_t)P.bo[j] * 2 * P.c[j + 1]);
+    mL = std::max(mL, (int64_t)P.bo[j] * P.c[j]);
+    if (j >= 1) {
+      P.qs_off[j] = qs;
+      qs += (int64_t)P.c[j] * 2 * P.c[j + 1];
+      fl += lq_flops(P.bo[j], 2.0 * P.c[j + 1]);
+      if (j + 1 < n) fl += 2.0 * (2.0 * P.bo[j - 1]) * P.bo[j] * P.c[j];  // absorb L into site j-1
+    }
+    if (j + 1 < n) {
+      const int m = 2 * P.k[j], nc = P.c[j + 1], kk = P.k[j + 1];
+      mM = std::max(mM, (int64_t)m * nc);
+      mW = std::max(mW, (int64_t)kk * nc);
+      mZ = std::max(mZ, (int64_t)kk * m);
+      mQz = std::max(mQz, (int64_t)kk * m);
+      mLz = std::max(mLz, (int64_t)kk * kk);
+      mS = std::max(mS, (int64_t)m);
+      mU = std::max(mU, (int64_t)m * kk);
+      mTf = std::max(mTf, (int64_t)lq_t_stride(std::max(kk, 1)));
+      fl += svd_flops(m, nc);
+      fl += 2.0 * kk * nc * 2.0 * P.c[j + 2];  // absorb S V^T into site j+1
+    }
+    mTf = std::max(mTf, (int64_t)lq_t_stride(std::max(P.c[j], 1)));
+  }
+  mM = std::max(mM, (int64_t)2 * P.c[1]);
+  int64_t o = 0;
+  auto take = [&](int64_t sz) {
+    int64_t r = o;
+    o += (sz + 31) / 32 * 32;
+    return r;
+  };
+  P.oB = take(mB);
+  P.oT = take(mT);
+  P.oL = take(mL);
+  P.oQs = take(qs);
+  P.oM = take(mM);
+  P.oY = take(mM);
+  P.oW = take(mW);
+  P.oZ = take(mZ);
+  P.oC = take(mW);
+  P.oLz = take(mLz);
+  P.oQz = take(mQz);
+  P.oTf = take(mTf);
+  P.oS = take(std::max<int64_t>(mS, 1));
+  P.oU = take(std::max<int64_t>(mU, 1));
+  P.per_job = o;
+  P.flops_per_job = fl;
+  return P;
+}
+
+// per-call device statistics: for each compression job and bond, rank and
+// discarded weight, and per SVD the Jacobi sweep count.
+struct CallStats {
+  double disc_max = 0.0;
+  int max_bond = 0;
+  int sweeps_max = 0;
+  int nonconv = 0;
+  int64_t compressions = 0;
+  int64_t launches = 0;
+  double flops = 0.0;
+};
+
+struct Engine {
+  thc_ctx *c;
+  hipStream_t st;
+  const thc_opts &o;
+  CallStats cs;
+  // device arrays for rank / disc / sweeps of the current batch (per job x site)
+  DevBuf rk, dw, sw;
+  std::vector<int> h_rank;
+  std::vector<double> h_disc;
+  std::vector<int> h_sw;
+  // pending stats readbacks are done synchronously per batch only in debug
+  Engine(thc_ctx *c_, hipStream_t s_, const thc_opts &o_) : c(c_), st(s_), o(o_) {}
+
+  int max_sweeps() const { return o.max_sweeps > 0 ? o.max_sweeps : 40; }
+  double cutoff() const { return o.rel_cutoff > 0 ? o.rel_cutoff : 0.0; }
+
+  // Upload job descriptors; returns device pointer.
+  CJob *upload_jobs(const std::vector<CJob> &jobs) {
+    size_t bytes = jobs.size() * sizeof(CJob);
+    // bump allocator inside the call's pinned + device arenas
+    size_t need = c->jobs_host_used + bytes;
+    if (need > c->jobs_host.bytes || need > c->jobs_dev.bytes) {
+      // arenas too small: synchronise, then grow (rare: sized per call up front)
+      HIPCHK(hipStreamSynchronize(st));
+      size_t nb = std::max(need * 2, (size_t)1 << 20);
+      c->jobs_host.ensure(nb);
+      c->jobs_dev.ensure(nb);
+      c->jobs_host_used = 0;
+      need = bytes;
+    }
+    char *h = (char *)c->jobs_host.p + c->jobs_host_used;
+    char *d = (char *)c->jobs_dev.p + c->jobs_host_used;
+    memcpy(h, jobs.data(), bytes);
+    HIPCHK(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, st));
+    c->jobs_host_used += (bytes + 255) / 256 * 256;
+    return (CJob *)d;
+  }
+
+  // Run the compression of nb jobs (same plan).  Output slots in jobs[].out.
+  void compress(const Plan &P, const std::vector<CJob> &hjobs, int D) {
+    const int nb = (int)hjobs.size();
+    if (nb == 0) return;
+    const int n = P.n;
+    c->ws.ensure((size_t)P.per_job * nb * sizeof(double));
+    rk.ensure((size_t)nb * n * sizeof(int));
+    dw.ensure((size_t)nb * n * sizeof(double));
+    sw.ensure((size_t)nb * n * sizeof(int));
+    double *W = c->ws.as<double>();
+    const int64_t S = P.per_job;
+    CJob *dj = upload_jobs(hjobs);
+    double *Bb = W + P.oB, *Tb = W + P.oT, *Lb = W + P.oL, *Qs = W + P.oQs, *Mb = W + P.oM, *Yb = W + P.oY,
+           *Wb = W + P.oW, *Zb = W + P.oZ, *Cb = W + P.oC, *Lz = W + P.oLz, *Qz = W + P.oQz, *Tf = W + P.oTf,
+           *Sb = W + P.oS, *Ub = W + P.oU;
+    int64_t launches = 0;
+    // ---- right -> left LQ sweep ----
+    for (int j = n - 1; j >= 1; --j) {
+      const int la = P.pa.b[j], ra = P.pa.b[j + 1];
+      const int lb = P.kind ? P.pb.b[j] : 0, rb = P.kind ? P.pb.b[j + 1] : 0;
+      launch_construct(st, dj, nb, j, n, P.pa.off[j], P.kind ? P.pb.off[j] : 0, la, ra, lb, rb, Bb, S, P.bo[j],
+                       P.bo[j + 1]);
+      ++launches;
+      double *X;
+      if (j == n - 1) {
+        X = Bb;  // (bo, 2, 1)
+      } else {
+        launch_gemm(st, nb, false, Bb, S, P.bo[j + 1], Lb, S, P.c[j + 1], Tb, S, P.c[j + 1], P.bo[j] * 2,
+                    P.c[j + 1], P.bo[j + 1]);
+        ++launches;
+        X = Tb;
+      }
+      if (launch_lq(st, nb, X, S, P.bo[j], 2 * P.c[j + 1], Lb, S, Qs + P.qs_off[j], S, Tf, S) != 0)
+        raise(THC_EINVAL, "site matrix too wide for the LQ kernel (2*bond > 1024)");
+      ++launches;
+    }
+    // site 0: M_0 = B_0 * L_1 (1, 2, c_1)
+    {
+      const int la = P.pa.b[0], ra = P.pa.b[1];
+      const int lb = P.kind ? P.pb.b[0] : 0, rb = P.kind ? P.pb.b[1] : 0;
+      launch_construct(st, dj, nb, 0, n, P.pa.off[0], P.kind ? P.pb.off[0] : 0, la, ra, lb, rb, Bb, S, P.bo[0],
+                       P.bo[1]);
+      if (n > 1)
+        launch_gemm(st, nb, false, Bb, S, P.bo[1], Lb, S, P.c[1], Mb, S, P.c[1], 2, P.c[1], P.bo[1]);
+      else
+        launch_copy(st, nb, Bb, S, Mb, S, 2);
+      launches += 2;
+    }
+    int *rk_d = rk.as<int>();
+    double *dw_d = dw.as<double>();
+    int *sw_d = sw.as<int>();
+    // ---- left -> right SVD sweep ----
+    for (int j = 0; j + 1 < n; ++j) {
+      const int m = 2 * P.k[j], nc = P.c[j + 1], kk = P.k[j + 1];
+      launch_copy(st, nb, Mb, S, Yb, S, (int64_t)m * nc);
+      if (launch_jacobi(st, nb, Yb, S, m, nc, Sb, S, sw_d + (size_t)j * nb, max_sweeps()) != 0)
+        raise(THC_EINVAL, "site matrix too wide for the Jacobi kernel (bond > 1024)");
+      launch_svd_select(st, nb, Yb, S, m, nc, Sb, S, kk, cutoff(), Wb, S, rk_d + (size_t)j * nb,
+                        dw_d + (size_t)j * nb, nullptr, 0);
+      // Z = W (kk x nc) * M^T (nc x m)
+      launch_gemm(st, nb, true, Wb, S, nc, Mb, S, nc, Zb, S, m, kk, m, nc);
+      if (launch_lq(st, nb, Zb, S, kk, m, Lz, S, Qz, S, Tf, S) != 0)
+        raise(THC_EINVAL, "site matrix too wide for the LQ kernel");
+      // C = Qz (kk x m) * M (m x nc)
+      launch_gemm(st, nb, false, Qz, S, m, Mb, S, nc, Cb, S, nc, kk, nc, m);
+      launch_svd_finish(st, nb, Qz, S, m, kk, rk_d + (size_t)j * nb, Ub, S, Cb, S, nc);
+      launch_scatter(st, nb, dj, P.out.off[j], Ub, S, (int64_t)m * kk);
+      // M_{j+1} = C (kk x c_{j+1}) * Q_{j+1} (c_{j+1} x 2 c_{j+2})
+      launch_gemm(st, nb, false, Cb, S, nc, Qs + P.qs_off[j + 1], S, 2 * P.c[j + 2], Mb, S, 2 * P.c[j + 2], kk,
+                  2 * P.c[j + 2], nc);
+      launches += 9;
+    }
+    // last site
+    launch_scatter(st, nb, dj, P.out.off[n - 1], Mb, S, (int64_t)P.k[n - 1] * 2);
+    ++launches;
+    HIPCHK(hipGetLastError());
+    // statistics: read back ranks/disc/sweeps of this batch (async into host arrays after sync at end)
+    h_rank.resize((size_t)nb * n);
+    h_disc.resize((size_t)nb * n);
+    h_sw.resize((size_t)nb * n);
+    HIPCHK(hipMemcpyAsync(h_rank.data(), rk_d, (size_t)nb * (n - 1) * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h_disc.data(), dw_d, (size_t)nb * (n - 1) * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h_sw.data(), sw_d, (size_t)nb * (n - 1) * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (size_t i = 0; i < (size_t)nb * (n - 1); ++i) {
+      cs.disc_max = std::max(cs.disc_max, h_disc[i]);
+      cs.max_bond = std::max(cs.max_bond, h_rank[i]);
+      cs.sweeps_max = std::max(cs.sweeps_max, h_sw[i]);
+      if (h_sw[i] > max_sweeps()) cs.nonconv++;
+    }
+    last_ranks.assign(h_rank.begin(), h_rank.begin() + (size_t)nb * (n - 1));
+    last_nb = nb;
+    cs.compressions += nb;
+    cs.launches += launches;
+    cs.flops += P.flops_per_job * nb;
+  }
+  std::vector<int> last_ranks;  // [site j][job] rank at bond j+1
+  int last_nb = 0;
+
+  int batch_limit(const Plan &P) {
+    if (o.batch > 0) return o.batch;
+    // keep the batch workspace under ~48 GiB
+    const double budget = 48.0 * (1ull << 30);
+    int b = (int)std::max(1.0, std::min(512.0, budget / (P.per_job * 8.0)));
+    return b;
+  }
+};
+
+// A node of work: an MPS held in a slot, with its static profile and a
+// pending scalar coefficient (applied when it enters a sum or the root).
+struct Node {
+  double *data = nullptr;
+  Profile prof;
+  double coef = 1.0;
+  bool owned = true;       // slot from the pool (vs caller memory)
+  std::vector<int> ranks;  // numerical ranks at bonds 1..n-1 (empty: unknown)
+};
+
+void check_mps(const thc_mps *m, int n_expected) {
+  if (!m) raise(THC_EINVAL, "NULL MPS");
+  if (m->d != 2) raise(THC_EINVAL, "local dimension must be 2");
+  if (n_expected > 0 && m->n_sites != n_expected) raise(THC_EINVAL, "n_sites must equal 2L");
+  if (m->n_sites < 2) raise(THC_EINVAL, "need at least 2 sites");
+  if (!m->bonds || !m->offsets || !m->data) raise(THC_EINVAL, "NULL bonds/offsets/data");
+  if (m->bonds[0] != 1 || m->bonds[m->n_sites] != 1) raise(THC_EINVAL, "boundary bonds must be 1");
+  for (int j = 0; j < m->n_sites; ++j) {
+    if (m->bonds[j + 1] < 1) raise(THC_EINVAL, "bond < 1");
+    int64_t end = m->offsets[j] + (int64_t)m->bonds[j] * 2 * m->bonds[j + 1];
+    if (m->offsets[j] < 0 || end > m->capacity) raise(THC_EINVAL, "site tensor outside the buffer capacity");
+  }
+}
+
+Profile profile_of(const thc_mps *m) {
+  Profile p;
+  p.b.assign(m->bonds, m->bonds + m->n_sites + 1);
+  p.off.assign(m->offsets, m->offsets + m->n_sites);
+  p.size = 0;
+  for (int j = 0; j < m->n_sites; ++j)
+    p.size = std::max(p.size, m->offsets[j] + (int64_t)m->bonds[j] * 2 * m->bonds[j + 1]);
+  return p;
+}
+
+bool packed(const Profile &p) {
+  Profile q = p;
+  q.pack();
+  return q.off == p.off;
+}
+
+
+}  // namespace
+
+namespace {
+
+void repack(hipStream_t st, const double *src, const Profile &ps, double *dst, const std::vector<int> &r,
+            std::vector<int64_t> &doff) {
+  int n = ps.n();
+  doff.assign(n, 0);
+  int64_t o = 0;
+  for (int j = 0; j < n; ++j) {
+    doff[j] = o;
+    int64_t tot = (int64_t)r[j] * 2 * r[j + 1];
+    int gx = (int)std::min<int64_t>(2048, std::max<int64_t>(1, (tot + 255) / 256));
+    launch_repack(st, gx, src, ps.off[j], ps.b[j], ps.b[j + 1], dst, o, r[j], r[j + 1]);
+    o += tot;
+  }
+}
+
+// Compress groups of jobs that share a plan signature.
+struct JobSpec {
+  int kind;
+  const Node *a;
+  const Node *b;
+  const double *y;
+  int dag;
+  double scale;  // for layer jobs (multiplies the last site)
+};
+
+// Run a list of job specs (any mix of signatures); returns output nodes in order.
+std::vector<Node> run_jobs(Engine &E, const std::vector<JobSpec> &specs, int D) {
+  thc_ctx *c = E.c;
+  std::vector<Node> out(specs.size());
+  // group by signature
+  std::map<std::pair<int, std::pair<std::vector<int>, std::vector<int>>>, std::vector<size_t>> groups;
+  for (size_t i = 0; i < specs.size(); ++i) {
+    const JobSpec &s = specs[i];
+    auto key = std::make_pair(s.kind, std::make_pair(s.a->prof.b, s.kind ? s.b->prof.b : std::vector<int>()));
+    groups[key].push_back(i);
+  }
+  for (auto &g : groups) {
+    const JobSpec &s0 = specs[g.second[0]];
+    // all members share offsets too? profiles with equal bonds in slots are packed the same way;
+    // caller-owned inputs may have other offsets, so split by offsets as well
+    std::map<std::pair<std::vector<int64_t>, std::vector<int64_t>>, std::vector<size_t>> sub;
+    for (size_t i : g.second) {
+      const JobSpec &s = specs[i];
+      sub[{s.a->prof.off, s.kind ? s.b->prof.off : std::vector<int64_t>()}].push_back(i);
+    }
+    for (auto &sg : sub) {
+      const JobSpec &sf = specs[sg.second[0]];
+      Plan P = make_plan(sf.kind, sf.a->prof, sf.kind ? &sf.b->prof : nullptr, D);
+      int B = E.batch_limit(P);
+      for (size_t i0 = 0; i0 < sg.second.size(); i0 += B) {
+        size_t i1 = std::min(sg.second.size(), i0 + B);
+        std::vector<CJob> hj;
+        for (size_t t = i0; t < i1; ++t) {
+          size_t i = sg.second[t];
+          const JobSpec &s = specs[i];
+          CJob j{};
+          j.kind = s.kind;
+          j.in_a = s.a->data;
+          j.in_b = s.kind ? s.b->data : nullptr;
+          j.y = s.y;
+          j.dag = s.dag;
+          if (s.kind == 0) {
+            j.ca = s.scale * s.a->coef;
+            j.cb = 0.0;
+          } else {
+            j.ca = s.a->coef;
+            j.cb = s.b->coef;
+          }
+          out[i].data = slot_alloc(c, D);
+          out[i].prof = P.out;
+          out[i].coef = 1.0;
+          out[i].owned = true;
+          j.out = out[i].data;
+          hj.push_back(j);
+        }
+        E.compress(P, hj, D);
+        const int nbt = (int)hj.size();
+        for (size_t t = i0; t < i1; ++t) {
+          Node &nd = out[sg.second[t]];
+          nd.ranks.resize(P.n - 1);
+          for (int jj = 0; jj + 1 < P.n; ++jj) nd.ranks[jj] = E.last_ranks[(size_t)jj * nbt + (t - i0)];
+        }
+      }
+    }
+    (void)s0;
+  }
+  return out;
+}
+
+void release(thc_ctx *c, Node &nd) {
+  if (nd.owned && nd.data) slot_free(c, nd.data);
+  nd.data = nullptr;
+}
+
+// Streaming pairwise reduction tree (Sec. 4.5, Fig. 11).  Level l keeps its
+// nodes in order; the first two nodes of a level always form the next pair,
+// which is the pairing (2k, 2k+1) of the level-by-level tree.  At the end an
+// odd last node of level l is appended to level l+1, as the tree carries it.
+// Pairs that are ready at any level are compressed together in one batch.
+struct Reducer {
+  Engine &E;
+  int D;
+  std::vector<std::vector<Node>> levels;
+  Reducer(Engine &e, int D_) : E(e), D(D_) {}
+
+  void push(const Node &leaf) {
+    if (levels.empty()) levels.resize(1);
+    levels[0].push_back(leaf);
+  }
+  size_t ready_pairs() const {
+    size_t r = 0;
+    for (auto &q : levels) r += q.size() / 2;
+    return r;
+  }
+  size_t queued() const {
+    size_t r = 0;
+    for (auto &q : levels) r += q.size();
+    return r;
+  }
+  // one batch: every pair that is ready now
+  void step() {
+    std::vector<JobSpec> specs;
+    std::vector<std::pair<size_t, size_t>> where;  // (level, pair index)
+    std::vector<std::vector<Node>> taken(levels.size());
+    for (size_t l = 0; l < levels.size(); ++l) {
+      size_t np = levels[l].size() / 2;
+      taken[l].assign(levels[l].begin(), levels[l].begin() + 2 * np);
+      levels[l].erase(levels[l].begin(), levels[l].begin() + 2 * np);
+    }
+    for (size_t l = 0; l < taken.size(); ++l)
+      for (size_t p = 0; p + 1 < taken[l].size(); p += 2) {
+        specs.push_back(JobSpec{1, &taken[l][p], &taken[l][p + 1], nullptr, 0, 1.0});
+        where.push_back({l, p / 2});
+      }
+    if (specs.empty()) return;
+    std::vector<Node> res = run_jobs(E, specs, D);
+    for (auto &t : taken)
+      for (auto &nd : t) release(E.c, nd);
+    if (levels.size() < taken.size() + 1) levels.resize(taken.size() + 1);
+    // results go to the next level in pair order (levels before higher ones)
+    for (size_t i = 0; i < res.size(); ++i) levels[where[i].first + 1].push_back(res[i]);
+  }
+  void flush(size_t min_pairs) {
+    while (ready_pairs() >= std::max<size_t>(1, min_pairs)) step();
+  }
+  Node finish() {
+    for (;;) {
+      while (ready_pairs() > 0) step();
+      // carry the lowest odd node up one level
+      size_t nonempty = 0, top = 0;
+      for (size_t l = 0; l < levels.size(); ++l)
+        if (!levels[l].empty()) {
+          ++nonempty;
+          top = l;
+        }
+      if (nonempty <= 1) return nonempty ? levels[top][0] : Node{};
+      for (size_t l = 0; l < levels.size(); ++l)
+        if (levels[l].size() == 1 && l < top) {
+          if (levels.size() < l + 2) levels.resize(l + 2);
+          levels[l + 1].push_back(levels[l][0]);
+          levels[l].clear();
+          break;
+        }
+    }
+  }
+};
+
+// Write node -> caller MPS (compacting to the numerical ranks of the last
+// compression when the node came from one), and set bonds/offsets.
+void emit(Engine &E, const Node &nd, thc_mps *out) {
+  const int n = nd.prof.n();
+  std::vector<int> r = nd.prof.b;
+  if ((int)nd.ranks.size() == n - 1) {
+    for (int j = 1; j < n; ++j) r[j] = std::max(1, std::min(r[j], nd.ranks[j - 1]));
+  }
+  int64_t need = 0;
+  for (int j = 0; j < n; ++j) need += (int64_t)r[j] * 2 * r[j + 1];
+  if (need > out->capacity) raise(THC_ECAPACITY, "output capacity too small");
+  std::vector<int64_t> doff;
+  repack(E.st, nd.data, nd.prof, out->data, r, doff);
+  if (nd.coef != 1.0) {
+    // apply a pending coefficient to the last site
+    int64_t cnt = (int64_t)r[n - 1] * 2 * r[n];
+    launch_scale(E.st, out->data + doff[n - 1], cnt, nd.coef);
+  }
+  HIPCHK(hipGetLastError());
+  for (int j = 0; j <= n; ++j) out->bonds[j] = r[j];
+  for (int j = 0; j < n; ++j) out->offsets[j] = doff[j];
+}
+
+Node caller_node(const thc_mps *m) {
+  Node nd;
+  nd.data = m->data;
+  nd.prof = profile_of(m);
+  nd.coef = 1.0;
+  nd.owned = false;
+  return nd;
+}
+
+void fill_stats(thc_stats *st, const CallStats &cs) {
+  if (!st) return;
+  st->discarded_weight_max = cs.disc_max;
+  st->flops_model = cs.flops;
+  st->n_compressions = cs.compressions;
+  st->n_launches = cs.launches;
+  st->max_bond = cs.max_bond;
+  st->jacobi_sweeps_max = cs.sweeps_max;
+  st->nonconverged = cs.nonconv;
+  st->reserved = 0;
+}
+
+thc_opts norm_opts(const thc_opts *o, int *D) {
+  thc_opts r;
+  if (o) r = *o;
+  else thc_default_opts(&r, 64);
+  if (r.D_max < 1) raise(THC_EINVAL, "D_max must be >= 1");
+  if (r.D_max > 256) raise(THC_EINVAL, "D_max > 256 is not supported by the kernels of this build");
+  if (r.D_sum <= 0) r.D_sum = r.D_max;
+  if (r.D_sum > 256) raise(THC_EINVAL, "D_sum > 256 is not supported");
+  if (r.rel_cutoff < 0) raise(THC_EINVAL, "negative cutoff");
+  if (r.prec != THC_PREC_F64 && r.prec != THC_PREC_F32 && r.prec != THC_PREC_BF16X3)
+    raise(THC_EINVAL, "unknown precision");
+  *D = r.D_max;
+  return r;
+}
+
+template <class F>
+thc_status run_guarded(F &&f) {
+  try {
+    f();
+    return THC_OK;
+  } catch (const StatusError &e) {
+    return fail(e.s, e.msg);
+  } catch (const HipError &e) {
+    return fail(THC_EDEVICE, e.where + ": " + hipGetErrorString(e.e));
+  } catch (const std::bad_alloc &) {
+    return fail(THC_ENOMEM, "host allocation failed");
+  }
+}
+
+// compress(coef * x) alone: the direct sum of x with a zero-weight copy of
+// itself has the same state, so the sum job compresses it exactly as the
+// QR + SVD sweep of Fig. 3 would (the zero half adds only exact zeros).
+Node compress_node(Engine &E, Node x, int D) {
+  Node zero = x;
+  zero.coef = 0.0;
+  std::vector<JobSpec> sp{JobSpec{1, &x, &zero, nullptr, 0, 1.0}};
+  std::vector<Node> r = run_jobs(E, sp, D);
+  release(E.c, x);
+  return r[0];
+}
+
+// H|psi> (Algorithm 1 terms with prefix reuse + T terms, reduced by the tree)
+Node apply_H_nodes(Engine &E, const Node &psi, int D, int D_sum) {
+  thc_ctx *c = E.c;
+  const int N = c->N, L = c->L;
+  const thc_opts &o = E.o;
+  Reducer red(E, D_sum);
+  // leaves in order: V (nu, s', mu, s) then T (i, s)
+  // prefix states
+  std::vector<Node> prefix;
+  if (o.include_V) {
+    std::vector<JobSpec> s1;
+    for (int nu = 0; nu < N; ++nu)
+      for (int sp = 0; sp < 2; ++sp) s1.push_back(JobSpec{0, &psi, nullptr, c->coef_ptr(2 * nu + sp), 0, 1.0});
+    std::vector<Node> a1 = run_jobs(E, s1, D);
+    std::vector<JobSpec> s2;
+    for (size_t i = 0; i < a1.size(); ++i) {
+      int nu = (int)i / 2, sp = (int)i % 2;
+      s2.push_back(JobSpec{0, &a1[i], nullptr, c->coef_ptr(2 * nu + sp), 1, 1.0});
+    }
+    prefix = run_jobs(E, s2, D);
+    for (auto &nd : a1) release(c, nd);
+  }
+  struct Leaf {
+    const Node *src;
+    const double *y;
+    double scale;
+  };
+  std::vector<Leaf> leaves;
+  if (o.include_V) {
+    for (int nu = 0; nu < N; ++nu)
+      for (int sp = 0; sp < 2; ++sp)
+        for (int mu = 0; mu < N; ++mu)
+          for (int s = 0; s < 2; ++s) {
+            double z = 0.5 * c->zeta[(size_t)mu * N + nu];
+            if (z == 0.0) continue;
+            leaves.push_back(Leaf{&prefix[2 * nu + sp], c->coef_ptr(2 * mu + s), z});
+          }
+  }
+  if (o.include_T) {
+    for (int i = 0; i < L; ++i) {
+      if (c->lam[i] == 0.0) continue;
+      for (int s = 0; s < 2; ++s) leaves.push_back(Leaf{&psi, c->coef_ptr(2 * N + 2 * i + s), c->lam[i]});
+    }
+  }
+  if (leaves.empty()) raise(THC_EINVAL, "H has no terms (all coefficients zero or both parts disabled)");
+  // chunked leaf production
+  Plan probe = make_plan(0, leaves[0].src->prof, nullptr, D);
+  int B = E.batch_limit(probe);
+  for (size_t i0 = 0; i0 < leaves.size(); i0 += B) {
+    size_t i1 = std::min(leaves.size(), i0 + B);
+    std::vector<JobSpec> s1;
+    for (size_t i = i0; i < i1; ++i) s1.push_back(JobSpec{0, leaves[i].src, nullptr, leaves[i].y, 0, leaves[i].scale});
+    std::vector<Node> a1 = run_jobs(E, s1, D);
+    std::vector<JobSpec> s2;
+    for (size_t i = i0; i < i1; ++i) s2.push_back(JobSpec{0, &a1[i - i0], nullptr, leaves[i].y, 1, 1.0});
+    std::vector<Node> a2 = run_jobs(E, s2, D);
+    for (auto &nd : a1) release(c, nd);
+    for (auto &nd : a2) red.push(nd);
+    // batch the ready sums once half a batch is available (or the queues grow long)
+    red.flush(std::max<size_t>(1, std::min<size_t>(B / 2, red.queued() > (size_t)(4 * B) ? 1 : B / 2)));
+  }
+  Node root = red.finish();
+  for (auto &nd : prefix) release(c, nd);
+  return root;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+void thc_default_opts(thc_opts *o, int32_t D) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->D_max = D;
+  o->D_sum = 0;
+  o->rel_cutoff = 1e-14;
+  o->prec = THC_PREC_F64;
+  o->batch = 0;
+  o->max_sweeps = 40;
+  o->include_T = 1;
+  o->include_V = 1;
+  o->flags = 0;
+}
+
+int64_t thc_mps_capacity(int32_t n_sites, int32_t D) {
+  if (n_sites < 1 || D < 1) return 0;
+  Profile p = capacity_profile(n_sites, D);
+  return p.size;
+}
+
+const char *thc_last_error(void) { return g_err.c_str(); }
+
+thc_status thc_load_factors(thc_ctx **ctx, int32_t L, int32_t N, const double *t, const double *chi,
+                            const double *zeta, uint64_t flags, void *hip_stream) {
+  (void)flags;
+  if (!ctx) return fail(THC_EINVAL, "ctx is NULL");
+  *ctx = nullptr;
+  if (L < 1 || N < 0) return fail(THC_EINVAL, "need L >= 1 and N >= 0");
+  if (!t || (N > 0 && (!chi || !zeta))) return fail(THC_EINVAL, "NULL factor array");
+  for (int i = 0; i < L * L; ++i)
+    if (!std::isfinite(t[i])) return fail(THC_ENONFINITE, "t has a non-finite entry");
+  for (int i = 0; i < L * N; ++i)
+    if (!std::isfinite(chi[i])) return fail(THC_ENONFINITE, "chi has a non-finite entry");
+  for (int i = 0; i < N * N; ++i)
+    if (!std::isfinite(zeta[i])) return fail(THC_ENONFINITE, "zeta has a non-finite entry");
+  auto sym_ok = [](const double *a, int m) {
+    double mx = 0.0, asym = 0.0;
+    for (int i = 0; i < m * m; ++i) mx = std::max(mx, std::fabs(a[i]));
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) asym = std::max(asym, std::fabs(a[i * m + j] - a[j * m + i]));
+    return asym <= 1e-12 * std::max(mx, 1e-300);
+  };
+  if (!sym_ok(t, L)) return fail(THC_EINVAL, "t is not symmetric");
+  if (N > 0 && !sym_ok(zeta, N)) return fail(THC_EINVAL, "zeta is not symmetric");
+  auto c = std::make_unique<thc_ctx>();
+  c->L = L;
+  c->N = N;
+  c->n = 2 * L;
+  c->t.assign(t, t + L * L);
+  c->chi.assign(chi, chi + (size_t)L * N);
+  c->zeta.assign(zeta, zeta + (size_t)N * N);
+  // t = U diag(lam) U^T (App. D), FP64 cyclic Jacobi on the host; ascending lam
+  {
+    std::vector<double> A(c->t), V((size_t)L * L, 0.0);
+    for (int i = 0; i < L; ++i) V[(size_t)i * L + i] = 1.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+      double off = 0.0, tot = 0.0;
+      for (int i = 0; i < L; ++i)
+        for (int j = 0; j < L; ++j) {
+          tot += A[i * L + j] * A[i * L + j];
+          if (i != j) off += A[i * L + j] * A[i * L + j];
+        }
+      if (off <= 1e-32 * tot || off == 0.0) break;
+      for (int p = 0; p < L; ++p)
+        for (int q = p + 1; q < L; ++q) {
+          double apq = A[p * L + q];
+          if (apq == 0.0) continue;
+          double th = (A[q * L + q] - A[p * L + p]) / (2.0 * apq);
+          double tt = std::copysign(1.0, th) / (std::fabs(th) + std::sqrt(1.0 + th * th));
+          double cc = 1.0 / std::sqrt(1.0 + tt * tt), ss = tt * cc;
+          for (int k = 0; k < L; ++k) {
+            double ap = A[p * L + k], aq = A[q * L + k];
+            A[p * L + k] = cc * ap - ss * aq;
+            A[q * L + k] = ss * ap + cc * aq;
+          }
+          for (int k = 0; k < L; ++k) {
+            double ap = A[k * L + p], aq = A[k * L + q];
+            A[k * L + p] = cc * ap - ss * aq;
+            A[k * L + q] = ss * ap + cc * aq;
+          }
+          for (int k = 0; k < L; ++k) {
+            double vp = V[k * L + p], vq = V[k * L + q];
+            V[k * L + p] = cc * vp - ss * vq;
+            V[k * L + q] = ss * vp + cc * vq;
+          }
+        }
+    }
+    std::vector<int> idx(L);
+    for (int i = 0; i < L; ++i) idx[i] = i;
+    std::sort(idx.begin(), idx.end(), [&](int a, int b) { return A[a * L + a] < A[b * L + b]; });
+    c->lam.resize(L);
+    c->u.assign((size_t)L * L, 0.0);
+    for (int i = 0; i < L; ++i) {
+      c->lam[i] = A[idx[i] * L + idx[i]];
+      for (int p = 0; p < L; ++p) c->u[(size_t)p * L + i] = V[(size_t)p * L + idx[i]];
+    }
+  }
+  // coefficient rows: y_j = x_p at j = 2p + s
+  const int n = 2 * L;
+  std::vector<double> rows((size_t)(2 * N + 2 * L) * n, 0.0);
+  for (int mu = 0; mu < N; ++mu)
+    for (int s = 0; s < 2; ++s)
+      for (int p = 0; p < L; ++p) rows[(size_t)(2 * mu + s) * n + 2 * p + s] = chi[(size_t)p * N + mu];
+  for (int i = 0; i < L; ++i)
+    for (int s = 0; s < 2; ++s)
+      for (int p = 0; p < L; ++p) rows[(size_t)(2 * N + 2 * i + s) * n + 2 * p + s] = c->u[(size_t)p * L + i];
+  thc_ctx *raw = c.get();
+  thc_status stt = run_guarded([&] {
+    raw->coef.ensure(rows.size() * sizeof(double));
+    HIPCHK(hipMemcpyAsync(raw->coef.p, rows.data(), rows.size() * sizeof(double), hipMemcpyHostToDevice,
+                          (hipStream_t)hip_stream));
+    HIPCHK(hipStreamSynchronize((hipStream_t)hip_stream));
+  });
+  if (stt != THC_OK) return stt;
+  *ctx = c.release();
+  return THC_OK;
+}
+
+thc_status thc_destroy(thc_ctx *ctx) {
+  if (!ctx) return THC_OK;
+  (void)hipDeviceSynchronize();
+  delete ctx;
+  return THC_OK;
+}
+
+thc_status mps_apply_thc_H(thc_ctx *ctx, const thc_mps *psi, thc_mps *out, const thc_opts *o, thc_stats *st,
+                           void *hip_stream) {
+  if (!ctx) return fail(THC_EINVAL, "ctx is NULL");
+  return run_guarded([&] {
+    int D;
+    thc_opts oo = norm_opts(o, &D);
+    check_mps(psi, ctx->n);
+    if (!out || !out->bonds || !out->offsets || !out->data) raise(THC_EINVAL, "bad output MPS");
+    if (out->n_sites != ctx->n) raise(THC_EINVAL, "output n_sites must equal 2L");
+    if (out->data == psi->data) raise(THC_EINVAL, "psi and out alias");
+    if (out->capacity < thc_mps_capacity(ctx->n, D)) raise(THC_ECAPACITY, "output capacity below thc_mps_capacity");
+    hipStream_t s = (hipStream_t)hip_stream;
+    Engine E(ctx, s, oo);
+    ctx->jobs_host_used = 0;
+    Node in = caller_node(psi);
+    Node root = apply_H_nodes(E, in, D, oo.D_sum);
+    if (oo.D_sum != D) root = compress_node(E, root, D);
+    emit(E, root, out);
+    HIPCHK(hipStreamSynchronize(s));
+    release(ctx, root);
+    fill_stats(st, E.cs);
+  });
+}
+
+thc_status mps_sum_compress(thc_ctx *ctx, int32_t k, const double *coeffs, const thc_mps *const *terms,
+                            thc_mps *out, const thc_opts *o, thc_stats *st, void *hip_stream) {
+  if (!ctx) return fail(THC_EINVAL, "ctx is NULL");
+  return run_guarded([&] {
+    int D;
+    thc_opts oo = norm_opts(o, &D);
+    if (k < 1 || !coeffs || !terms) raise(THC_EINVAL, "need k >= 1 terms");
+    const int n = terms[0] ? terms[0]->n_sites : 0;
+    for (int i = 0; i < k; ++i) {
+      check_mps(terms[i], n);
+      if (!std::isfinite(coeffs[i])) raise(THC_ENONFINITE, "non-finite coefficient");
+    }
+    if (!out || out->n_sites != n) raise(THC_EINVAL, "bad output MPS");
+    if (out->capacity < thc_mps_capacity(n, D)) raise(THC_ECAPACITY, "output capacity below thc_mps_capacity");
+    for (int i = 0; i < k; ++i)
+      if (terms[i]->data == out->data) raise(THC_EINVAL, "output aliases an input");
+    hipStream_t s = (hipStream_t)hip_stream;
+    Engine E(ctx, s, oo);
+    ctx->jobs_host_used = 0;
+    if (ctx->n != n) raise(THC_EINVAL, "n_sites differs from the context's 2L");
+    std::vector<Node> leaves(k);
+    for (int i = 0; i < k; ++i) {
+      leaves[i] = caller_node(terms[i]);
+      leaves[i].coef = coeffs[i];
+    }
+    Node root;
+    if (k == 1) {
+      root = compress_node(E, leaves[0], D);
+    } else {
+      Reducer red(E, oo.D_sum);
+      for (int i = 0; i < k; ++i) red.push(leaves[i]);
+      root = red.finish();
+      if (oo.D_sum != D) root = compress_node(E, root, D);
+    }
+    emit(E, root, out);
+    HIPCHK(hipStreamSynchronize(s));
+    release(ctx, root);
+    fill_stats(st, E.cs);
+  });
+}
+
+thc_status mps_compress(thc_ctx *ctx, const thc_mps *in, thc_mps *out, const thc_opts *o, thc_stats *st,
+                        void *hip_stream) {
+  double one = 1.0;
+  const thc_mps *t[1] = {in};
+  return mps_sum_compress(ctx, 1, &one, t, out, o, st, hip_stream);
+}
+
+thc_status mps_apply_layer(thc_ctx *ctx, const thc_mps *psi, const double *y, int32_t dag, thc_mps *out,
+                           const thc_opts *o, thc_stats *st, void *hip_stream) {
+  if (!ctx) return fail(THC_EINVAL, "ctx is NULL");
+  return run_guarded([&] {
+    int D;
+    thc_opts oo = norm_opts(o, &D);
+    check_mps(psi, 0);
+    const int n = psi->n_sites;
+    if (!y) raise(THC_EINVAL, "y is NULL");
+    for (int j = 0; j < n; ++j)
+      if (!std::isfinite(y[j])) raise(THC_ENONFINITE, "non-finite coefficient");
+    if (!out || out->n_sites != n) raise(THC_EINVAL, "bad output MPS");
+    if (out->capacity < thc_mps_capacity(n, D)) raise(THC_ECAPACITY, "output capacity below thc_mps_capacity");
+    hipStream_t s = (hipStream_t)hip_stream;
+    Engine E(ctx, s, oo);
+    ctx->jobs_host_used = 0;
+    DevBuf yd;
+    yd.ensure(n * sizeof(double));
+    HIPCHK(hipMemcpyAsync(yd.p, y, n * sizeof(double), hipMemcpyHostToDevice, s));
+    Node in = caller_node(psi);
+    std::vector<JobSpec> sp{JobSpec{0, &in, nullptr, yd.as<double>(), dag ? 1 : 0, 1.0}};
+    std::vector<Node> r = run_jobs(E, sp, D);
+    emit(E, r[0], out);
+    HIPCHK(hipStreamSynchronize(s));
+    release(ctx, r[0]);
+    fill_stats(st, E.cs);
+  });
+}
+
+thc_status mps_overlap(thc_ctx *ctx, const thc_mps *a, const thc_mps *b, double *result, void *hip_stream) {
+  if (!ctx) return fail(THC_EINVAL, "ctx is NULL");
+  return run_guarded([&] {
+    check_mps(a, 0);
+    check_mps(b, a->n_sites);
+    if (!result) raise(THC_EINVAL, "result is NULL");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int n = a->n_sites;
+    int maxb = 1;
+    for (int j = 0; j <= n; ++j) maxb = std::max(maxb, std::max(a->bonds[j], b->bonds[j]));
+    int64_t s_scr = 3 * (int64_t)maxb * maxb;
+    DevBuf scr, meta, res;
+    scr.ensure((size_t)s_scr * sizeof(double));
+    size_t mbytes = sizeof(OJob) + 2 * (n + 1) * sizeof(int) + 2 * n * sizeof(int64_t) + 64;
+    meta.ensure(mbytes);
+    std::vector<char> h(mbytes);
+    OJob oj{a->data, b->data};
+    size_t p = 0;
+    memcpy(h.data() + p, &oj, sizeof(OJob));
+    size_t pba = (p + sizeof(OJob) + 7) / 8 * 8;
+    memcpy(h.data() + pba, a->bonds, (n + 1) * sizeof(int));
+    size_t pbb = pba + (n + 1) * sizeof(int);
+    memcpy(h.data() + pbb, b->bonds, (n + 1) * sizeof(int));
+    size_t poa = (pbb + (n + 1) * sizeof(int) + 7) / 8 * 8;
+    memcpy(h.data() + poa, a->offsets, n * sizeof(int64_t));
+    size_t pob = poa + n * sizeof(int64_t);
+    memcpy(h.data() + pob, b->offsets, n * sizeof(int64_t));
+    HIPCHK(hipMemcpyAsync(meta.p, h.data(), mbytes, hipMemcpyHostToDevice, s));
+    res.ensure(sizeof(double));
+    char *mp = (char *)meta.p;
+    launch_overlap(s, 1, (const OJob *)mp, n, (const int *)(mp + pba), (const int64_t *)(mp + poa),
+                   (const int *)(mp + pbb), (const int64_t *)(mp + pob), scr.as<double>(), s_scr, res.as<double>());
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(result, res.p, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+  });
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Lanczos (Sec. 2.2)
+// ===========================================================================
+struct thc_krylov {
+  thc_ctx *ctx = nullptr;
+  thc_opts o{};
+  int K = 0, i = 0, n = 0, D = 0;
+  int64_t cap = 0;
+  std::vector<std::unique_ptr<DevBuf>> vbuf, wbuf;
+  std::vector<std::vector<int>> vb, wb;          // bonds
+  std::vector<std::vector<int64_t>> vo, wo;      // offsets
+  std::vector<double> Mm, S, alpha, beta;        // host mirrors, (K+1)^2
+  DevBuf dM, dS, dA, dB, dOutG, dOutT, dInfo;
+};
+
+namespace {
+thc_mps view(thc_krylov *k, bool isw, int i) {
+  thc_mps m{};
+  m.n_sites = k->n;
+  m.d = 2;
+  auto &b = isw ? k->wb[i] : k->vb[i];
+  auto &o = isw ? k->wo[i] : k->vo[i];
+  m.bonds = b.data();
+  m.offsets = o.data();
+  m.data = (isw ? k->wbuf[i] : k->vbuf[i])->as<double>();
+  m.capacity = k->cap;
+  return m;
+}
+}  // namespace
+
+extern "C" {
+
+thc_status krylov_create(thc_ctx *ctx, const thc_mps *psi0, int32_t K, const thc_opts *o, thc_krylov **state,
+                         void *hip_stream) {
+  if (!ctx || !state) return fail(THC_EINVAL, "NULL argument");
+  *state = nullptr;
+  if (K < 1 || K + 1 > RITZ_MAX) return fail(THC_EINVAL, "K must be in [1, 31]");
+  auto k = std::make_unique<thc_krylov>();
+  thc_status s = run_guarded([&] {
+    int D;
+    k->o = norm_opts(o, &D);
+    check_mps(psi0, ctx->n);
+    k->ctx = ctx;
+    k->K = K;
+    k->n = ctx->n;
+    k->D = D;
+    k->cap = std::max<int64_t>(thc_mps_capacity(ctx->n, D), 0);
+    int64_t in_size = 0;
+    for (int j = 0; j < psi0->n_sites; ++j)
+      in_size = std::max(in_size, psi0->offsets[j] + (int64_t)psi0->bonds[j] * 2 * psi0->bonds[j + 1]);
+    k->cap = std::max(k->cap, in_size);
+    for (int i = 0; i <= K; ++i) {
+      k->vbuf.push_back(std::make_unique<DevBuf>());
+      k->vbuf.back()->ensure((size_t)k->cap * sizeof(double));
+      k->vb.push_back(std::vector<int>(k->n + 1, 1));
+      k->vo.push_back(std::vector<int64_t>(k->n, 0));
+    }
+    for (int i = 0; i < K; ++i) {
+      k->wbuf.push_back(std::make_unique<DevBuf>());
+      k->wbuf.back()->ensure((size_t)k->cap * sizeof(double));
+      k->wb.push_back(std::vector<int>(k->n + 1, 1));
+      k->wo.push_back(std::vector<int64_t>(k->n, 0));
+    }
+    hipStream_t st = (hipStream_t)hip_stream;
+    // v_0 = psi0 / ||psi0|| (copied as given, then scaled on the last site)
+    k->vb[0].assign(psi0->bonds, psi0->bonds + k->n + 1);
+    k->vo[0].assign(psi0->offsets, psi0->offsets + k->n);
+    HIPCHK(hipMemcpyAsync(k->vbuf[0]->p, psi0->data, (size_t)in_size * sizeof(double), hipMemcpyDeviceToDevice, st));
+    thc_mps v0 = view(k.get(), false, 0);
+    double nn = 0.0;
+    thc_status r = mps_overlap(ctx, &v0, &v0, &nn, hip_stream);
+    if (r != THC_OK) raise(r, thc_last_error());
+    if (!(nn > 0.0) || !std::isfinite(nn)) raise(THC_EINVAL, "start vector has zero or non-finite norm");
+    const int nl = k->n - 1;
+    launch_scale(st, k->vbuf[0]->as<double>() + k->vo[0][nl], (int64_t)k->vb[0][nl] * 2 * k->vb[0][nl + 1],
+                 1.0 / std::sqrt(nn));
+    int R = K + 1;
+    k->Mm.assign(R * R, 0.0);
+    k->S.assign(R * R, 0.0);
+    thc_mps v0b = view(k.get(), false, 0);
+    double s00 = 0.0;
+    r = mps_overlap(ctx, &v0b, &v0b, &s00, hip_stream);
+    if (r != THC_OK) raise(r, thc_last_error());
+    k->S[0] = s00;
+    k->dM.ensure(R * R * sizeof(double));
+    k->dS.ensure(R * R * sizeof(double));
+    k->dA.ensure(R * sizeof(double));
+    k->dB.ensure(R * sizeof(double));
+    k->dOutG.ensure(R * sizeof(double));
+    k->dOutT.ensure(R * sizeof(double));
+    k->dInfo.ensure(4 * sizeof(int));
+  });
+  if (s != THC_OK) return s;
+  *state = k.release();
+  return THC_OK;
+}
+
+thc_status krylov_destroy(thc_krylov *state) {
+  if (!state) return THC_OK;
+  (void)hipDeviceSynchronize();
+  delete state;
+  return THC_OK;
+}
+
+thc_status krylov_step(thc_krylov *k, double *ritz_gen, double *ritz_tri, double *beta, thc_stats *st,
+                       void *hip_stream) {
+  if (!k) return fail(THC_EINVAL, "state is NULL");
+  if (k->i >= k->K) return fail(THC_EINVAL, "all K Krylov steps have been taken");
+  return run_guarded([&] {
+    thc_ctx *ctx = k->ctx;
+    const int i = k->i, R = k->K + 1;
+    thc_stats s1{}, s2{};
+    // w_i = H v_i
+    thc_mps vi = view(k, false, i);
+    thc_mps wi = view(k, true, i);
+    thc_status r = mps_apply_thc_H(ctx, &vi, &wi, &k->o, &s1, hip_stream);
+    if (r != THC_OK) raise(r, thc_last_error());
+    // h_ji = <v_j|w_i>
+    for (int j = 0; j <= i; ++j) {
+      thc_mps vj = view(k, false, j);
+      double h = 0.0;
+      r = mps_overlap(ctx, &vj, &wi, &h, hip_stream);
+      if (r != THC_OK) raise(r, thc_last_error());
+      k->Mm[j * R + i] = h;
+    }
+    k->alpha.push_back(k->Mm[i * R + i]);
+    // r = compress(w_i - sum_j h_ji v_j)
+    std::vector<double> co{1.0};
+    std::vector<thc_mps> views{wi};
+    for (int j = 0; j <= i; ++j) {
+      co.push_back(-k->Mm[j * R + i]);
+      views.push_back(view(k, false, j));
+    }
+    std::vector<const thc_mps *> ptrs;
+    for (auto &v : views) ptrs.push_back(&v);
+    thc_mps vn = view(k, false, i + 1);
+    r = mps_sum_compress(ctx, (int)co.size(), co.data(), ptrs.data(), &vn, &k->o, &s2, hip_stream);
+    if (r != THC_OK) raise(r, thc_last_error());
+    double rr = 0.0;
+    r = mps_overlap(ctx, &vn, &vn, &rr, hip_stream);
+    if (r != THC_OK) raise(r, thc_last_error());
+    double b = std::sqrt(std::max(rr, 0.0));
+    k->beta.push_back(b);
+    hipStream_t st_ = (hipStream_t)hip_stream;
+    if (b > 0.0) {
+      const int nl = k->n - 1;
+      launch_scale(st_, k->vbuf[i + 1]->as<double>() + k->vo[i + 1][nl],
+                   (int64_t)k->vb[i + 1][nl] * 2 * k->vb[i + 1][nl + 1], 1.0 / b);
+      HIPCHK(hipGetLastError());
+      for (int j = 0; j <= i + 1; ++j) {
+        thc_mps a = view(k, false, i + 1), bj = view(k, false, j);
+        double sv = 0.0;
+        r = mps_overlap(ctx, &a, &bj, &sv, hip_stream);
+        if (r != THC_OK) raise(r, thc_last_error());
+        k->S[(i + 1) * R + j] = k->S[j * R + (i + 1)] = sv;
+      }
+      for (int l = 0; l <= i; ++l) {
+        thc_mps a = view(k, false, i + 1), wl = view(k, true, l);
+        double mv = 0.0;
+        r = mps_overlap(ctx, &a, &wl, &mv, hip_stream);
+        if (r != THC_OK) raise(r, thc_last_error());
+        k->Mm[(i + 1) * R + l] = mv;
+      }
+    }
+    // Ritz values on the device (FP64)
+    const int m = i + 1;
+    HIPCHK(hipMemcpyAsync(k->dM.p, k->Mm.data(), R * R * sizeof(double), hipMemcpyHostToDevice, st_));
+    HIPCHK(hipMemcpyAsync(k->dS.p, k->S.data(), R * R * sizeof(double), hipMemcpyHostToDevice, st_));
+    HIPCHK(hipMemcpyAsync(k->dA.p, k->alpha.data(), m * sizeof(double), hipMemcpyHostToDevice, st_));
+    if (m > 1)
+      HIPCHK(hipMemcpyAsync(k->dB.p, k->beta.data(), (m - 1) * sizeof(double), hipMemcpyHostToDevice, st_));
+    launch_ritz(st_, k->dM.as<double>(), k->dS.as<double>(), m, R, k->dA.as<double>(), k->dB.as<double>(),
+                k->dOutG.as<double>(), k->dOutT.as<double>(), k->dInfo.as<int>());
+    HIPCHK(hipGetLastError());
+    std::vector<double> g(m), t(m);
+    HIPCHK(hipMemcpyAsync(g.data(), k->dOutG.p, m * sizeof(double), hipMemcpyDeviceToHost, st_));
+    HIPCHK(hipMemcpyAsync(t.data(), k->dOutT.p, m * sizeof(double), hipMemcpyDeviceToHost, st_));
+    HIPCHK(hipStreamSynchronize(st_));
+    if (ritz_gen) memcpy(ritz_gen, g.data(), m * sizeof(double));
+    if (ritz_tri) memcpy(ritz_tri, t.data(), m * sizeof(double));
+    if (beta) *beta = b;
+    k->i = i + 1;
+    if (st) {
+      st->discarded_weight_max = std::max(s1.discarded_weight_max, s2.discarded_weight_max);
+      st->flops_model = s1.flops_model + s2.flops_model;
+      st->n_compressions = s1.n_compressions + s2.n_compressions;
+      st->n_launches = s1.n_launches + s2.n_launches;
+      st->max_bond = std::max(s1.max_bond, s2.max_bond);
+      st->jacobi_sweeps_max = std::max(s1.jacobi_sweeps_max, s2.jacobi_sweeps_max);
+      st->nonconverged = s1.nonconverged + s2.nonconverged;
+    }
+  });
+}
+
+thc_status krylov_get_vector(thc_krylov *k, int32_t i, thc_mps *out, void *hip_stream) {
+  if (!k || !out) return fail(THC_EINVAL, "NULL argument");
+  if (i < 0 || i > k->i) return fail(THC_EINVAL, "vector index out of range");
+  return run_guarded([&] {
+    int64_t need = 0;
+    for (int j = 0; j < k->n; ++j) need = std::max(need, k->vo[i][j] + (int64_t)k->vb[i][j] * 2 * k->vb[i][j + 1]);
+    if (out->capacity < need || out->n_sites != k->n) raise(THC_ECAPACITY, "output too small");
+    HIPCHK(hipMemcpyAsync(out->data, k->vbuf[i]->p, need * sizeof(double), hipMemcpyDeviceToDevice,
+                          (hipStream_t)hip_stream));
+    for (int j = 0; j <= k->n; ++j) out->bonds[j] = k->vb[i][j];
+    for (int j = 0; j < k->n; ++j) out->offsets[j] = k->vo[i][j];
+    HIPCHK(hipStreamSynchronize((hipStream_t)hip_stream));
+  });
+}
+
+thc_status krylov_get_matrices(thc_krylov *k, double *Mm, double *S, int32_t *m) {
+  if (!k) return fail(THC_EINVAL, "NULL state");
+  const int R = k->K + 1, mm = k->i;
+  if (m) *m = mm;
+  for (int a = 0; a < mm; ++a)
+    for (int b = 0; b < mm; ++b) {
+      if (Mm) Mm[a * mm + b] = k->Mm[a * R + b];
+      if (S) S[a * mm + b] = k->S[a * R + b];
+    }
+  return THC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,59 @@
+// Internal interface between the engine (host scheduling) and the HIP
+// kernels.  Not part of the public C ABI (include/thck.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace thck {
+
+// One compression job: construct a bond-2D MPS from one or two inputs, then
+// compress it.  kind 0 = layer  sum_j y_j a_j (dag 0) or a+_j (dag 1) applied
+// to in_a, the last site scaled by ca; kind 1 = direct sum ca*in_a + cb*in_b.
+struct CJob {
+  const double *in_a;
+  const double *in_b;
+  const double *y;
+  double ca, cb;
+  double *out;
+  int kind;
+  int dag;
+};
+
+struct OJob {
+  const double *a;
+  const double *b;
+};
+
+constexpr int RITZ_MAX = 32;
+
+int lq_t_stride(int k);
+
+void launch_construct(hipStream_t st, const CJob *jobs, int nb, int site, int n_sites, int64_t in_off_a,
+                      int64_t in_off_b, int la, int ra, int lb, int rb, double *out, int64_t out_stride, int lo,
+                      int ro);
+void launch_gemm(hipStream_t st, int nb, bool transB, const double *A, int64_t sA, int lda, const double *B,
+                 int64_t sB, int ldb, double *C, int64_t sC, int ldc, int M, int N, int K);
+int launch_lq(hipStream_t st, int nb, double *X, int64_t sX, int m, int n, double *L, int64_t sL, double *Q,
+              int64_t sQ, double *Tw, int64_t sT);
+int launch_jacobi(hipStream_t st, int nb, double *Y, int64_t sY, int m, int n, double *s, int64_t ss, int *sweeps,
+                  int max_sweeps);
+void launch_svd_select(hipStream_t st, int nb, const double *Y, int64_t sY, int m, int n, const double *s,
+                       int64_t ss, int kk, double cutoff, double *W, int64_t sW, int *rank, double *disc,
+                       double *sv_out, int64_t ssv);
+void launch_svd_finish(hipStream_t st, int nb, const double *Q, int64_t sQ, int m, int kk, const int *rank,
+                       double *U, int64_t sU, double *C, int64_t sC, int n);
+void launch_copy(hipStream_t st, int nb, const double *src, int64_t ssrc, double *dst, int64_t sdst, int64_t count);
+void launch_gather(hipStream_t st, int nb, const CJob *jobs, int which, int64_t off, double *dst, int64_t sdst,
+                   int64_t count);
+void launch_scatter(hipStream_t st, int nb, const CJob *jobs, int64_t off, const double *src, int64_t ssrc,
+                    int64_t count);
+void launch_overlap(hipStream_t st, int nb, const OJob *jobs, int n_sites, const int *bonds_a, const int64_t *off_a,
+                    const int *bonds_b, const int64_t *off_b, double *scratch, int64_t s_scr, double *out);
+void launch_scale(hipStream_t st, double *p, int64_t count, double c);
+void launch_repack(hipStream_t st, int gx, const double *src, int64_t soff, int ks_l, int ks_r, double *dst,
+                   int64_t doff, int rl, int rr);
+void launch_ritz(hipStream_t st, const double *Mm, const double *S, int m, int ld, const double *alpha,
+                 const double *beta, double *out_gen, double *out_tri, int *info);
+
+}  // namespace thck

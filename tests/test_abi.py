@@ -1,0 +1,69 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and rejects bad factor tables before touching the GPU."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_symbols():
+    src = open(os.path.join(ROOT, "include", "thck.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_\s\*]*?\b([a-z_][A-Za-z0-9_]*)\s*\(", src, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "while")))
+
+
+def test_header_symbols_exported():
+    from paper_2409_12708_amd import thck
+    lib = thck.load_library()
+    syms = _header_symbols()
+    assert len(syms) >= 15, syms
+    missing = [s for s in syms if not hasattr(lib, s)]
+    assert not missing, missing
+    assert sorted(syms) == sorted(thck.EXPORTS)
+
+
+def test_capacity_matches_profile():
+    from paper_2409_12708_amd import thck
+    import synth
+    for n, D in [(8, 16), (24, 128), (40, 256), (16, 256)]:
+        b = synth.bond_profile(n, D)
+        assert thck.capacity(n, D) == sum(b[j] * 2 * b[j + 1] for j in range(n))
+
+
+def _load(t, chi, zeta):
+    from paper_2409_12708_amd import thck
+    lib = thck.load_library()
+    h = C.c_void_p()
+    st = lib.thc_load_factors(C.byref(h), chi.shape[0], chi.shape[1], thck._dptr(t), thck._dptr(chi),
+                              thck._dptr(zeta), 0, None)
+    return st, lib.thc_last_error().decode()
+
+
+def test_load_factors_rejects_bad_input():
+    rng = np.random.default_rng(0)
+    L, N = 3, 4
+    t = rng.standard_normal((L, L)); t = t + t.T
+    chi = rng.standard_normal((L, N))
+    z = rng.standard_normal((N, N)); z = z + z.T
+    bad = z.copy(); bad[0, 1] += 1.0
+    st, msg = _load(t, chi, bad)
+    assert st == -1 and "zeta" in msg
+    st, msg = _load(t + np.triu(np.ones((L, L)), 1), chi, z)
+    assert st == -1 and "t " in msg + " "
+    chi2 = chi.copy(); chi2[1, 2] = np.nan
+    st, msg = _load(t, chi2, z)
+    assert st == -4
+    t2 = t.copy(); t2[0, 0] = np.inf
+    st, msg = _load(t2, chi, z)
+    assert st == -4
+
+
+def test_default_opts():
+    from paper_2409_12708_amd import thck
+    o = thck.make_opts(64)
+    assert o.D_max == 64 and o.rel_cutoff == 1e-14 and o.include_T == 1 and o.include_V == 1 and o.prec == 0
