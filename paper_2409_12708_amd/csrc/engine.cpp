@@ -210,7 +210,8 @@ struct Plan {
   Profile out;
   // per-job workspace layout (elements)
   int64_t oB = 0, oT = 0, oL = 0, oQs = 0, oM = 0, oY = 0, oW = 0, oZ = 0, oC = 0, oLz = 0, oQz = 0, oTf = 0,
-          oS = 0, oU = 0;
+          oS = 0, oU = 0, oG = 0, oDet = 0, oZm = 0, oLam = 0, oScr = 0;
+  int64_t sv = 0;  // stride of the d / e / tau vectors inside oDet
   std::vector<int64_t> qs_off;  // offset of Q_j inside Qs
   int64_t per_job = 0;
   double flops_per_job = 0.0;
@@ -240,7 +241,8 @@ Plan make_plan(int kind, const Profile &pa, const Profile *pb, int D) {
   for (int j = 0; j + 1 < n; ++j) P.k[j + 1] = std::min(std::min(2 * P.k[j], P.c[j + 1]), D);
   P.out.b = P.k;
   P.out.pack();
-  int64_t mB = 0, mT = 0, mL = 0, mM = 0, mW = 0, mZ = 0, mQz = 0, mLz = 0, mS = 0, mTf = 0, mU = 0;
+  int64_t mB = 0, mT = 0, mL = 0, mM = 0, mW = 0, mZ = 0, mQz = 0, mLz = 0, mS = 0, mTf = 0, mU = 0, mG = 0,
+          mZm = 0, mScr = 0;
   P.qs_off.assign(n, 0);
   int64_t qs = 0;
   double fl = 0.0;
@@ -264,6 +266,9 @@ Plan make_plan(int kind, const Profile &pa, const Profile *pb, int D) {
       mS = std::max(mS, (int64_t)m);
       mU = std::max(mU, (int64_t)m * kk);
       mTf = std::max(mTf, (int64_t)lq_t_stride(std::max(kk, 1)));
+      mG = std::max(mG, (int64_t)m * m);
+      mZm = std::max(mZm, (int64_t)m * kk);
+      mScr = std::max(mScr, tri_eig_scratch(m, kk));
       fl += svd_flops(m, nc);
       fl += 2.0 * kk * nc * 2.0 * P.c[j + 2];  // absorb S V^T into site j+1
     }
@@ -290,6 +295,12 @@ Plan make_plan(int kind, const Profile &pa, const Profile *pb, int D) {
   P.oTf = take(mTf);
   P.oS = take(std::max<int64_t>(mS, 1));
   P.oU = take(std::max<int64_t>(mU, 1));
+  P.oG = take(std::max<int64_t>(mG, 1));
+  P.sv = (std::max<int64_t>(mS, 1) + 31) / 32 * 32;
+  P.oDet = take(3 * P.sv);
+  P.oZm = take(std::max<int64_t>(mZm, 1));
+  P.oLam = take(std::max<int64_t>(mS, 1));
+  P.oScr = take(std::max<int64_t>(mScr, 1));
   P.per_job = o;
   P.flops_per_job = fl;
   return P;
@@ -350,6 +361,7 @@ struct Engine {
     const int nb = (int)hjobs.size();
     if (nb == 0) return;
     const int n = P.n;
+    static const char *trace_path = getenv("THCK_TRACE");
     c->ws.ensure((size_t)P.per_job * nb * sizeof(double));
     rk.ensure((size_t)nb * n * sizeof(int));
     dw.ensure((size_t)nb * n * sizeof(double));
@@ -379,7 +391,6 @@ struct Engine {
       }
       if (launch_lq(st, nb, X, S, P.bo[j], 2 * P.c[j + 1], Lb, S, Qs + P.qs_off[j], S, Tf, S) != 0)
         raise(THC_EINVAL, "site matrix too wide for the LQ kernel (2*bond > 1024)");
-      ++launches;
     }
     // site 0: M_0 = B_0 * L_1 (1, 2, c_1)
     {
@@ -397,7 +408,31 @@ struct Engine {
     double *dw_d = dw.as<double>();
     int *sw_d = sw.as<int>();
     // ---- left -> right SVD sweep ----
-    for (int j = 0; j + 1 < n; ++j) {
+    double *Gb = W + P.oG, *Db = W + P.oDet, *Eb = Db + P.sv, *Taub = Db + 2 * P.sv, *Zm = W + P.oZm,
+           *Lam = W + P.oLam, *Scr = W + P.oScr;
+    const bool jacobi = (o.flags & THC_FLAG_SVD_JACOBI) != 0;
+    for (int j = 0; j + 1 < n && !jacobi; ++j) {
+      const int m = 2 * P.k[j], nc = P.c[j + 1], kk = P.k[j + 1];
+      // Gram G = Y Y^T, Y = M_j (m x nc)
+      launch_gemm(st, nb, true, Mb, S, nc, Mb, S, nc, Gb, S, m, m, m, nc);
+      if (launch_sytrd(st, nb, Gb, S, m, Db, Eb, Taub, S) != 0) raise(THC_EINVAL, "site matrix too tall for sytrd");
+      if (launch_tri_eig(st, nb, Db, Eb, S, m, kk, Zm, S, Lam, S, Scr, S) != 0)
+        raise(THC_EINVAL, "site matrix too tall for the tridiagonal eigensolver");
+      if (launch_ormtr(st, nb, Gb, S, m, Taub, S, Zm, S, kk, Zb, S) != 0) raise(THC_EINVAL, "ormtr size");
+      // orthonormal rows spanning the top-kk eigenvectors
+      if (launch_lq(st, nb, Zb, S, kk, m, Lz, S, Qz, S, Tf, S) != 0)
+        raise(THC_EINVAL, "site matrix too wide for the LQ kernel");
+      // C = Qz (kk x m) * M (m x nc)
+      launch_gemm(st, nb, false, Qz, S, m, Mb, S, nc, Cb, S, nc, kk, nc, m);
+      launch_svd_finish2(st, nb, Qz, S, m, kk, Cb, S, nc, cutoff(), Db, S, Ub, S, rk_d + (size_t)j * nb,
+                         dw_d + (size_t)j * nb);
+      launch_scatter(st, nb, dj, P.out.off[j], Ub, S, (int64_t)m * kk);
+      launch_gemm(st, nb, false, Cb, S, nc, Qs + P.qs_off[j + 1], S, 2 * P.c[j + 2], Mb, S, 2 * P.c[j + 2], kk,
+                  2 * P.c[j + 2], nc);
+      launches += 10;
+    }
+    if (!jacobi) HIPCHK(hipMemsetAsync(sw_d, 0, (size_t)nb * n * sizeof(int), st));
+    for (int j = 0; j + 1 < n && jacobi; ++j) {
       const int m = 2 * P.k[j], nc = P.c[j + 1], kk = P.k[j + 1];
       launch_copy(st, nb, Mb, S, Yb, S, (int64_t)m * nc);
       if (launch_jacobi(st, nb, Yb, S, m, nc, Sb, S, sw_d + (size_t)j * nb, max_sweeps()) != 0)
@@ -435,14 +470,53 @@ struct Engine {
       cs.sweeps_max = std::max(cs.sweeps_max, h_sw[i]);
       if (h_sw[i] > max_sweeps()) cs.nonconv++;
     }
+    if (trace_path) trace_batch(trace_path, P, hjobs);
     last_ranks.assign(h_rank.begin(), h_rank.begin() + (size_t)nb * (n - 1));
     last_nb = nb;
+    ++batch_counter;
     cs.compressions += nb;
     cs.launches += launches;
     cs.flops += P.flops_per_job * nb;
   }
+  // debugging aid: append every job of the batch (inputs, metadata, output) to a file
+  void trace_batch(const char *path, const Plan &P, const std::vector<CJob> &hj) {
+    FILE *f = fopen(path, "ab");
+    if (!f) return;
+    const int n = P.n;
+    auto dump = [&](const double *dev, const Profile &pr) {
+      std::vector<double> h(std::max<int64_t>(pr.size, 1));
+      HIPCHK(hipMemcpy(h.data(), dev, pr.size * sizeof(double), hipMemcpyDeviceToHost));
+      fwrite(pr.b.data(), sizeof(int), n + 1, f);
+      fwrite(pr.off.data(), sizeof(int64_t), n, f);
+      int64_t sz = pr.size;
+      fwrite(&sz, sizeof(int64_t), 1, f);
+      fwrite(h.data(), sizeof(double), pr.size, f);
+    };
+    for (const CJob &j : hj) {
+      int hdr[3] = {j.kind, j.dag, n};
+      fwrite(hdr, sizeof(int), 3, f);
+      double co[2] = {j.ca, j.cb};
+      fwrite(co, sizeof(double), 2, f);
+      std::vector<double> y(n, 0.0);
+      if (j.kind == 0) HIPCHK(hipMemcpy(y.data(), j.y, n * sizeof(double), hipMemcpyDeviceToHost));
+      fwrite(y.data(), sizeof(double), n, f);
+      Profile pa = P.pa;
+      pa.size = 0;
+      for (int q = 0; q < n; ++q) pa.size = std::max(pa.size, pa.off[q] + (int64_t)pa.b[q] * 2 * pa.b[q + 1]);
+      dump(j.in_a, pa);
+      if (j.kind == 1) {
+        Profile pb = P.pb;
+        pb.size = 0;
+        for (int q = 0; q < n; ++q) pb.size = std::max(pb.size, pb.off[q] + (int64_t)pb.b[q] * 2 * pb.b[q + 1]);
+        dump(j.in_b, pb);
+      }
+      dump(j.out, P.out);
+    }
+    fclose(f);
+  }
   std::vector<int> last_ranks;  // [site j][job] rank at bond j+1
   int last_nb = 0;
+  int batch_counter = 0;
 
   int batch_limit(const Plan &P) {
     if (o.batch > 0) return o.batch;

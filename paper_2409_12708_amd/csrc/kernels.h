@@ -53,6 +53,15 @@ void launch_overlap(hipStream_t st, int nb, const OJob *jobs, int n_sites, const
 void launch_scale(hipStream_t st, double *p, int64_t count, double c);
 void launch_repack(hipStream_t st, int gx, const double *src, int64_t soff, int ks_l, int ks_r, double *dst,
                    int64_t doff, int rl, int rr);
+int launch_sytrd(hipStream_t st, int nb, double *A, int64_t sA, int m, double *d, double *e, double *tau, int64_t sv);
+int launch_tri_eig(hipStream_t st, int nb, const double *d, const double *e, int64_t sv, int m, int kk, double *Z,
+                   int64_t sZ, double *lam, int64_t sl, double *scr, int64_t sscr);
+int launch_ormtr(hipStream_t st, int nb, const double *A, int64_t sA, int m, const double *tau, int64_t sv, double *Z,
+                 int64_t sZ, int kk, double *Ut, int64_t sU);
+void launch_svd_finish2(hipStream_t st, int nb, const double *Q, int64_t sQ, int m, int kk, double *C, int64_t sC,
+                        int n, double cutoff, const double *d, int64_t sv, double *U, int64_t sU, int *rank,
+                        double *disc);
+int64_t tri_eig_scratch(int m, int kk);
 void launch_ritz(hipStream_t st, const double *Mm, const double *S, int m, int ld, const double *alpha,
                  const double *beta, double *out_gen, double *out_tri, int *info);
 

@@ -204,19 +204,31 @@ __global__ __launch_bounds__(256) void k_lq(double *__restrict__ Xb, int64_t sX,
           s = wave_sum(s) * tau[q];
           for (int c = q + lane; c < w; c += WAVE) row[c] -= s * (c == q ? 1.0 : v[c]);
         }
-        // Householder vector for row p on columns p..w-1
-        double ss = 0.0;
-        for (int c = p + 1 + lane; c < w; c += WAVE) ss += row[c] * row[c];
-        ss = wave_sum(ss);
+        // Householder vector for row p on columns p..w-1.  The norm is taken
+        // on the row scaled by its largest entry so that no square under- or
+        // overflows (entries far below the row's scale would otherwise turn
+        // into denormals and break the orthogonality of the reflector).
+        double amax = 0.0;
+        for (int c = p + 1 + lane; c < w; c += WAVE) amax = fmax(amax, fabs(row[c]));
+        amax = wave_max(amax);
         const double alpha = row[p];
         double tp, beta;
-        if (ss == 0.0) {
+        if (!(amax > 1e-290)) {  // nothing (or only denormal dust) below the diagonal
           tp = 0.0;
           beta = alpha;
         } else {
-          beta = -copysign(sqrt(alpha * alpha + ss), alpha);
-          tp = (beta - alpha) / beta;
-          const double sc = 1.0 / (alpha - beta);
+          const double scl = fmax(amax, fabs(alpha)), inv = 1.0 / scl;
+          double ss = 0.0;
+          for (int c = p + 1 + lane; c < w; c += WAVE) {
+            const double x = row[c] * inv;
+            ss += x * x;
+          }
+          ss = wave_sum(ss);
+          const double as = alpha * inv;
+          const double bs = -copysign(sqrt(as * as + ss), alpha);
+          beta = bs * scl;
+          tp = (bs - as) / bs;
+          const double sc = inv / (as - bs);
           for (int c = p + 1 + lane; c < w; c += WAVE) row[c] *= sc;
         }
         if (lane == 0) {
@@ -877,6 +889,517 @@ __global__ void k_ritz(const double *__restrict__ Mm, const double *__restrict__
 }
 
 // ---------------------------------------------------------------------------
+// Symmetric eigen path of the SVD step (Gram matrix G = Y Y^T):
+//   sytrd      Householder tridiagonalisation G = Q_H T Q_H^T (lower part)
+//   tri_eig    top-kk eigenpairs of T: bisection (Sturm counts) and inverse
+//              iteration with partial-pivoting tridiagonal LU
+//   ormtr      U^T = Z^T Q_H^T, blocked compact-WY application
+// ---------------------------------------------------------------------------
+
+// sytrd: one workgroup (1024 threads) per matrix.  A (m x m, row-major,
+// symmetric) is read and written in its lower triangle only.  Step i:
+// (a) apply the pending rank-2 update (v_{i-1}, w_{i-1}) to column i,
+// (b) reflector v_i from column i below the diagonal (v_i[i+1] = 1, the
+//     rest stored in A[i+2:, i]), d_i = A[i][i], e_i = beta, tau_i,
+// (c) one pass over the trailing lower triangle that applies the pending
+//     update and accumulates p = A22 v_i (each stored entry feeds p_r and
+//     p_c), (d) w_i = tau p - (tau^2/2 (p.v)) v  (LAPACK dsytd2 'L').
+template <int MMAX>
+__global__ __launch_bounds__(1024) void k_sytrd(double *__restrict__ Ab, int64_t sA, int m,
+                                                double *__restrict__ db, double *__restrict__ eb,
+                                                double *__restrict__ taub, int64_t sv) {
+  constexpr int NW = 16, CPL = MMAX / WAVE;  // columns per lane
+  extern __shared__ double lds[];
+  double *v = lds;              // MMAX
+  double *vp = v + MMAX;        // MMAX pending v
+  double *w = vp + MMAX;        // MMAX pending w
+  double *prow = w + MMAX;      // MMAX
+  double *pp = prow + MMAX;     // NW x MMAX column partials
+  double *red = pp + NW * MMAX; // 64
+  double *A = Ab + (int64_t)blockIdx.x * sA;
+  double *d = db + (int64_t)blockIdx.x * sv;
+  double *e = eb + (int64_t)blockIdx.x * sv;
+  double *tau = taub + (int64_t)blockIdx.x * sv;
+  const int tid = threadIdx.x, lane = tid % WAVE, wid = tid / WAVE;
+  __shared__ int s_pending;
+  __shared__ double s_tau, s_beta;
+  if (tid == 0) s_pending = 0;
+  for (int r = tid; r < MMAX; r += blockDim.x) { vp[r] = 0.0; w[r] = 0.0; }
+  __syncthreads();
+  for (int i = 0; i + 2 < m; ++i) {
+    const int pend = s_pending;
+    // (a) column i, rows i..m-1
+    if (pend) {
+      const double vpi = vp[i], wi = w[i];
+      for (int r = i + tid; r < m; r += blockDim.x) A[(int64_t)r * m + i] -= vp[r] * wi + w[r] * vpi;
+    }
+    __syncthreads();
+    // (b) reflector from x = A[i+1:, i], norm taken on the scaled column
+    {
+      double amax = 0.0;
+      for (int r = i + 2 + tid; r < m; r += blockDim.x) amax = fmax(amax, fabs(A[(int64_t)r * m + i]));
+      amax = wave_max(amax);
+      if (lane == 0) red[32 + wid] = amax;
+      __syncthreads();
+      double am = 0.0;
+      for (int q = 0; q < NW; ++q) am = fmax(am, red[32 + q]);
+      const double alpha0 = A[(int64_t)(i + 1) * m + i];
+      const double scl = fmax(am, fabs(alpha0));
+      if (!(am > 1e-290)) am = 0.0;  // only denormal dust below the subdiagonal: no reflection
+      const double inv = (am > 0.0) ? 1.0 / scl : 0.0;
+      double ss = 0.0;
+      for (int r = i + 2 + tid; r < m; r += blockDim.x) {
+        const double x = A[(int64_t)r * m + i] * inv;
+        ss += x * x;
+      }
+      ss = wave_sum(ss);
+      if (lane == 0) red[wid] = ss;
+      __syncthreads();
+      if (tid == 0) {
+        double s = 0.0;
+        for (int q = 0; q < NW; ++q) s += red[q];
+        const double alpha = alpha0;
+        double t_, beta;
+        if (!(am > 0.0)) {
+          t_ = 0.0;
+          beta = alpha;
+        } else {
+          const double as = alpha * inv;
+          const double bs = -copysign(sqrt(as * as + s), alpha);
+          beta = bs * scl;
+          t_ = (bs - as) / bs;
+          red[NW] = inv / (as - bs);
+        }
+        s_tau = t_;
+        s_beta = beta;
+        d[i] = A[(int64_t)i * m + i];
+        e[i] = beta;
+        tau[i] = t_;
+      }
+      __syncthreads();
+      const double t_ = s_tau;
+      const double sc = (t_ != 0.0) ? red[NW] : 0.0;
+      for (int r = tid; r < MMAX; r += blockDim.x) {
+        double vr = 0.0;
+        if (r == i + 1) vr = 1.0;
+        else if (r > i + 1 && r < m) {
+          const double x = A[(int64_t)r * m + i] * sc;
+          vr = (t_ != 0.0) ? x : 0.0;
+          if (t_ != 0.0) A[(int64_t)r * m + i] = x;
+        }
+        v[r] = vr;
+        prow[r] = 0.0;
+      }
+      __syncthreads();
+    }
+    const double t_ = s_tau;
+    // (c) fused pass over rows r >= i+1, columns i+1..r
+    {
+      double pc[CPL];
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) pc[q] = 0.0;
+      for (int r = i + 1 + wid; r < m; r += NW) {
+        double *row = A + (int64_t)r * m;
+        const double vpr = vp[r], wr = w[r], vr = v[r];
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) {
+          const int c = q * WAVE + lane;
+          if (c >= i + 1 && c <= r) {
+            double a = row[c];
+            if (pend) {
+              a -= vpr * w[c] + wr * vp[c];
+              row[c] = a;
+            }
+            acc += a * v[c];
+            if (c < r) pc[q] += a * vr;
+          }
+        }
+        acc = wave_sum(acc);
+        if (lane == 0) prow[r] = acc;
+      }
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) pp[wid * MMAX + q * WAVE + lane] = pc[q];
+    }
+    __syncthreads();
+    // (d) p = tau (prow + sum of column partials); K = tau/2 p.v; w = p - K v
+    double dotpv = 0.0;
+    for (int r = i + 1 + tid; r < m; r += blockDim.x) {
+      double p = prow[r];
+      for (int q = 0; q < NW; ++q) p += pp[q * MMAX + r];
+      p *= t_;
+      prow[r] = p;
+      dotpv += p * v[r];
+    }
+    dotpv = wave_sum(dotpv);
+    if (lane == 0) red[wid] = dotpv;
+    __syncthreads();
+    double K = 0.0;
+    for (int q = 0; q < NW; ++q) K += red[q];
+    K *= 0.5 * t_;
+    for (int r = tid; r < MMAX; r += blockDim.x) {
+      const bool act = (r >= i + 1 && r < m);
+      w[r] = act ? prow[r] - K * v[r] : 0.0;
+      vp[r] = act ? v[r] : 0.0;
+    }
+    if (tid == 0) s_pending = (t_ != 0.0) ? 1 : 0;
+    __syncthreads();
+  }
+  // trailing 2x2 (or 1x1) block
+  if (tid == 0) {
+    const int pend = s_pending;
+    if (m >= 2) {
+      double a00 = A[(int64_t)(m - 2) * m + (m - 2)], a10 = A[(int64_t)(m - 1) * m + (m - 2)],
+             a11 = A[(int64_t)(m - 1) * m + (m - 1)];
+      if (pend) {
+        a00 -= 2.0 * vp[m - 2] * w[m - 2];
+        a10 -= vp[m - 1] * w[m - 2] + w[m - 1] * vp[m - 2];
+        a11 -= 2.0 * vp[m - 1] * w[m - 1];
+      }
+      d[m - 2] = a00;
+      d[m - 1] = a11;
+      e[m - 2] = a10;
+      tau[m - 2] = 0.0;
+    } else {
+      d[0] = A[0];
+    }
+  }
+}
+
+// Sturm count: number of eigenvalues of the symmetric tridiagonal (d, e) below x.
+__device__ __forceinline__ int sturm_count(const double *d, const double *e2, int m, double x, double pivmin) {
+  int cnt = 0;
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  if (q < 0.0) ++cnt;
+  for (int k = 1; k < m; ++k) {
+    q = (d[k] - x) - e2[k - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    if (q < 0.0) ++cnt;
+  }
+  return cnt;
+}
+
+// tri_eig: top-kk eigenpairs of the tridiagonal (d, e), one workgroup per
+// matrix.  Eigenvalues: bisection on Sturm counts to full precision, thread t
+// owning the t-th largest.  Eigenvectors: inverse iteration (three steps)
+// with a partial-pivoting LU of (T - lambda I), zero pivots replaced by
+// eps*||T||, from a deterministic pseudo-random start.  Eigenvalues closer
+// than 1e-7*||T|| form a cluster whose members are iterated by one thread in
+// turn, each iterate orthogonalised (MGS) against the earlier members, as in
+// LAPACK's stein; eigenvalues below the noise floor 1e-14*||T|| are not
+// clustered (their vectors only need to complete an orthonormal basis,
+// which the re-orthonormalisation that follows provides).
+// Output Z (m x kk, column t = eigenvector t) and lambda (kk, descending).
+// Scratch per job: 4 m kk doubles + m kk ints, laid out [r][t].
+__device__ void inv_iter_one(const double *sd, const double *se, int m, int kk, int t, double lm, double tiny,
+                             double *U0, double *U1, double *U2, double *ML, int *SW, double *Z, int q0) {
+  double r0 = sd[0] - lm, r1 = (m > 1) ? se[0] : 0.0, r2 = 0.0;
+  for (int k = 0; k + 1 < m; ++k) {
+    const double l = se[k], an = sd[k + 1] - lm, bn = (k + 2 < m) ? se[k + 1] : 0.0;
+    const int64_t o = (int64_t)k * kk + t;
+    if (fabs(r0) >= fabs(l)) {
+      if (r0 == 0.0) r0 = tiny;
+      const double mult = l / r0;
+      U0[o] = r0; U1[o] = r1; U2[o] = r2; ML[o] = mult; SW[o] = 0;
+      r0 = an - mult * r1;
+      r1 = bn - mult * r2;
+    } else {
+      const double mult = r0 / l;
+      U0[o] = l; U1[o] = an; U2[o] = bn; ML[o] = mult; SW[o] = 1;
+      const double n0 = r1 - mult * an, n1 = r2 - mult * bn;
+      r0 = n0;
+      r1 = n1;
+    }
+    r2 = 0.0;
+  }
+  if (r0 == 0.0) r0 = tiny;
+  {
+    const int64_t o = (int64_t)(m - 1) * kk + t;
+    U0[o] = r0; U1[o] = 0.0; U2[o] = 0.0;
+  }
+  for (int k = 0; k < m; ++k) {
+    unsigned int h = (unsigned int)k * 2654435761u ^ ((unsigned int)(t + 1) * 40503u) ^ 0x9e3779b9u;
+    h ^= h >> 16; h *= 0x85ebca6bu; h ^= h >> 13; h *= 0xc2b2ae35u; h ^= h >> 16;
+    Z[(int64_t)k * kk + t] = ((double)(h & 0xffffffu) / 16777216.0) - 0.5;
+  }
+  if (!(tiny > 1e-250)) {  // T = 0: every vector is an eigenvector; use e_t
+    for (int k = 0; k < m; ++k) Z[(int64_t)k * kk + t] = (k == t) ? 1.0 : 0.0;
+    return;
+  }
+  for (int iter = 0; iter < 3; ++iter) {
+    double yk = Z[t];
+    for (int k = 0; k + 1 < m; ++k) {
+      const int64_t o = (int64_t)k * kk + t;
+      double yk1 = Z[o + kk];
+      if (SW[o]) { const double tmp = yk; yk = yk1; yk1 = tmp; }
+      yk1 -= ML[o] * yk;
+      Z[o] = yk;
+      yk = yk1;
+    }
+    Z[(int64_t)(m - 1) * kk + t] = yk;
+    // back substitution with running rescaling: a solve against a nearly
+    // singular (T - lambda I) grows by up to 1/eps per tiny pivot, so the
+    // partial solution is scaled down whenever it exceeds 1e150
+    double x1 = 0.0, x2 = 0.0, mx = 0.0;
+    for (int k = m - 1; k >= 0; --k) {
+      const int64_t o = (int64_t)k * kk + t;
+      double x = (Z[o] - U1[o] * x1 - U2[o] * x2) / U0[o];
+      if (fabs(x) > 1e150) {
+        const double s = 1e-150;
+        for (int q = k + 1; q < m; ++q) Z[(int64_t)q * kk + t] *= s;
+        for (int q = 0; q < k; ++q) Z[(int64_t)q * kk + t] *= s;  // remaining right-hand side
+        x1 *= s;
+        x2 *= s;
+        mx *= s;
+        x = (Z[o] * s - U1[o] * x1 - U2[o] * x2) / U0[o];
+      }
+      Z[o] = x;
+      x2 = x1;
+      x1 = x;
+      mx = fmax(mx, fabs(x));
+    }
+    // rescale by the max first (avoids overflow of the 2-norm), then orthogonalise
+    const double im = (mx > 0.0 && isfinite(mx)) ? 1.0 / mx : 0.0;
+    for (int k = 0; k < m; ++k) Z[(int64_t)k * kk + t] *= im;
+    for (int q = q0; q < t; ++q) {
+      double dt = 0.0;
+      for (int k = 0; k < m; ++k) dt += Z[(int64_t)k * kk + q] * Z[(int64_t)k * kk + t];
+      for (int k = 0; k < m; ++k) Z[(int64_t)k * kk + t] -= dt * Z[(int64_t)k * kk + q];
+    }
+    double s2 = 0.0;
+    for (int k = 0; k < m; ++k) { const double x = Z[(int64_t)k * kk + t]; s2 += x * x; }
+    const double inv = (s2 > 0.0) ? 1.0 / sqrt(s2) : 0.0;
+    for (int k = 0; k < m; ++k) Z[(int64_t)k * kk + t] *= inv;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_tri_eig(const double *__restrict__ db, const double *__restrict__ eb,
+                                                 int64_t sv, int m, int kk, double *__restrict__ Zb, int64_t sZ,
+                                                 double *__restrict__ lamb, int64_t sl, double *__restrict__ scrb,
+                                                 int64_t sscr) {
+  __shared__ double sd[1024], se[1024], se2[1024];
+  __shared__ double slam[1024];
+  __shared__ double s_lo, s_hi, s_tn;
+  const double *d0 = db + (int64_t)blockIdx.x * sv;
+  const double *e0 = eb + (int64_t)blockIdx.x * sv;
+  double *Z = Zb + (int64_t)blockIdx.x * sZ;
+  double *lam = lamb + (int64_t)blockIdx.x * sl;
+  double *scr = scrb + (int64_t)blockIdx.x * sscr;
+  const int tid = threadIdx.x;
+  const int64_t MK = (int64_t)m * kk;
+  double *U0 = scr, *U1 = scr + MK, *U2 = scr + 2 * MK, *ML = scr + 3 * MK;
+  int *SW = (int *)(scr + 4 * MK);
+  for (int k = tid; k < m; k += blockDim.x) {
+    sd[k] = d0[k];
+    const double ek = (k + 1 < m) ? e0[k] : 0.0;
+    se[k] = ek;
+    se2[k] = ek * ek;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double lo = 1e300, hi = -1e300, tn = 0.0;
+    for (int k = 0; k < m; ++k) {
+      const double r = (k > 0 ? fabs(se[k - 1]) : 0.0) + (k + 1 < m ? fabs(se[k]) : 0.0);
+      lo = fmin(lo, sd[k] - r);
+      hi = fmax(hi, sd[k] + r);
+      tn = fmax(tn, fabs(sd[k]) + r);
+    }
+    s_lo = lo;
+    s_hi = hi;
+    s_tn = tn;
+  }
+  __syncthreads();
+  // work on T / ||T|| so that no square of an entry under- or overflows
+  const double tn_raw = s_tn;
+  const double tsc = (tn_raw > 1e-280) ? 1.0 / tn_raw : 1.0;
+  __syncthreads();
+  for (int k = tid; k < m; k += blockDim.x) {
+    sd[k] *= tsc;
+    se[k] *= tsc;
+    se2[k] = se[k] * se[k];
+  }
+  __syncthreads();
+  const double tn = (tn_raw > 1e-280) ? 1.0 : 0.0;
+  const double lo_s = s_lo * tsc, hi_s = s_hi * tsc;
+  const double pivmin = 1e-290;
+  const double tiny = (tn > 0.0) ? 2.2e-16 : 0.0;
+  const double pad = 1e-12 * tn + 1e-290;
+  for (int t = tid; t < kk; t += blockDim.x) {
+    const int j = m - 1 - t;  // index in ascending order
+    double a = lo_s - pad, b = hi_s + pad;
+    for (int it = 0; it < 160; ++it) {
+      const double mid = 0.5 * (a + b);
+      if (!(mid > a && mid < b)) break;
+      if (b - a <= 2.2e-16 * fmax(fabs(a), fabs(b)) + pivmin) break;
+      if (sturm_count(sd, se2, m, mid, pivmin) <= j) a = mid;
+      else b = mid;
+    }
+    slam[t] = 0.5 * (a + b);
+    lam[t] = slam[t] * tn_raw;
+  }
+  __syncthreads();
+  const double gap = 1e-7 * tn, noise = 1e-14 * tn;
+  for (int t = tid; t < kk; t += blockDim.x) {
+    const bool sig = slam[t] > noise;
+    const bool leader = !sig || t == 0 || (slam[t - 1] - slam[t] > gap) || !(slam[t - 1] > noise);
+    if (!leader) continue;
+    int t1 = t + 1;
+    if (sig)
+      while (t1 < kk && slam[t1] > noise && slam[t1 - 1] - slam[t1] <= gap) ++t1;
+    for (int u = t; u < t1; ++u) inv_iter_one(sd, se, m, kk, u, slam[u], tiny, U0, U1, U2, ML, SW, Z, t);
+  }
+}
+
+// ormtr: U = Q_H Z = H_0 H_1 ... H_{m-3} Z for Z (m x kk, row-major), the
+// reflectors v_i (v_i[i+1] = 1, v_i[r] = A[r][i] for r >= i+2) and tau_i left
+// by sytrd.  Blocks of NB reflectors are applied last block first as
+// Z <- Z - V (T (V^T Z)) with the forward compact-WY factor T.  The result
+// is written transposed: Ut (kk x m) row t = eigenvector t of G.
+// One workgroup per matrix, thread t owns column t of Z.  LDS: V (NB x m), T.
+template <int NB>
+__global__ __launch_bounds__(256) void k_ormtr(const double *__restrict__ Ab, int64_t sA, int m,
+                                               const double *__restrict__ taub, int64_t sv,
+                                               double *__restrict__ Zb, int64_t sZ, int kk,
+                                               double *__restrict__ Utb, int64_t sU) {
+  extern __shared__ double lds[];
+  double *V = lds;              // NB x m (row p = reflector i0 + p over rows 0..m-1)
+  double *T = V + NB * m;       // NB x NB
+  double *tv = T + NB * NB;     // NB taus
+  const double *A = Ab + (int64_t)blockIdx.x * sA;
+  const double *tau = taub + (int64_t)blockIdx.x * sv;
+  double *Z = Zb + (int64_t)blockIdx.x * sZ;
+  double *Ut = Utb + (int64_t)blockIdx.x * sU;
+  const int tid = threadIdx.x;
+  const int nref = m - 2;  // reflectors 0..m-3
+  const int nblk = nref > 0 ? (nref + NB - 1) / NB : 0;
+  for (int bi = nblk - 1; bi >= 0; --bi) {
+    const int i0 = bi * NB;
+    const int pb = (nref - i0) < NB ? (nref - i0) : NB;
+    for (int e = tid; e < NB * m; e += blockDim.x) {
+      const int p = e / m, r = e % m;
+      const int i = i0 + p;
+      double x = 0.0;
+      if (p < pb) {
+        if (r == i + 1) x = 1.0;
+        else if (r > i + 1) x = A[(int64_t)r * m + i];
+      }
+      V[e] = x;
+    }
+    if (tid < NB) tv[tid] = (tid < pb) ? tau[i0 + tid] : 0.0;
+    __syncthreads();
+    // Y = V^T V (NB x NB) in parallel, then the triangular recursion for T
+    for (int e = tid; e < NB * NB; e += blockDim.x) {
+      const int q = e / NB, p = e % NB;
+      double s = 0.0;
+      if (q < p)
+        for (int r = i0 + p + 1; r < m; ++r) s += V[q * m + r] * V[p * m + r];
+      T[e] = s;  // upper part holds V^T V temporarily
+    }
+    __syncthreads();
+    if (tid == 0) {
+      // T[0:p,p] = -tau_p T[0:p,0:p] (V^T v_p)[0:p], T[p][p] = tau_p
+      for (int p = 0; p < NB; ++p) {
+        double y[NB];
+        for (int q = 0; q < p; ++q) y[q] = T[q * NB + p];
+        for (int q = 0; q < p; ++q) {
+          double acc = 0.0;
+          for (int r2 = q; r2 < p; ++r2) acc += T[q * NB + r2] * y[r2];
+          T[q * NB + p] = -tv[p] * acc;
+        }
+        T[p * NB + p] = tv[p];
+        for (int q = p + 1; q < NB; ++q) T[q * NB + p] = 0.0;
+      }
+    }
+    __syncthreads();
+    for (int c = tid; c < kk; c += blockDim.x) {
+      double W[NB];
+#pragma unroll
+      for (int p = 0; p < NB; ++p) W[p] = 0.0;
+      for (int r = i0 + 1; r < m; ++r) {
+        const double z = Z[(int64_t)r * kk + c];
+#pragma unroll
+        for (int p = 0; p < NB; ++p) W[p] = fma(V[p * m + r], z, W[p]);
+      }
+      double X[NB];
+#pragma unroll
+      for (int p = 0; p < NB; ++p) {
+        double a = 0.0;
+#pragma unroll
+        for (int q = 0; q < NB; ++q) a += (q >= p) ? T[p * NB + q] * W[q] : 0.0;
+        X[p] = a;
+      }
+      for (int r = i0 + 1; r < m; ++r) {
+        double s = 0.0;
+#pragma unroll
+        for (int p = 0; p < NB; ++p) s = fma(V[p * m + r], X[p], s);
+        Z[(int64_t)r * kk + c] -= s;
+      }
+    }
+    __syncthreads();
+  }
+  // transposed write
+  for (int64_t e = tid; e < (int64_t)kk * m; e += blockDim.x) {
+    const int t = (int)(e / m), r = (int)(e % m);
+    Ut[e] = Z[(int64_t)r * kk + t];
+  }
+}
+
+// svd_finish2: C (kk x n) holds Qz Y.  Row norms s_t; cutoff relative to the
+// largest; rows with s_t <= cutoff * s_max are zeroed together with column t
+// of U = Qz^T (m x kk, written to Ub).  rank = 1 + last kept index;
+// discarded = trace(G) - sum_kept s_t^2 with trace(G) = sum(d).
+__global__ __launch_bounds__(256) void k_svd_finish2(const double *__restrict__ Qb, int64_t sQ, int m, int kk,
+                                                     double *__restrict__ Cb, int64_t sC, int n, double cutoff,
+                                                     const double *__restrict__ db, int64_t sv,
+                                                     double *__restrict__ Ub, int64_t sU,
+                                                     int *__restrict__ rank_out, double *__restrict__ disc_out) {
+  __shared__ double nr[1024];
+  __shared__ int s_rank;
+  __shared__ double s_keep2, s_smax;
+  const int job = blockIdx.x;
+  const double *Q = Qb + (int64_t)job * sQ;
+  double *Cc = Cb + (int64_t)job * sC;
+  double *U = Ub + (int64_t)job * sU;
+  const int tid = threadIdx.x, lane = tid % WAVE, wid = tid / WAVE, nw = blockDim.x / WAVE;
+  for (int t = wid; t < kk; t += nw) {
+    double s = 0.0;
+    for (int c = lane; c < n; c += WAVE) { const double x = Cc[(int64_t)t * n + c]; s += x * x; }
+    s = wave_sum(s);
+    if (lane == 0) nr[t] = sqrt(s);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double smax = 0.0;
+    for (int t = 0; t < kk; ++t) smax = fmax(smax, nr[t]);
+    int last = 0;
+    double keep2 = 0.0;
+    for (int t = 0; t < kk; ++t) {
+      const bool keep = smax > 0.0 && nr[t] > cutoff * smax;
+      if (keep) { last = t; keep2 += nr[t] * nr[t]; }
+      else nr[t] = -1.0;
+    }
+    if (!(smax > 0.0)) nr[0] = 0.0;  // zero matrix: keep one (zero) column
+    s_rank = last + 1;
+    s_keep2 = keep2;
+    s_smax = smax;
+    double tr = 0.0;
+    for (int k = 0; k < m; ++k) tr += db[(int64_t)job * sv + k];
+    rank_out[job] = last + 1;
+    disc_out[job] = fmax(0.0, tr - keep2);
+  }
+  __syncthreads();
+  for (int64_t e = tid; e < (int64_t)m * kk; e += blockDim.x) {
+    const int row = (int)(e / kk), t = (int)(e % kk);
+    U[e] = (nr[t] >= 0.0) ? Q[(int64_t)t * m + row] : 0.0;
+  }
+  for (int64_t e = tid; e < (int64_t)kk * n; e += blockDim.x) {
+    const int t = (int)(e / n);
+    if (nr[t] < 0.0) Cc[e] = 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // host launch wrappers
 // ---------------------------------------------------------------------------
 static inline int cdiv64(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
@@ -1007,6 +1530,48 @@ void launch_scale(hipStream_t st, double *p, int64_t count, double c) {
   if (gx < 1) gx = 1;
   hipLaunchKernelGGL(k_scale_range, dim3(gx), dim3(256), 0, st, p, count, c);
 }
+
+template <class K>
+static void set_lds(K kern, size_t lds) {
+  (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+int launch_sytrd(hipStream_t st, int nb, double *A, int64_t sA, int m, double *d, double *e, double *tau, int64_t sv) {
+  if (m > 512) return -1;
+  constexpr int MMAX = 512;
+  size_t lds = (4 * MMAX + 16 * MMAX + 64) * sizeof(double);
+  static bool attr = false;
+  if (!attr) { set_lds(k_sytrd<MMAX>, lds); attr = true; }
+  hipLaunchKernelGGL(k_sytrd<MMAX>, dim3(nb), dim3(1024), lds, st, A, sA, m, d, e, tau, sv);
+  return 0;
+}
+
+int launch_tri_eig(hipStream_t st, int nb, const double *d, const double *e, int64_t sv, int m, int kk, double *Z,
+                   int64_t sZ, double *lam, int64_t sl, double *scr, int64_t sscr) {
+  if (m > 1024) return -1;
+  hipLaunchKernelGGL(k_tri_eig, dim3(nb), dim3(256), 0, st, d, e, sv, m, kk, Z, sZ, lam, sl, scr, sscr);
+  return 0;
+}
+
+int launch_ormtr(hipStream_t st, int nb, const double *A, int64_t sA, int m, const double *tau, int64_t sv, double *Z,
+                 int64_t sZ, int kk, double *Ut, int64_t sU) {
+  constexpr int NB = 16;
+  if (m > 1024) return -1;
+  size_t lds = ((size_t)NB * m + NB * NB + NB) * sizeof(double);
+  static bool attr = false;
+  if (!attr) { set_lds(k_ormtr<NB>, (NB * 1024 + NB * NB + NB) * sizeof(double)); attr = true; }
+  hipLaunchKernelGGL(k_ormtr<NB>, dim3(nb), dim3(256), lds, st, A, sA, m, tau, sv, Z, sZ, kk, Ut, sU);
+  return 0;
+}
+
+void launch_svd_finish2(hipStream_t st, int nb, const double *Q, int64_t sQ, int m, int kk, double *C, int64_t sC,
+                        int n, double cutoff, const double *d, int64_t sv, double *U, int64_t sU, int *rank,
+                        double *disc) {
+  hipLaunchKernelGGL(k_svd_finish2, dim3(nb), dim3(256), 0, st, Q, sQ, m, kk, C, sC, n, cutoff, d, sv, U, sU, rank,
+                     disc);
+}
+
+int64_t tri_eig_scratch(int m, int kk) { return 4 * (int64_t)m * kk + ((int64_t)m * kk + 1) / 2 + 8; }
 
 void launch_ritz(hipStream_t st, const double *Mm, const double *S, int m, int ld, const double *alpha,
                  const double *beta, double *out_gen, double *out_tri, int *info) {

@@ -17,6 +17,12 @@ from oracle import thc as TH
 
 pytestmark = pytest.mark.gpu
 
+# Both SVD methods of the truncation step: 0 = eigenpairs of the Gram matrix
+# (default), 1 = one-sided block Jacobi.  The Gram method resolves singular
+# values below ~1e-8 s_1 only to ~eps s_1^2 / s; on the Hartree-Fock-derived
+# states used here (Schmidt spectra spanning > 20 decades) it still meets 1e-11.
+SVD_MODES = [(0, 1e-11), (1, 1e-12)]
+
 
 def _norm_mps(rng, n, D):
     psi = synth.random_mps_tensors(rng, n, D)
@@ -61,15 +67,15 @@ def test_layer_compress(thck, dag, D):
     st = thck.ThcStats()
     out = ctx.apply_layer(thck.DeviceMPS.from_sites(psi), y, dag, D, stats=st)
     got = M.to_dense(out.to_sites())
-    ref_state = OH.layer_compress(psi, np.asarray(y), 0, bool(dag), D) if False else \
-        M.compress(M.apply_layer(psi, y, bool(dag)), D)
+    ref_state = M.compress(M.apply_layer(psi, y, bool(dag)), D)
     ref = M.to_dense(ref_state)
     tol = 1e-12 if D >= 16 else 1e-9
     assert _rel(got, ref) < tol, (_rel(got, ref), st.as_dict())
     assert out.bond_list() == M.bonds(ref_state)
 
 
-def test_compress_hf_rank_deficient(thck):
+@pytest.mark.parametrize("flags,tol", SVD_MODES)
+def test_compress_hf_rank_deficient(thck, flags, tol):
     # bond-1 product state: every layer output is rank deficient in the padding
     L = 4
     occ = synth.hartree_fock_occupation(L, 4)
@@ -78,9 +84,9 @@ def test_compress_hf_rank_deficient(thck):
     y = rng.standard_normal(2 * L)
     t, chi, zeta = synth.thc_factors(np.random.default_rng(0), L, 2)
     ctx = thck.Context(t, chi, zeta)
-    out = ctx.apply_layer(thck.DeviceMPS.from_sites(hf), y, 0, 8)
+    out = ctx.apply_layer(thck.DeviceMPS.from_sites(hf), y, 0, 8, flags=flags)
     ref_state = M.compress(M.apply_layer(hf, y, False), 8)
-    assert _rel(M.to_dense(out.to_sites()), M.to_dense(ref_state)) < 1e-12
+    assert _rel(M.to_dense(out.to_sites()), M.to_dense(ref_state)) < tol
     assert out.bond_list() == M.bonds(ref_state)
 
 
@@ -140,7 +146,8 @@ def test_apply_H_truncated_matches_oracle_tree(thck):
     assert err < 1e-8
 
 
-def test_hf_energy_gpu(thck):
+@pytest.mark.parametrize("flags,tol", SVD_MODES)
+def test_hf_energy_gpu(thck, flags, tol):
     L, N = 4, 8
     t, chi, zeta = synth.thc_factors(np.random.default_rng(8), L, N)
     v = TH.thc_v(chi, zeta)
@@ -149,11 +156,14 @@ def test_hf_energy_gpu(thck):
     hf = synth.occupation_mps_tensors(occ)
     ctx = thck.Context(t, chi, zeta)
     dhf = thck.DeviceMPS.from_sites(hf)
-    e = ctx.overlap(dhf, ctx.apply_H(dhf, D=16))
-    assert abs(e - HF.closed_shell_energy(t, v, [0, 1])) < 1e-12 * max(1, abs(e))
+    e = ctx.overlap(dhf, ctx.apply_H(dhf, D=16, flags=flags))
+    err = abs(e - HF.closed_shell_energy(t, v, [0, 1])) / max(1, abs(e))
+    print(f"HF energy flags={flags}: rel err {err:.3e}")
+    assert err < tol
 
 
-def test_lanczos_small_matches_oracle(thck):
+@pytest.mark.parametrize("flags,tol", SVD_MODES)
+def test_lanczos_small_matches_oracle(thck, flags, tol):
     L, N = 3, 4
     t, chi, zeta = synth.thc_factors(np.random.default_rng(16), L, N)
     occ = synth.hartree_fock_occupation(L, 2)
@@ -161,10 +171,12 @@ def test_lanczos_small_matches_oracle(thck):
     K = 5
     st = OL.KrylovState(hf, K)
     ctx = thck.Context(t, chi, zeta)
-    kr = thck.Krylov(ctx, thck.DeviceMPS.from_sites(hf), K, D=8)
+    kr = thck.Krylov(ctx, thck.DeviceMPS.from_sites(hf), K, D=8, flags=flags)
+    atol = max(1e-10, 100 * tol)
     for i in range(K):
         rg, rt, b = OL.krylov_step(st, t, chi, zeta, D=8)
         g, tt, bb = kr.step()
-        assert np.allclose(g, rg, atol=1e-10, rtol=0), (i, g, rg)
-        assert np.allclose(tt, rt, atol=1e-10, rtol=0), (i, tt, rt)
-        assert abs(bb - b) < 1e-10
+        print(f"lanczos flags={flags} step {i}: ritz err {np.max(np.abs(g - rg)):.2e}")
+        assert np.allclose(g, rg, atol=atol, rtol=0), (i, g, rg)
+        assert np.allclose(tt, rt, atol=atol, rtol=0), (i, tt, rt)
+        assert abs(bb - b) < atol
