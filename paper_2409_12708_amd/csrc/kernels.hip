@@ -356,6 +356,251 @@ __global__ __launch_bounds__(256) void k_lq(double *__restrict__ Xb, int64_t sX,
 }
 
 // ---------------------------------------------------------------------------
+// MFMA FP64 helpers (v_mfma_f64_16x16x4f64 on gfx950).  Operand layouts:
+//   A (16x4):  lane l holds A[l%16][l/16]
+//   B (4x16):  lane l holds B[l/16][l%16]
+//   D (16x16): lane l, register r holds D[l/16 + 4r][l%16]
+// ---------------------------------------------------------------------------
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4_t mfma16(double a, double b, d4_t c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Block reflector applied to a set of rows of a row-major matrix:
+//   X[r, c0:c0+w] <- X[r, c0:c0+w] - ((X V^T) Tm V)[r, :]   for r in [r_begin, r_end)
+// V: LDS, 16 x vld (row p = reflector p over the w columns, zero-padded),
+// Tm: LDS 16 x 16 (T for X(I - V^T T V)... applied as X - X V^T T V; pass T^T
+// to apply the transposed block reflector).  Work split: 16-row tiles; the w
+// columns are cut into NWV chunks (one per wave) of multiples of 4; each wave
+// computes its partial X V^T on MFMA, the partials are summed in LDS (Wp),
+// multiplied by Tm (WT), and each wave updates its own column chunk on MFMA.
+template <int NWV>
+__device__ void block_reflect_rows(double *__restrict__ X, int ldx, int r_begin, int r_end, int c0, int w,
+                                   const double *__restrict__ V, int vld, const double *__restrict__ Tm,
+                                   double *__restrict__ Wp, double *__restrict__ WT) {
+  constexpr int SMAX = 32;  // k-steps of 4 columns per wave (w <= 4 * SMAX * NWV)
+  const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
+  const int chunk = ((w + NWV - 1) / NWV + 15) / 16 * 16;  // columns per wave, multiple of 16
+  const int cb = wv * chunk;
+  const int ce = min(w, cb + chunk);
+  const int li = lane % 16, lk = lane / 16;
+  const int S = (ce > cb) ? (ce - cb + 3) / 4 : 0;
+  for (int rt = r_begin; rt < r_end; rt += 16) {
+    // this wave's 16 x chunk tile in registers: xa[s] = X[rt+li][cb+4s+lk]
+    const int row = rt + li;
+    const bool rok = row < r_end;
+    double *xr = X + (int64_t)row * ldx + c0 + cb + lk;
+    double xa[SMAX];
+#pragma unroll
+    for (int s = 0; s < SMAX; ++s) {
+      const int kc = cb + 4 * s + lk;
+      xa[s] = (s < S && rok && kc < ce) ? xr[4 * s] : 0.0;
+    }
+    // partial W = X V^T over this wave's columns
+    d4_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < SMAX; ++s) {
+      if (s < S) {
+        const int kc = cb + 4 * s + lk;
+        const double bv = (kc < ce) ? V[li * vld + kc] : 0.0;
+        acc = mfma16(xa[s], bv, acc);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Wp[wv * 256 + (lk + 4 * r) * 16 + li] = acc[r];
+    __syncthreads();
+    if (tid < 256) {
+      const int i = tid / 16, p = tid % 16;
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < NWV; ++q) s += Wp[q * 256 + i * 16 + p];
+      Wp[NWV * 256 + i * 16 + p] = s;
+    }
+    __syncthreads();
+    if (tid < 256) {
+      const int i = tid / 16, p = tid % 16;
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) s += Wp[NWV * 256 + i * 16 + q] * Tm[q * 16 + p];
+      WT[i * 16 + p] = s;
+    }
+    __syncthreads();
+    // update, transposed so the result lands in the xa layout:
+    // D^T[c][i] = sum_p V[p][c] WT[i][p]; lane l, reg r -> column lk + 4r, row li
+    double bw[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) bw[q] = WT[li * 16 + 4 * q + lk];
+#pragma unroll
+    for (int b4 = 0; b4 < SMAX / 4; ++b4) {
+      if (4 * b4 < S) {
+        const int c16 = cb + 16 * b4;
+        d4_t d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int cc = c16 + li;
+          const double av = (cc < ce) ? V[(4 * q + lk) * vld + cc] : 0.0;  // A[c][p] = V[p][c]
+          d = mfma16(av, bw[q], d);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) xa[4 * b4 + r] -= d[r];
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < SMAX; ++s) {
+      const int kc = cb + 4 * s + lk;
+      if (s < S && rok && kc < ce) xr[4 * s] = xa[s];
+    }
+    __syncthreads();
+  }
+}
+
+// lq2: X (m x n) = L Q by blocked Householder (panels of 16 rows, compact WY),
+// the trailing update and the formation of Q on MFMA tiles.  One workgroup
+// of 512 threads per matrix.  Same outputs and storage as k_lq.
+template <int NMAX>
+__global__ __launch_bounds__(512) void k_lq2(double *__restrict__ Xb, int64_t sX, int m, int n,
+                                             double *__restrict__ Lb, int64_t sL, double *__restrict__ Qb,
+                                             int64_t sQ, double *__restrict__ Tb, int64_t sT) {
+  constexpr int NB = 16, NWV = 8;
+  constexpr int VLD = NMAX + 1;     // padded row stride: rows of V fall in different LDS banks
+  extern __shared__ double lds[];
+  double *P = lds;                  // NB x VLD panel / reflectors
+  double *T = P + NB * VLD;         // 16 x 16
+  double *TT = T + 256;             // 16 x 16 (transpose)
+  double *Wp = TT + 256;            // (NWV + 1) x 256
+  double *WT = Wp + (NWV + 1) * 256;  // 256
+  double *tau = WT + 256;           // 16
+  double *X = Xb + (int64_t)blockIdx.x * sX;
+  double *Lo = Lb + (int64_t)blockIdx.x * sL;
+  double *Qo = Qb + (int64_t)blockIdx.x * sQ;
+  double *Ts = Tb + (int64_t)blockIdx.x * sT;
+  const int tid = threadIdx.x, lane = tid % WAVE, wid = tid / WAVE;
+  const int k = m < n ? m : n;
+
+  for (int i0 = 0; i0 < k; i0 += NB) {
+    const int pb = (k - i0) < NB ? (k - i0) : NB;
+    const int w = n - i0;
+    for (int e = tid; e < NB * w; e += blockDim.x) {
+      const int p = e / w, c = e % w;
+      P[p * VLD + c] = (p < pb) ? X[(int64_t)(i0 + p) * n + i0 + c] : 0.0;
+    }
+    __syncthreads();
+    if (wid == 0) {
+      for (int p = 0; p < pb; ++p) {
+        double *row = P + p * VLD;
+        for (int q = 0; q < p; ++q) {
+          const double *v = P + q * VLD;
+          double s = 0.0;
+          for (int c = q + lane; c < w; c += WAVE) s += row[c] * (c == q ? 1.0 : v[c]);
+          s = wave_sum(s) * tau[q];
+          for (int c = q + lane; c < w; c += WAVE) row[c] -= s * (c == q ? 1.0 : v[c]);
+        }
+        double amax = 0.0;
+        for (int c = p + 1 + lane; c < w; c += WAVE) amax = fmax(amax, fabs(row[c]));
+        amax = wave_max(amax);
+        const double alpha = row[p];
+        double tp, beta;
+        if (!(amax > 1e-290)) {
+          tp = 0.0;
+          beta = alpha;
+        } else {
+          const double scl = fmax(amax, fabs(alpha)), inv = 1.0 / scl;
+          double ss = 0.0;
+          for (int c = p + 1 + lane; c < w; c += WAVE) {
+            const double x = row[c] * inv;
+            ss += x * x;
+          }
+          ss = wave_sum(ss);
+          const double as = alpha * inv;
+          const double bs = -copysign(sqrt(as * as + ss), alpha);
+          beta = bs * scl;
+          tp = (bs - as) / bs;
+          const double sc = inv / (as - bs);
+          for (int c = p + 1 + lane; c < w; c += WAVE) row[c] *= sc;
+        }
+        if (lane == 0) {
+          row[p] = beta;
+          tau[p] = tp;
+        }
+      }
+      for (int p = 0; p < NB; ++p) {
+        for (int q = 0; q < p; ++q) {
+          double s = 0.0;
+          if (p < pb) {
+            const double *vq = P + q * VLD, *vp = P + p * VLD;
+            for (int c = p + lane; c < w; c += WAVE) s += (c == q ? 1.0 : vq[c]) * (c == p ? 1.0 : vp[c]);
+            s = wave_sum(s);
+          }
+          if (lane == 0) T[q * 16 + p] = s;
+        }
+        if (lane == 0) {
+          double y[NB];
+          for (int q = 0; q < p; ++q) y[q] = T[q * 16 + p];
+          const double tpp = (p < pb) ? tau[p] : 0.0;
+          for (int q = 0; q < p; ++q) {
+            double acc = 0.0;
+            for (int r = q; r < p; ++r) acc += T[q * 16 + r] * y[r];
+            T[q * 16 + p] = -tpp * acc;
+          }
+          T[p * 16 + p] = tpp;
+          for (int q = p + 1; q < NB; ++q) T[q * 16 + p] = 0.0;
+        }
+      }
+    }
+    __syncthreads();
+    // store the panel (L part + reflectors), T for the Q pass; make P the
+    // explicit V (unit diagonal, zeros left of it) for the MFMA update
+    for (int e = tid; e < pb * w; e += blockDim.x) {
+      const int p = e / w, c = e % w;
+      X[(int64_t)(i0 + p) * n + i0 + c] = P[p * VLD + c];
+    }
+    for (int e = tid; e < 256; e += blockDim.x) Ts[(int64_t)(i0 / NB) * 256 + e] = T[e];
+    __syncthreads();
+    for (int e = tid; e < NB * w; e += blockDim.x) {
+      const int p = e / w, c = e % w;
+      if (p >= pb || c < p) P[p * VLD + c] = 0.0;
+      else if (c == p) P[p * VLD + c] = 1.0;
+    }
+    __syncthreads();
+    // trailing rows: X_r <- X_r - (X_r V^T) T V
+    block_reflect_rows<NWV>(X, n, i0 + pb, m, i0, w, P, VLD, T, Wp, WT);
+  }
+
+  for (int64_t e = tid; e < (int64_t)m * k; e += blockDim.x) {
+    const int r = (int)(e / k), c = (int)(e % k);
+    Lo[e] = (c <= r) ? X[(int64_t)r * n + c] : 0.0;
+  }
+  for (int64_t e = tid; e < (int64_t)k * n; e += blockDim.x) {
+    const int r = (int)(e / n), c = (int)(e % n);
+    Qo[e] = (r == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int npanel = (k + NB - 1) / NB;
+  for (int pi = npanel - 1; pi >= 0; --pi) {
+    const int i0 = pi * NB;
+    const int pb = (k - i0) < NB ? (k - i0) : NB;
+    const int w = n - i0;
+    for (int e = tid; e < NB * w; e += blockDim.x) {
+      const int p = e / w, c = e % w;
+      double v = 0.0;
+      if (p < pb) {
+        if (c == p) v = 1.0;
+        else if (c > p) v = X[(int64_t)(i0 + p) * n + i0 + c];
+      }
+      P[p * VLD + c] = v;
+    }
+    for (int e = tid; e < 256; e += blockDim.x) {
+      const int q = e / 16, p = e % 16;
+      TT[e] = Ts[(int64_t)pi * 256 + p * 16 + q];  // T^T
+    }
+    __syncthreads();
+    // Q_r <- Q_r - (Q_r V^T) T^T V for rows i0..k-1
+    block_reflect_rows<NWV>(Qo, n, i0, k, i0, w, P, VLD, TT, Wp, WT);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // jacobi: one-sided block Jacobi on the rows of Y (m x n, row-major, in
 // place) until the rows are mutually orthogonal.  Rows are split in blocks
 // of BS; every pair of blocks (round-robin order) is staged in LDS, its
@@ -1127,7 +1372,7 @@ __device__ void inv_iter_one(const double *sd, const double *se, int m, int kk, 
     for (int k = 0; k < m; ++k) Z[(int64_t)k * kk + t] = (k == t) ? 1.0 : 0.0;
     return;
   }
-  for (int iter = 0; iter < 3; ++iter) {
+  for (int iter = 0; iter < 2; ++iter) {
     double yk = Z[t];
     for (int k = 0; k + 1 < m; ++k) {
       const int64_t o = (int64_t)k * kk + t;
@@ -1225,13 +1470,25 @@ __global__ __launch_bounds__(256) void k_tri_eig(const double *__restrict__ db, 
   const double pivmin = 1e-290;
   const double tiny = (tn > 0.0) ? 2.2e-16 : 0.0;
   const double pad = 1e-12 * tn + 1e-290;
+  // eigenvalues above the noise floor: m - #{lambda < noise}; the rest only
+  // need to complete an orthonormal basis (re-orthonormalisation follows)
+  const double gap = 1e-6, noise = 1e-14 * tn;
+  __shared__ int s_nsig;
+  if (tid == 0) s_nsig = (tn > 0.0) ? m - sturm_count(sd, se2, m, noise, pivmin) : 0;
+  __syncthreads();
+  const int nsig = s_nsig;
   for (int t = tid; t < kk; t += blockDim.x) {
+    if (t >= nsig) {
+      slam[t] = 0.0;
+      lam[t] = 0.0;
+      continue;
+    }
     const int j = m - 1 - t;  // index in ascending order
-    double a = lo_s - pad, b = hi_s + pad;
-    for (int it = 0; it < 160; ++it) {
+    double a = fmax(lo_s - pad, noise), b = hi_s + pad;
+    for (int it = 0; it < 80; ++it) {
       const double mid = 0.5 * (a + b);
       if (!(mid > a && mid < b)) break;
-      if (b - a <= 2.2e-16 * fmax(fabs(a), fabs(b)) + pivmin) break;
+      if (b - a <= 2.2e-16 * fmax(fabs(a), fabs(b)) + 1e-18 * tn) break;
       if (sturm_count(sd, se2, m, mid, pivmin) <= j) a = mid;
       else b = mid;
     }
@@ -1239,14 +1496,24 @@ __global__ __launch_bounds__(256) void k_tri_eig(const double *__restrict__ db, 
     lam[t] = slam[t] * tn_raw;
   }
   __syncthreads();
-  const double gap = 1e-7 * tn, noise = 1e-14 * tn;
   for (int t = tid; t < kk; t += blockDim.x) {
-    const bool sig = slam[t] > noise;
-    const bool leader = !sig || t == 0 || (slam[t - 1] - slam[t] > gap) || !(slam[t - 1] > noise);
+    if (t >= nsig) {  // noise: a pseudo-random direction, orthonormalised later
+      for (int k = 0; k < m; ++k) {
+        unsigned int h = (unsigned int)k * 2654435761u ^ ((unsigned int)(t + 7) * 40503u) ^ 0x9e3779b9u;
+        h ^= h >> 16; h *= 0x85ebca6bu; h ^= h >> 13; h *= 0xc2b2ae35u; h ^= h >> 16;
+        Z[(int64_t)k * kk + t] = ((double)(h & 0xffffffu) / 16777216.0) - 0.5;
+      }
+      continue;
+    }
+    // cluster: consecutive eigenvalues closer than rgap relative to their size
+    // (an absolute threshold would chain every tiny eigenvalue into one cluster);
+    // the MGS within a cluster is capped at 32 members, beyond which distinct
+    // pseudo-random starts keep the iterates independent
+    auto close = [&](int u) { return slam[u - 1] - slam[u] <= gap * slam[u - 1] + 1e-15 * tn; };
+    const bool leader = t == 0 || !close(t) || (t % 32 == 0);
     if (!leader) continue;
     int t1 = t + 1;
-    if (sig)
-      while (t1 < kk && slam[t1] > noise && slam[t1 - 1] - slam[t1] <= gap) ++t1;
+    while (t1 < kk && t1 < nsig && close(t1) && (t1 % 32 != 0)) ++t1;
     for (int u = t; u < t1; ++u) inv_iter_one(sd, se, m, kk, u, slam[u], tiny, U0, U1, U2, ML, SW, Z, t);
   }
 }
@@ -1425,11 +1692,27 @@ void launch_gemm(hipStream_t st, int nb, bool transB, const double *A, int64_t s
 
 int lq_t_stride(int k) {
   const int NB = 16;
-  return ((k + NB - 1) / NB) * (NB * NB + NB);
+  return ((k + NB - 1) / NB) * (NB * NB + NB);  // covers both LQ kernels (k_lq2 uses NB*NB per panel)
 }
 
 int launch_lq(hipStream_t st, int nb, double *X, int64_t sX, int m, int n, double *L, int64_t sL, double *Q,
               int64_t sQ, double *Tw, int64_t sT) {
+  if (n <= 1024) {
+    constexpr int NMAX = 1024, NWV = 8;
+    size_t lds = (16 * (NMAX + 1) + 256 + 256 + (NWV + 1) * 256 + 256 + 16) * sizeof(double);
+    static bool attr2 = false;
+    if (!attr2) {
+      (void)hipFuncSetAttribute((const void *)k_lq2<NMAX>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      attr2 = true;
+    }
+    hipLaunchKernelGGL((k_lq2<NMAX>), dim3(nb), dim3(512), lds, st, X, sX, m, n, L, sL, Q, sQ, Tw, sT);
+    return 0;
+  }
+  return -1;
+}
+
+int launch_lq_v1(hipStream_t st, int nb, double *X, int64_t sX, int m, int n, double *L, int64_t sL, double *Q,
+                 int64_t sQ, double *Tw, int64_t sT) {
   constexpr int NB = 16;
   if (n <= 1024) {
     constexpr int NMAX = 1024;
