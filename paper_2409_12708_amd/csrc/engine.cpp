@@ -380,16 +380,16 @@ struct Engine {
       launch_construct(st, dj, nb, j, n, P.pa.off[j], P.kind ? P.pb.off[j] : 0, la, ra, lb, rb, Bb, S, P.bo[j],
                        P.bo[j + 1]);
       ++launches;
-      double *X;
+      // X_j = B_j L_{j+1} (bo_j x 2 c_{j+1}) is handed to the LQ kernel
+      // transposed; the kernel returns Q_j transposed (2 c_{j+1} x c_j)
       if (j == n - 1) {
-        X = Bb;  // (bo, 2, 1)
+        launch_transpose(st, nb, Bb, S, P.bo[j], 2, Tb, S);
       } else {
-        launch_gemm(st, nb, false, Bb, S, P.bo[j + 1], Lb, S, P.c[j + 1], Tb, S, P.c[j + 1], P.bo[j] * 2,
-                    P.c[j + 1], P.bo[j + 1]);
-        ++launches;
-        X = Tb;
+        launch_gemm(st, nb, GEMM_ST2, Bb, S, P.bo[j + 1], Lb, S, P.c[j + 1], Tb, S, P.bo[j], P.bo[j] * 2, P.c[j + 1],
+                    P.bo[j + 1]);
       }
-      if (launch_lq(st, nb, X, S, P.bo[j], 2 * P.c[j + 1], Lb, S, Qs + P.qs_off[j], S, Tf, S) != 0)
+      ++launches;
+      if (launch_lq(st, nb, Tb, S, P.bo[j], 2 * P.c[j + 1], Lb, S, Qs + P.qs_off[j], S, Tf, S, true) != 0)
         raise(THC_EINVAL, "site matrix too wide for the LQ kernel (2*bond > 1024)");
     }
     // site 0: M_0 = B_0 * L_1 (1, 2, c_1)
@@ -399,7 +399,7 @@ struct Engine {
       launch_construct(st, dj, nb, 0, n, P.pa.off[0], P.kind ? P.pb.off[0] : 0, la, ra, lb, rb, Bb, S, P.bo[0],
                        P.bo[1]);
       if (n > 1)
-        launch_gemm(st, nb, false, Bb, S, P.bo[1], Lb, S, P.c[1], Mb, S, P.c[1], 2, P.c[1], P.bo[1]);
+        launch_gemm(st, nb, 0, Bb, S, P.bo[1], Lb, S, P.c[1], Mb, S, P.c[1], 2, P.c[1], P.bo[1]);
       else
         launch_copy(st, nb, Bb, S, Mb, S, 2);
       launches += 2;
@@ -414,21 +414,24 @@ struct Engine {
     for (int j = 0; j + 1 < n && !jacobi; ++j) {
       const int m = 2 * P.k[j], nc = P.c[j + 1], kk = P.k[j + 1];
       // Gram G = Y Y^T, Y = M_j (m x nc)
-      launch_gemm(st, nb, true, Mb, S, nc, Mb, S, nc, Gb, S, m, m, m, nc);
+      launch_gemm(st, nb, GEMM_TB, Mb, S, nc, Mb, S, nc, Gb, S, m, m, m, nc);
       if (launch_sytrd(st, nb, Gb, S, m, Db, Eb, Taub, S) != 0) raise(THC_EINVAL, "site matrix too tall for sytrd");
       if (launch_tri_eig(st, nb, Db, Eb, S, m, kk, Zm, S, Lam, S, Scr, S) != 0)
         raise(THC_EINVAL, "site matrix too tall for the tridiagonal eigensolver");
-      if (launch_ormtr(st, nb, Gb, S, m, Taub, S, Zm, S, kk, Zb, S) != 0) raise(THC_EINVAL, "ormtr size");
-      // orthonormal rows spanning the top-kk eigenvectors
-      if (launch_lq(st, nb, Zb, S, kk, m, Lz, S, Qz, S, Tf, S) != 0)
+      // eigenvectors as the columns of Z (m x kk)
+      if (launch_ormtr(st, nb, Gb, S, m, Taub, S, Zm, S, kk, Zb, S, true) != 0) raise(THC_EINVAL, "ormtr size");
+      // orthonormal rows spanning the top-kk eigenvectors: LQ of Z^T, given
+      // transposed; Qz holds Q^T (m x kk)
+      if (launch_lq(st, nb, Zb, S, kk, m, Lz, S, Qz, S, Tf, S, true) != 0)
         raise(THC_EINVAL, "site matrix too wide for the LQ kernel");
-      // C = Qz (kk x m) * M (m x nc)
-      launch_gemm(st, nb, false, Qz, S, m, Mb, S, nc, Cb, S, nc, kk, nc, m);
+      // C = Q (kk x m) * M (m x nc)
+      launch_gemm(st, nb, GEMM_TA, Qz, S, kk, Mb, S, nc, Cb, S, nc, kk, nc, m);
       launch_svd_finish2(st, nb, Qz, S, m, kk, Cb, S, nc, cutoff(), Db, S, Ub, S, rk_d + (size_t)j * nb,
-                         dw_d + (size_t)j * nb);
+                         dw_d + (size_t)j * nb, true);
       launch_scatter(st, nb, dj, P.out.off[j], Ub, S, (int64_t)m * kk);
-      launch_gemm(st, nb, false, Cb, S, nc, Qs + P.qs_off[j + 1], S, 2 * P.c[j + 2], Mb, S, 2 * P.c[j + 2], kk,
-                  2 * P.c[j + 2], nc);
+      // M_{j+1} = C (kk x c_{j+1}) * Q_{j+1} (Q_{j+1} stored transposed)
+      launch_gemm(st, nb, GEMM_TB, Cb, S, nc, Qs + P.qs_off[j + 1], S, nc, Mb, S, 2 * P.c[j + 2], kk, 2 * P.c[j + 2],
+                  nc);
       launches += 10;
     }
     if (!jacobi) HIPCHK(hipMemsetAsync(sw_d, 0, (size_t)nb * n * sizeof(int), st));
@@ -440,16 +443,16 @@ struct Engine {
       launch_svd_select(st, nb, Yb, S, m, nc, Sb, S, kk, cutoff(), Wb, S, rk_d + (size_t)j * nb,
                         dw_d + (size_t)j * nb, nullptr, 0);
       // Z = W (kk x nc) * M^T (nc x m)
-      launch_gemm(st, nb, true, Wb, S, nc, Mb, S, nc, Zb, S, m, kk, m, nc);
+      launch_gemm(st, nb, GEMM_TB, Wb, S, nc, Mb, S, nc, Zb, S, m, kk, m, nc);
       if (launch_lq(st, nb, Zb, S, kk, m, Lz, S, Qz, S, Tf, S) != 0)
         raise(THC_EINVAL, "site matrix too wide for the LQ kernel");
       // C = Qz (kk x m) * M (m x nc)
-      launch_gemm(st, nb, false, Qz, S, m, Mb, S, nc, Cb, S, nc, kk, nc, m);
+      launch_gemm(st, nb, 0, Qz, S, m, Mb, S, nc, Cb, S, nc, kk, nc, m);
       launch_svd_finish(st, nb, Qz, S, m, kk, rk_d + (size_t)j * nb, Ub, S, Cb, S, nc);
       launch_scatter(st, nb, dj, P.out.off[j], Ub, S, (int64_t)m * kk);
-      // M_{j+1} = C (kk x c_{j+1}) * Q_{j+1} (c_{j+1} x 2 c_{j+2})
-      launch_gemm(st, nb, false, Cb, S, nc, Qs + P.qs_off[j + 1], S, 2 * P.c[j + 2], Mb, S, 2 * P.c[j + 2], kk,
-                  2 * P.c[j + 2], nc);
+      // M_{j+1} = C (kk x c_{j+1}) * Q_{j+1} (Q_{j+1} stored transposed)
+      launch_gemm(st, nb, GEMM_TB, Cb, S, nc, Qs + P.qs_off[j + 1], S, nc, Mb, S, 2 * P.c[j + 2], kk, 2 * P.c[j + 2],
+                  nc);
       launches += 9;
     }
     // last site

@@ -32,10 +32,17 @@ int lq_t_stride(int k);
 void launch_construct(hipStream_t st, const CJob *jobs, int nb, int site, int n_sites, int64_t in_off_a,
                       int64_t in_off_b, int la, int ra, int lb, int rb, double *out, int64_t out_stride, int lo,
                       int ro);
-void launch_gemm(hipStream_t st, int nb, bool transB, const double *A, int64_t sA, int lda, const double *B,
+// GEMM modes (bits): B given transposed, A given transposed, split-transposed
+// store (see k_gemm_mfma).
+constexpr int GEMM_TB = 1, GEMM_TA = 2, GEMM_ST2 = 4;
+void launch_gemm(hipStream_t st, int nb, int mode, const double *A, int64_t sA, int lda, const double *B,
                  int64_t sB, int ldb, double *C, int64_t sC, int ldc, int M, int N, int K);
+void launch_transpose(hipStream_t st, int nb, const double *src, int64_t ss, int r, int c, double *dst, int64_t sd);
+// LQ of X (m x n): L (m x min(m,n), row-major), Q (min(m,n) x n).  With tr,
+// X is given transposed (n x m row-major) and Q is returned transposed
+// (n x min(m,n) row-major); L keeps its layout.
 int launch_lq(hipStream_t st, int nb, double *X, int64_t sX, int m, int n, double *L, int64_t sL, double *Q,
-              int64_t sQ, double *Tw, int64_t sT);
+              int64_t sQ, double *Tw, int64_t sT, bool tr = false);
 int launch_jacobi(hipStream_t st, int nb, double *Y, int64_t sY, int m, int n, double *s, int64_t ss, int *sweeps,
                   int max_sweeps);
 void launch_svd_select(hipStream_t st, int nb, const double *Y, int64_t sY, int m, int n, const double *s,
@@ -56,11 +63,13 @@ void launch_repack(hipStream_t st, int gx, const double *src, int64_t soff, int 
 int launch_sytrd(hipStream_t st, int nb, double *A, int64_t sA, int m, double *d, double *e, double *tau, int64_t sv);
 int launch_tri_eig(hipStream_t st, int nb, const double *d, const double *e, int64_t sv, int m, int kk, double *Z,
                    int64_t sZ, double *lam, int64_t sl, double *scr, int64_t sscr);
+// U = Q_H Z; written as rows of Ut (kk x m), or with zout as Z itself (m x kk).
 int launch_ormtr(hipStream_t st, int nb, const double *A, int64_t sA, int m, const double *tau, int64_t sv, double *Z,
-                 int64_t sZ, int kk, double *Ut, int64_t sU);
+                 int64_t sZ, int kk, double *Ut, int64_t sU, bool zout = false);
+// qt: Q given as its transpose (m x kk) instead of kk x m.
 void launch_svd_finish2(hipStream_t st, int nb, const double *Q, int64_t sQ, int m, int kk, double *C, int64_t sC,
                         int n, double cutoff, const double *d, int64_t sv, double *U, int64_t sU, int *rank,
-                        double *disc);
+                        double *disc, bool qt = false);
 int64_t tri_eig_scratch(int m, int kk);
 void launch_ritz(hipStream_t st, const double *Mm, const double *S, int m, int ld, const double *alpha,
                  const double *beta, double *out_gen, double *out_tri, int *info);

@@ -99,273 +99,156 @@ __global__ void k_construct(const CJob *__restrict__ jobs, int site, int n_sites
 }
 
 // ---------------------------------------------------------------------------
-// gemm: C = op(A) * op(B), row-major, FP64, batched by blockIdx.z.
-// 64x64 output tile, BK = 16, 256 threads, 4x4 outputs per thread.
-// transB: B is given as N x K (row-major) and used transposed.
-// ---------------------------------------------------------------------------
-template <bool TRANS_B>
-__global__ __launch_bounds__(256) void k_gemm_f64(const double *__restrict__ A, int64_t sA, int lda,
-                                                  const double *__restrict__ B, int64_t sB, int ldb,
-                                                  double *__restrict__ C, int64_t sC, int ldc, int M,
-                                                  int N, int K) {
-  constexpr int TM = 64, TN = 64, TK = 16;
-  __shared__ double As[TK][TM + 1];
-  __shared__ double Bs[TK][TN + 1];
-  A += (int64_t)blockIdx.z * sA;
-  B += (int64_t)blockIdx.z * sB;
-  C += (int64_t)blockIdx.z * sC;
-  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
-  const int tid = threadIdx.x;
-  const int tr = tid / 16, tc = tid % 16;
-  double acc[4][4] = {};
-  for (int k0 = 0; k0 < K; k0 += TK) {
-    for (int e = tid; e < TM * TK; e += 256) {
-      int mm = e / TK, kk = e % TK;
-      int gm = m0 + mm, gk = k0 + kk;
-      As[kk][mm] = (gm < M && gk < K) ? A[(int64_t)gm * lda + gk] : 0.0;
-    }
-    for (int e = tid; e < TN * TK; e += 256) {
-      if (TRANS_B) {
-        int nn = e / TK, kk = e % TK;
-        int gn = n0 + nn, gk = k0 + kk;
-        Bs[kk][nn] = (gn < N && gk < K) ? B[(int64_t)gn * ldb + gk] : 0.0;
-      } else {
-        int kk = e / TN, nn = e % TN;
-        int gn = n0 + nn, gk = k0 + kk;
-        Bs[kk][nn] = (gn < N && gk < K) ? B[(int64_t)gk * ldb + gn] : 0.0;
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < TK; ++kk) {
-      double a[4], b[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][tr * 4 + i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tc * 4 + j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    int gm = m0 + tr * 4 + i;
-    if (gm >= M) continue;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      int gn = n0 + tc * 4 + j;
-      if (gn < N) C[(int64_t)gm * ldc + gn] = acc[i][j];
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// lq: X (m x n, row-major, in place) = L Q by Householder reflections acting
-// on rows (LAPACK dgelqf/dorglq style, blocked with panels of NB rows and
-// the compact WY form H_i ... H_{i+nb-1} = I - V T V^T).  One workgroup
-// (256 threads) per matrix.  Outputs: L (m x k, row-major), Q (k x n,
-// row-major), k = min(m, n).  X keeps the reflectors afterwards.
-// LDS: the panel rows (NB x n) and T (NB x NB).
-// ---------------------------------------------------------------------------
-template <int NB, int NMAX>
-__global__ __launch_bounds__(256) void k_lq(double *__restrict__ Xb, int64_t sX, int m, int n,
-                                            double *__restrict__ Lb, int64_t sL, double *__restrict__ Qb,
-                                            int64_t sQ, double *__restrict__ Tb, int64_t sT) {
-  extern __shared__ double lds[];
-  double *P = lds;                // NB x NMAX panel (reflectors v, unit diagonal implicit)
-  double *T = P + NB * NMAX;      // NB x NB
-  double *tau = T + NB * NB;      // NB
-  double *X = Xb + (int64_t)blockIdx.x * sX;
-  double *Lo = Lb + (int64_t)blockIdx.x * sL;
-  double *Qo = Qb + (int64_t)blockIdx.x * sQ;
-  double *Ts = Tb + (int64_t)blockIdx.x * sT;  // all panels' T factors and taus
-  const int tid = threadIdx.x, lane = tid % WAVE, wid = tid / WAVE, nw = blockDim.x / WAVE;
-  const int k = m < n ? m : n;
-
-  for (int i0 = 0; i0 < k; i0 += NB) {
-    const int pb = (k - i0) < NB ? (k - i0) : NB;
-    const int w = n - i0;  // panel width
-    // load panel rows i0..i0+pb-1, columns i0..n-1
-    for (int e = tid; e < pb * w; e += blockDim.x) {
-      int p = e / w, c = e % w;
-      P[p * NMAX + c] = X[(int64_t)(i0 + p) * n + i0 + c];
-    }
-    __syncthreads();
-    if (wid == 0) {
-      for (int p = 0; p < pb; ++p) {
-        double *row = P + p * NMAX;
-        for (int q = 0; q < p; ++q) {  // apply H_q (q < p) to row p
-          const double *v = P + q * NMAX;
-          double s = 0.0;
-          for (int c = q + lane; c < w; c += WAVE) s += row[c] * (c == q ? 1.0 : v[c]);
-          s = wave_sum(s) * tau[q];
-          for (int c = q + lane; c < w; c += WAVE) row[c] -= s * (c == q ? 1.0 : v[c]);
-        }
-        // Householder vector for row p on columns p..w-1.  The norm is taken
-        // on the row scaled by its largest entry so that no square under- or
-        // overflows (entries far below the row's scale would otherwise turn
-        // into denormals and break the orthogonality of the reflector).
-        double amax = 0.0;
-        for (int c = p + 1 + lane; c < w; c += WAVE) amax = fmax(amax, fabs(row[c]));
-        amax = wave_max(amax);
-        const double alpha = row[p];
-        double tp, beta;
-        if (!(amax > 1e-290)) {  // nothing (or only denormal dust) below the diagonal
-          tp = 0.0;
-          beta = alpha;
-        } else {
-          const double scl = fmax(amax, fabs(alpha)), inv = 1.0 / scl;
-          double ss = 0.0;
-          for (int c = p + 1 + lane; c < w; c += WAVE) {
-            const double x = row[c] * inv;
-            ss += x * x;
-          }
-          ss = wave_sum(ss);
-          const double as = alpha * inv;
-          const double bs = -copysign(sqrt(as * as + ss), alpha);
-          beta = bs * scl;
-          tp = (bs - as) / bs;
-          const double sc = inv / (as - bs);
-          for (int c = p + 1 + lane; c < w; c += WAVE) row[c] *= sc;
-        }
-        if (lane == 0) {
-          row[p] = beta;
-          tau[p] = tp;
-        }
-      }
-      // T factor (forward, columnwise): T[p][p] = tau_p,
-      // T[0:p, p] = -tau_p T[0:p, 0:p] (V[:, 0:p]^T v_p)
-      for (int p = 0; p < pb; ++p) {
-        for (int q = 0; q < p; ++q) {
-          const double *vq = P + q * NMAX, *vp = P + p * NMAX;
-          double s = 0.0;
-          for (int c = p + lane; c < w; c += WAVE) s += (c == q ? 1.0 : vq[c]) * (c == p ? 1.0 : vp[c]);
-          s = wave_sum(s);
-          if (lane == 0) T[q * NB + p] = s;  // temporarily V^T v_p
-        }
-        if (lane == 0) {
-          // y = V^T v_p (stored in column p rows 0..p-1); T[0:p,p] = -tau_p * T[0:p,0:p] y
-          double y[NB];
-          for (int q = 0; q < p; ++q) y[q] = T[q * NB + p];
-          for (int q = 0; q < p; ++q) {
-            double acc = 0.0;
-            for (int r = q; r < p; ++r) acc += T[q * NB + r] * y[r];
-            T[q * NB + p] = -tau[p] * acc;
-          }
-          T[p * NB + p] = tau[p];
-          for (int q = p + 1; q < NB; ++q) T[q * NB + p] = 0.0;
-        }
-      }
-    }
-    __syncthreads();
-    // store the panel back (L part and reflectors) and T/tau for the Q pass
-    for (int e = tid; e < pb * w; e += blockDim.x) {
-      int p = e / w, c = e % w;
-      X[(int64_t)(i0 + p) * n + i0 + c] = P[p * NMAX + c];
-    }
-    for (int e = tid; e < NB * NB; e += blockDim.x) Ts[(int64_t)(i0 / NB) * (NB * NB + NB) + e] = T[e];
-    for (int e = tid; e < NB; e += blockDim.x) Ts[(int64_t)(i0 / NB) * (NB * NB + NB) + NB * NB + e] = (e < pb) ? tau[e] : 0.0;
-    // trailing rows: X_r <- X_r - (X_r V) T V^T, columns i0..n-1
-    for (int r = i0 + pb + wid; r < m; r += nw) {
-      double *xr = X + (int64_t)r * n + i0;
-      double wv[NB];
-#pragma unroll
-      for (int p = 0; p < NB; ++p) wv[p] = 0.0;
-      for (int c = lane; c < w; c += WAVE) {
-        const double x = xr[c];
-#pragma unroll
-        for (int p = 0; p < NB; ++p)
-          if (p < pb) wv[p] += x * (c == p ? 1.0 : (c > p ? P[p * NMAX + c] : 0.0));
-      }
-#pragma unroll
-      for (int p = 0; p < NB; ++p) wv[p] = wave_sum(wv[p]);
-      double u[NB];
-#pragma unroll
-      for (int p = 0; p < NB; ++p) {
-        double a = 0.0;
-        for (int q = 0; q <= p && q < pb; ++q) a += wv[q] * T[q * NB + p];
-        u[p] = (p < pb) ? a : 0.0;
-      }
-      for (int c = lane; c < w; c += WAVE) {
-        double d = 0.0;
-#pragma unroll
-        for (int p = 0; p < NB; ++p)
-          if (p < pb) d += u[p] * (c == p ? 1.0 : (c > p ? P[p * NMAX + c] : 0.0));
-        xr[c] -= d;
-      }
-    }
-    __syncthreads();
-  }
-
-  // L (m x k): lower-triangular part of X
-  for (int64_t e = tid; e < (int64_t)m * k; e += blockDim.x) {
-    int r = (int)(e / k), c = (int)(e % k);
-    Lo[e] = (c <= r) ? X[(int64_t)r * n + c] : 0.0;
-  }
-  // Q = [I_k 0] H_{k-1} ... H_0, panels applied last-to-first:
-  // rows i0..k-1: Q_r <- Q_r - (Q_r V) T^T V^T
-  for (int64_t e = tid; e < (int64_t)k * n; e += blockDim.x) {
-    int r = (int)(e / n), c = (int)(e % n);
-    Qo[e] = (r == c) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  const int npanel = (k + NB - 1) / NB;
-  for (int pi = npanel - 1; pi >= 0; --pi) {
-    const int i0 = pi * NB;
-    const int pb = (k - i0) < NB ? (k - i0) : NB;
-    const int w = n - i0;
-    for (int e = tid; e < pb * w; e += blockDim.x) {
-      int p = e / w, c = e % w;
-      P[p * NMAX + c] = X[(int64_t)(i0 + p) * n + i0 + c];
-    }
-    for (int e = tid; e < NB * NB; e += blockDim.x) T[e] = Ts[(int64_t)pi * (NB * NB + NB) + e];
-    __syncthreads();
-    for (int r = i0 + wid; r < k; r += nw) {
-      double *qr = Qo + (int64_t)r * n + i0;
-      double wv[NB];
-#pragma unroll
-      for (int p = 0; p < NB; ++p) wv[p] = 0.0;
-      for (int c = lane; c < w; c += WAVE) {
-        const double x = qr[c];
-#pragma unroll
-        for (int p = 0; p < NB; ++p)
-          if (p < pb) wv[p] += x * (c == p ? 1.0 : (c > p ? P[p * NMAX + c] : 0.0));
-      }
-#pragma unroll
-      for (int p = 0; p < NB; ++p) wv[p] = wave_sum(wv[p]);
-      double u[NB];
-#pragma unroll
-      for (int p = 0; p < NB; ++p) {  // u = w T^T : u_p = sum_q w_q T[p][q]
-        double a = 0.0;
-        for (int q = p; q < pb; ++q) a += wv[q] * T[p * NB + q];
-        u[p] = (p < pb) ? a : 0.0;
-      }
-      for (int c = lane; c < w; c += WAVE) {
-        double d = 0.0;
-#pragma unroll
-        for (int p = 0; p < NB; ++p)
-          if (p < pb) d += u[p] * (c == p ? 1.0 : (c > p ? P[p * NMAX + c] : 0.0));
-        qr[c] -= d;
-      }
-    }
-    __syncthreads();
-  }
-}
-
-// ---------------------------------------------------------------------------
 // MFMA FP64 helpers (v_mfma_f64_16x16x4f64 on gfx950).  Operand layouts:
 //   A (16x4):  lane l holds A[l%16][l/16]
 //   B (4x16):  lane l holds B[l/16][l%16]
 //   D (16x16): lane l, register r holds D[l/16 + 4r][l%16]
 // ---------------------------------------------------------------------------
 typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef unsigned int u2_t __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ d4_t mfma16(double a, double b, d4_t c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
+
+// ---------------------------------------------------------------------------
+// gemm: C = op(A) * op(B), row-major FP64, batched.  A is M x K (lda), or
+// with TA given as its transpose (K x M, lda).  B is K x N (ldb), or with TB
+// given as N x K.  ST2: the M rows are (a, s) pairs (M = 2 M2) and C is
+// stored as the transpose of the M2 x (2N) matrix [C_(a,0) | C_(a,1)], i.e.
+// element (2a + s, n) goes to C[(s N + n) ldc + a].  MFMA 16x16x4 tiles:
+// BM x BN output tile per workgroup of 4 waves (2 x 2, each wave BM/2 x
+// BN/2), K in chunks of 16 staged in LDS, the next chunk prefetched into
+// registers while the current one is multiplied.  A and B^T chunks sit in
+// LDS as [rows][17] (fragment reads of 16 rows x 4 k spread over the banks),
+// a plain B chunk as [16][BN + 16].  The workgroup index is remapped so
+// that each XCD (workgroups are dealt to the 8 XCDs round-robin) receives a
+// contiguous run of (job, tile) pairs: the tiles of one job share that
+// XCD's L2.
+// ---------------------------------------------------------------------------
+template <int MODE, int BM, int BN>
+__global__ __launch_bounds__(256) void k_gemm_mfma(const double *__restrict__ A, int64_t sA, int lda,
+                                                   const double *__restrict__ B, int64_t sB, int ldb,
+                                                   double *__restrict__ C, int64_t sC, int ldc, int M, int N,
+                                                   int K, int tiles_m, int tiles_n) {
+  constexpr bool TB = (MODE & GEMM_TB) != 0, TA = (MODE & GEMM_TA) != 0, ST2 = (MODE & GEMM_ST2) != 0;
+  constexpr int BK = 16;
+  constexpr int WM = BM / 32, WN = BN / 32;  // 16x16 blocks per wave
+  constexpr int LA = BK + 1;                 // row stride of [rows][k] chunks
+  constexpr int LB = BN + 16;                // row stride of a [k][n] chunk
+  constexpr int NA = BM * BK / 256, NBL = BN * BK / 256;
+  __shared__ double As[BM * LA];
+  __shared__ double Bs[TB ? BN * LA : BK * LB];
+
+  const int T = tiles_m * tiles_n;
+  const int G = gridDim.x;
+  int g = blockIdx.x;
+  if ((G & 7) == 0) g = (g & 7) * (G >> 3) + (g >> 3);
+  const int job = g / T, t = g % T;
+  const int m0 = (t / tiles_n) * BM, n0 = (t % tiles_n) * BN;
+  A += (int64_t)job * sA;
+  B += (int64_t)job * sB;
+  C += (int64_t)job * sC;
+
+  const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
+  const int wm = wv >> 1, wn = wv & 1;
+  const int li = lane % 16, lk = lane / 16;
+
+  // global -> register mapping: 16 consecutive threads read 16 consecutive k
+  // of one row (A, B^T) or of one k-row of B (n fastest)
+  double ra[NA], rb[NBL];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      if (TA) {
+        const int e = tid + 256 * i;
+        const int r = e % BM, k = e / BM;
+        const int gm = m0 + r, gk = k0 + k;
+        ra[i] = (gm < M && gk < K) ? A[(int64_t)gk * lda + gm] : 0.0;
+      } else {
+        const int r = tid / 16 + 16 * i, k = tid % 16;
+        const int gm = m0 + r, gk = k0 + k;
+        ra[i] = (gm < M && gk < K) ? A[(int64_t)gm * lda + gk] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NBL; ++i) {
+      if (TB) {
+        const int r = tid / 16 + 16 * i, k = tid % 16;
+        const int gn = n0 + r, gk = k0 + k;
+        rb[i] = (gn < N && gk < K) ? B[(int64_t)gn * ldb + gk] : 0.0;
+      } else {
+        const int e = tid + 256 * i;
+        const int k = e / BN, c = e % BN;
+        const int gn = n0 + c, gk = k0 + k;
+        rb[i] = (gn < N && gk < K) ? B[(int64_t)gk * ldb + gn] : 0.0;
+      }
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      if (TA) {
+        const int e = tid + 256 * i;
+        As[(e % BM) * LA + e / BM] = ra[i];
+      } else {
+        As[(tid / 16 + 16 * i) * LA + tid % 16] = ra[i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NBL; ++i) {
+      if (TB) {
+        Bs[(tid / 16 + 16 * i) * LA + tid % 16] = rb[i];
+      } else {
+        const int e = tid + 256 * i;
+        Bs[(e / BN) * LB + e % BN] = rb[i];
+      }
+    }
+  };
+
+  d4_t acc[WM][WN];
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+
+  load(0);
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    store();
+    __syncthreads();
+    if (k0 + BK < K) load(k0 + BK);
+#pragma unroll
+    for (int ks = 0; ks < BK / 4; ++ks) {
+      double af[WM], bf[WN];
+#pragma unroll
+      for (int i = 0; i < WM; ++i) af[i] = As[(wm * (BM / 2) + 16 * i + li) * LA + 4 * ks + lk];
+#pragma unroll
+      for (int j = 0; j < WN; ++j)
+        bf[j] = TB ? Bs[(wn * (BN / 2) + 16 * j + li) * LA + 4 * ks + lk]
+                   : Bs[(4 * ks + lk) * LB + wn * (BN / 2) + 16 * j + li];
+#pragma unroll
+      for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j) acc[i][j] = mfma16(af[i], bf[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+      const int gc = n0 + wn * (BN / 2) + 16 * j + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gr = m0 + wm * (BM / 2) + 16 * i + lk + 4 * r;
+        if (gr < M && gc < N) {
+          if (ST2) C[((int64_t)(gr & 1) * N + gc) * ldc + (gr >> 1)] = acc[i][j][r];
+          else C[(int64_t)gr * ldc + gc] = acc[i][j][r];
+        }
+      }
+    }
+}
+
 
 // Block reflector applied to a set of rows of a row-major matrix:
 //   X[r, c0:c0+w] <- X[r, c0:c0+w] - ((X V^T) Tm V)[r, :]   for r in [r_begin, r_end)
@@ -375,10 +258,13 @@ __device__ __forceinline__ d4_t mfma16(double a, double b, d4_t c) {
 // columns are cut into NWV chunks (one per wave) of multiples of 4; each wave
 // computes its partial X V^T on MFMA, the partials are summed in LDS (Wp),
 // multiplied by Tm (WT), and each wave updates its own column chunk on MFMA.
-template <int NWV>
-__device__ void block_reflect_rows(double *__restrict__ X, int ldx, int r_begin, int r_end, int c0, int w,
-                                   const double *__restrict__ V, int vld, const double *__restrict__ Tm,
+template <int NWV, bool TR>
+__device__ __forceinline__ void block_reflect_rows(double *__restrict__ X, int ldx, int64_t xbytes, int r_begin, int r_end, int c0,
+                                   int w, const double *__restrict__ V, int vld, const double *__restrict__ Tm,
                                    double *__restrict__ Wp, double *__restrict__ WT) {
+  // buffer loads / stores: one per-lane offset, the k-step as a scalar
+  // offset, accesses past xbytes read 0 and are dropped
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(X, 0, (int)xbytes, 0x00020000);
   constexpr int SMAX = 32;  // k-steps of 4 columns per wave (w <= 4 * SMAX * NWV)
   const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
   const int chunk = ((w + NWV - 1) / NWV + 15) / 16 * 16;  // columns per wave, multiple of 16
@@ -390,12 +276,18 @@ __device__ void block_reflect_rows(double *__restrict__ X, int ldx, int r_begin,
     // this wave's 16 x chunk tile in registers: xa[s] = X[rt+li][cb+4s+lk]
     const int row = rt + li;
     const bool rok = row < r_end;
-    double *xr = X + (int64_t)row * ldx + c0 + cb + lk;
+    // element (row, c0 + kc): row-major X[row * ldx + c0 + kc], or with TR
+    // (X stored transposed) X[(c0 + kc) * ldx + row]; 16 lanes then read 16
+    // consecutive doubles
+    const int vo = 8 * (TR ? (c0 + cb + lk) * ldx + row : row * ldx + c0 + cb + lk);
+    const int so = 8 * (TR ? 4 * ldx : 4);
     double xa[SMAX];
 #pragma unroll
     for (int s = 0; s < SMAX; ++s) {
       const int kc = cb + 4 * s + lk;
-      xa[s] = (s < S && rok && kc < ce) ? xr[4 * s] : 0.0;
+      double x = 0.0;
+      if (s < S) x = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, vo, s * so, 0));
+      xa[s] = (rok && kc < ce) ? x : 0.0;
     }
     // partial W = X V^T over this wave's columns
     d4_t acc = {0.0, 0.0, 0.0, 0.0};
@@ -449,7 +341,8 @@ __device__ void block_reflect_rows(double *__restrict__ X, int ldx, int r_begin,
 #pragma unroll
     for (int s = 0; s < SMAX; ++s) {
       const int kc = cb + 4 * s + lk;
-      if (s < S && rok && kc < ce) xr[4 * s] = xa[s];
+      if (s < S && rok && kc < ce)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2_t, xa[s]), rs, vo, s * so, 0);
     }
     __syncthreads();
   }
@@ -458,7 +351,7 @@ __device__ void block_reflect_rows(double *__restrict__ X, int ldx, int r_begin,
 // lq2: X (m x n) = L Q by blocked Householder (panels of 16 rows, compact WY),
 // the trailing update and the formation of Q on MFMA tiles.  One workgroup
 // of 512 threads per matrix.  Same outputs and storage as k_lq.
-template <int NMAX>
+template <int NMAX, bool TR>
 __global__ __launch_bounds__(512) void k_lq2(double *__restrict__ Xb, int64_t sX, int m, int n,
                                              double *__restrict__ Lb, int64_t sL, double *__restrict__ Qb,
                                              int64_t sQ, double *__restrict__ Tb, int64_t sT) {
@@ -471,89 +364,118 @@ __global__ __launch_bounds__(512) void k_lq2(double *__restrict__ Xb, int64_t sX
   double *Wp = TT + 256;            // (NWV + 1) x 256
   double *WT = Wp + (NWV + 1) * 256;  // 256
   double *tau = WT + 256;           // 16
+  double *Gd = tau + 16;            // 16 x 16 reflector dot products
   double *X = Xb + (int64_t)blockIdx.x * sX;
   double *Lo = Lb + (int64_t)blockIdx.x * sL;
   double *Qo = Qb + (int64_t)blockIdx.x * sQ;
   double *Ts = Tb + (int64_t)blockIdx.x * sT;
   const int tid = threadIdx.x, lane = tid % WAVE, wid = tid / WAVE;
   const int k = m < n ? m : n;
+  // element (r, c) of X: row-major, or with TR stored transposed (X^T, n x m)
+  auto XI = [&](int r, int c) -> int64_t { return TR ? (int64_t)c * m + r : (int64_t)r * n + c; };
 
   for (int i0 = 0; i0 < k; i0 += NB) {
     const int pb = (k - i0) < NB ? (k - i0) : NB;
     const int w = n - i0;
     for (int e = tid; e < NB * w; e += blockDim.x) {
-      const int p = e / w, c = e % w;
-      P[p * VLD + c] = (p < pb) ? X[(int64_t)(i0 + p) * n + i0 + c] : 0.0;
+      const int p = TR ? e % NB : e / w, c = TR ? e / NB : e % w;
+      P[p * VLD + c] = (p < pb) ? X[XI(i0 + p, i0 + c)] : 0.0;
     }
     __syncthreads();
     if (wid == 0) {
+      // panel rows one after the other; row p lives in registers (lane l
+      // holds columns l + 64 t), the earlier reflectors are read from LDS
+      constexpr int CPL = NMAX / WAVE;
       for (int p = 0; p < pb; ++p) {
         double *row = P + p * VLD;
+        double rr[CPL];
+#pragma unroll
+        for (int t = 0; t < CPL; ++t) {
+          const int c = lane + WAVE * t;
+          rr[t] = (c < w) ? row[c] : 0.0;
+        }
         for (int q = 0; q < p; ++q) {
           const double *v = P + q * VLD;
+          double vv[CPL];
           double s = 0.0;
-          for (int c = q + lane; c < w; c += WAVE) s += row[c] * (c == q ? 1.0 : v[c]);
+#pragma unroll
+          for (int t = 0; t < CPL; ++t) {
+            const int c = lane + WAVE * t;
+            vv[t] = (c > q && c < w) ? v[c] : (c == q ? 1.0 : 0.0);
+            s += rr[t] * vv[t];
+          }
           s = wave_sum(s) * tau[q];
-          for (int c = q + lane; c < w; c += WAVE) row[c] -= s * (c == q ? 1.0 : v[c]);
+#pragma unroll
+          for (int t = 0; t < CPL; ++t) rr[t] -= s * vv[t];
         }
         double amax = 0.0;
-        for (int c = p + 1 + lane; c < w; c += WAVE) amax = fmax(amax, fabs(row[c]));
+#pragma unroll
+        for (int t = 0; t < CPL; ++t) {
+          const int c = lane + WAVE * t;
+          if (c > p && c < w) amax = fmax(amax, fabs(rr[t]));
+        }
         amax = wave_max(amax);
-        const double alpha = row[p];
-        double tp, beta;
+        const double alpha = __shfl(rr[0], p, WAVE);
+        double tp, beta, sc = 1.0;
         if (!(amax > 1e-290)) {
           tp = 0.0;
           beta = alpha;
         } else {
           const double scl = fmax(amax, fabs(alpha)), inv = 1.0 / scl;
           double ss = 0.0;
-          for (int c = p + 1 + lane; c < w; c += WAVE) {
-            const double x = row[c] * inv;
-            ss += x * x;
+#pragma unroll
+          for (int t = 0; t < CPL; ++t) {
+            const int c = lane + WAVE * t;
+            const double x = rr[t] * inv;
+            if (c > p && c < w) ss += x * x;
           }
           ss = wave_sum(ss);
           const double as = alpha * inv;
           const double bs = -copysign(sqrt(as * as + ss), alpha);
           beta = bs * scl;
           tp = (bs - as) / bs;
-          const double sc = inv / (as - bs);
-          for (int c = p + 1 + lane; c < w; c += WAVE) row[c] *= sc;
+          sc = inv / (as - bs);
         }
-        if (lane == 0) {
-          row[p] = beta;
-          tau[p] = tp;
+#pragma unroll
+        for (int t = 0; t < CPL; ++t) {
+          const int c = lane + WAVE * t;
+          if (c < w) row[c] = (c > p) ? rr[t] * sc : (c == p ? beta : rr[t]);
         }
+        if (lane == 0) tau[p] = tp;
       }
+    }
+    __syncthreads();
+    // G[q][p] = v_q . v_p (q < p), one dot product per wave at a time
+    for (int dd = wid; dd < NB * NB; dd += NWV) {
+      const int q = dd / NB, p = dd % NB;
+      if (q < p) {
+        double sacc = 0.0;
+        if (p < pb) {
+          const double *vq = P + q * VLD, *vp = P + p * VLD;
+          for (int c = p + lane; c < w; c += WAVE) sacc += vq[c] * (c == p ? 1.0 : vp[c]);
+          sacc = wave_sum(sacc);
+        }
+        if (lane == 0) Gd[dd] = sacc;
+      }
+    }
+    __syncthreads();
+    if (tid < NB) {
+      // forward compact-WY factor: T[0:p, p] = -tau_p T[0:p, 0:p] G[0:p, p];
+      // lane q owns row q of T
+      const int q = tid;
       for (int p = 0; p < NB; ++p) {
-        for (int q = 0; q < p; ++q) {
-          double s = 0.0;
-          if (p < pb) {
-            const double *vq = P + q * VLD, *vp = P + p * VLD;
-            for (int c = p + lane; c < w; c += WAVE) s += (c == q ? 1.0 : vq[c]) * (c == p ? 1.0 : vp[c]);
-            s = wave_sum(s);
-          }
-          if (lane == 0) T[q * 16 + p] = s;
-        }
-        if (lane == 0) {
-          double y[NB];
-          for (int q = 0; q < p; ++q) y[q] = T[q * 16 + p];
-          const double tpp = (p < pb) ? tau[p] : 0.0;
-          for (int q = 0; q < p; ++q) {
-            double acc = 0.0;
-            for (int r = q; r < p; ++r) acc += T[q * 16 + r] * y[r];
-            T[q * 16 + p] = -tpp * acc;
-          }
-          T[p * 16 + p] = tpp;
-          for (int q = p + 1; q < NB; ++q) T[q * 16 + p] = 0.0;
-        }
+        const double tp = (p < pb) ? tau[p] : 0.0;
+        double acc = 0.0;
+        for (int r = q; r < p; ++r) acc += T[q * 16 + r] * Gd[r * 16 + p];
+        T[q * 16 + p] = (q < p) ? -tp * acc : (q == p ? tp : 0.0);
       }
     }
     __syncthreads();
     // store the panel (L part + reflectors), T for the Q pass; make P the
     // explicit V (unit diagonal, zeros left of it) for the MFMA update
     for (int e = tid; e < pb * w; e += blockDim.x) {
-      const int p = e / w, c = e % w;
-      X[(int64_t)(i0 + p) * n + i0 + c] = P[p * VLD + c];
+      const int p = TR ? e % pb : e / w, c = TR ? e / pb : e % w;
+      X[XI(i0 + p, i0 + c)] = P[p * VLD + c];
     }
     for (int e = tid; e < 256; e += blockDim.x) Ts[(int64_t)(i0 / NB) * 256 + e] = T[e];
     __syncthreads();
@@ -564,16 +486,16 @@ __global__ __launch_bounds__(512) void k_lq2(double *__restrict__ Xb, int64_t sX
     }
     __syncthreads();
     // trailing rows: X_r <- X_r - (X_r V^T) T V
-    block_reflect_rows<NWV>(X, n, i0 + pb, m, i0, w, P, VLD, T, Wp, WT);
+    block_reflect_rows<NWV, TR>(X, TR ? m : n, (int64_t)m * n * 8, i0 + pb, m, i0, w, P, VLD, T, Wp, WT);
   }
 
   for (int64_t e = tid; e < (int64_t)m * k; e += blockDim.x) {
     const int r = (int)(e / k), c = (int)(e % k);
-    Lo[e] = (c <= r) ? X[(int64_t)r * n + c] : 0.0;
+    Lo[e] = (c <= r) ? X[XI(r, c)] : 0.0;
   }
   for (int64_t e = tid; e < (int64_t)k * n; e += blockDim.x) {
     const int r = (int)(e / n), c = (int)(e % n);
-    Qo[e] = (r == c) ? 1.0 : 0.0;
+    Qo[TR ? (int64_t)c * k + r : e] = (r == c) ? 1.0 : 0.0;
   }
   __syncthreads();
   const int npanel = (k + NB - 1) / NB;
@@ -582,11 +504,11 @@ __global__ __launch_bounds__(512) void k_lq2(double *__restrict__ Xb, int64_t sX
     const int pb = (k - i0) < NB ? (k - i0) : NB;
     const int w = n - i0;
     for (int e = tid; e < NB * w; e += blockDim.x) {
-      const int p = e / w, c = e % w;
+      const int p = TR ? e % NB : e / w, c = TR ? e / NB : e % w;
       double v = 0.0;
       if (p < pb) {
         if (c == p) v = 1.0;
-        else if (c > p) v = X[(int64_t)(i0 + p) * n + i0 + c];
+        else if (c > p) v = X[XI(i0 + p, i0 + c)];
       }
       P[p * VLD + c] = v;
     }
@@ -596,7 +518,7 @@ __global__ __launch_bounds__(512) void k_lq2(double *__restrict__ Xb, int64_t sX
     }
     __syncthreads();
     // Q_r <- Q_r - (Q_r V^T) T^T V for rows i0..k-1
-    block_reflect_rows<NWV>(Qo, n, i0, k, i0, w, P, VLD, TT, Wp, WT);
+    block_reflect_rows<NWV, TR>(Qo, TR ? k : n, (int64_t)k * n * 8, i0, k, i0, w, P, VLD, TT, Wp, WT);
   }
 }
 
@@ -900,6 +822,18 @@ __global__ void k_copy(const double *__restrict__ src, int64_t ssrc, double *__r
 }
 
 // gather copy: dst[job] = src_ptrs[job] + off (count elements)
+// transpose: dst (c x r) = src (r x c)^T, batched.
+__global__ void k_transpose(const double *__restrict__ src, int64_t ss, int r, int c, double *__restrict__ dst,
+                            int64_t sd) {
+  const double *a = src + (int64_t)blockIdx.y * ss;
+  double *b = dst + (int64_t)blockIdx.y * sd;
+  const int64_t total = (int64_t)r * c;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / c), j = (int)(e % c);
+    b[(int64_t)j * r + i] = a[e];
+  }
+}
+
 __global__ void k_gather(const CJob *__restrict__ jobs, int which, int64_t off, double *__restrict__ dst,
                          int64_t sdst, int64_t count) {
   const CJob jb = jobs[blockIdx.y];
@@ -1139,6 +1073,140 @@ __global__ void k_ritz(const double *__restrict__ Mm, const double *__restrict__
 //   tri_eig    top-kk eigenpairs of T: bisection (Sturm counts) and inverse
 //              iteration with partial-pivoting tridiagonal LU
 //   ormtr      U^T = Z^T Q_H^T, blocked compact-WY application
+// ---------------------------------------------------------------------------
+// ormtr2: the same product U = Q_H Z as k_ormtr, for m <= 512.  Z is cut
+// into slabs of 64 columns, one workgroup (8 waves) per slab; wave w keeps
+// rows [64w, 64w + 64) of its slab in registers for the whole pass, as 4 x 4
+// MFMA blocks in the accumulator layout (lane l, register r <-> row
+// R0 + l/16 + 4r, column n0 + l%16).  Register r of such a block is also the
+// B operand of the 16x16x4 step over rows R0 + 4r .. R0 + 4r + 3, so each
+// block of 16 reflectors (last block first) costs
+//   W  = V Z        16 x 64, each wave over its 64 rows, summed in LDS
+//   X  = T W        T the forward compact-WY factor of the block
+//   Z -= V^T X      accumulated into the resident blocks
+// and Z is read once and written once (transposed, as rows of Ut).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(512) void k_ormtr2(const double *__restrict__ Ab, int64_t sA, int m,
+                                                const double *__restrict__ taub, int64_t sv,
+                                                const double *__restrict__ Zb, int64_t sZ, int kk,
+                                                double *__restrict__ Utb, int64_t sU, int nslab, int zout) {
+  constexpr int NB = 16, NWV = 8, CS = 64, VL = 516;
+  extern __shared__ double lds[];
+  double *V = lds;                   // NB x VL: row p = reflector i0 + p over rows 0..m-1
+  double *Wp = V + NB * VL;          // NWV x NB x CS partial products
+  double *Ws = Wp + NWV * NB * CS;   // NB x CS
+  double *Xs = Ws + NB * CS;         // NB x CS
+  double *T = Xs + NB * CS;          // NB x NB
+  double *G = T + NB * NB;           // NB x NB: v_q . v_p
+  double *tv = G + NB * NB;          // NB
+  const int job = blockIdx.x / nslab, slab = blockIdx.x % nslab;
+  const double *A = Ab + (int64_t)job * sA;
+  const double *tau = taub + (int64_t)job * sv;
+  const double *Z = Zb + (int64_t)job * sZ;
+  double *Ut = Utb + (int64_t)job * sU;
+  const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
+  const int li = lane % 16, lk = lane / 16;
+  const int c0 = slab * CS;
+
+  d4_t z[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 64 * wv + 16 * i + lk + 4 * r, col = c0 + 16 * j + li;
+        z[i][j][r] = (row < m && col < kk) ? Z[(int64_t)row * kk + col] : 0.0;
+      }
+
+  const int nref = m - 2;
+  const int nblk = nref > 0 ? (nref + NB - 1) / NB : 0;
+  for (int bi = nblk - 1; bi >= 0; --bi) {
+    const int i0 = bi * NB;
+    const int pb = (nref - i0) < NB ? (nref - i0) : NB;
+    // reflectors of the block: 16 consecutive columns of A per row (coalesced)
+    for (int e = tid; e < NB * 512; e += 512) {
+      const int r = e / NB, q = e % NB;
+      const int i = i0 + q;
+      double x = 0.0;
+      if (q < pb && r < m) {
+        if (r == i + 1) x = 1.0;
+        else if (r > i + 1) x = A[(int64_t)r * m + i];
+      }
+      V[q * VL + r] = x;
+    }
+    if (tid < NB) tv[tid] = (tid < pb) ? tau[i0 + tid] : 0.0;
+    __syncthreads();
+    if (tid < NB * NB) {
+      const int q = tid / NB, p = tid % NB;
+      double acc = 0.0;
+      if (q < p)
+        for (int r = i0 + p + 1; r < m; ++r) acc += V[q * VL + r] * V[p * VL + r];
+      G[tid] = acc;
+    }
+    // partial W = V Z over this wave's rows
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      d4_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc = mfma16(V[li * VL + 64 * wv + 16 * i + 4 * r + lk], z[i][j][r], acc);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Wp[(wv * NB + lk + 4 * r) * CS + 16 * j + li] = acc[r];
+    }
+    __syncthreads();
+    if (tid < NB) {
+      // T[0:p, p] = -tau_p T[0:p, 0:p] (V^T v_p)[0:p]; lane q owns row q of T
+      const int q = tid;
+      for (int p = 0; p < NB; ++p) {
+        double acc = 0.0;
+        for (int r = q; r < p; ++r) acc += T[q * NB + r] * G[r * NB + p];
+        if (q < p) T[q * NB + p] = -tv[p] * acc;
+        else if (q == p) T[q * NB + p] = tv[p];
+        else T[q * NB + p] = 0.0;
+      }
+    }
+    for (int e = tid; e < NB * CS; e += 512) {
+      double acc = 0.0;
+#pragma unroll
+      for (int w = 0; w < NWV; ++w) acc += Wp[w * NB * CS + e];
+      Ws[e] = acc;
+    }
+    __syncthreads();
+    for (int e = tid; e < NB * CS; e += 512) {
+      const int p = e / CS, c = e % CS;
+      double acc = 0.0;
+      for (int q = p; q < NB; ++q) acc += T[p * NB + q] * Ws[q * CS + c];
+      Xs[e] = acc;
+    }
+    __syncthreads();
+    // Z -= V^T X
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      double b[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Xs[(4 * s4 + lk) * CS + 16 * j + li];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double a = -V[(4 * s4 + lk) * VL + 64 * wv + 16 * i + li];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) z[i][j] = mfma16(a, b[j], z[i][j]);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 64 * wv + 16 * i + lk + 4 * r, col = c0 + 16 * j + li;
+        if (row < m && col < kk) Ut[zout ? (int64_t)row * kk + col : (int64_t)col * m + row] = z[i][j][r];
+      }
+}
+
 // ---------------------------------------------------------------------------
 
 // sytrd: one workgroup (1024 threads) per matrix.  A (m x m, row-major,
@@ -1518,99 +1586,7 @@ __global__ __launch_bounds__(256) void k_tri_eig(const double *__restrict__ db, 
   }
 }
 
-// ormtr: U = Q_H Z = H_0 H_1 ... H_{m-3} Z for Z (m x kk, row-major), the
-// reflectors v_i (v_i[i+1] = 1, v_i[r] = A[r][i] for r >= i+2) and tau_i left
-// by sytrd.  Blocks of NB reflectors are applied last block first as
-// Z <- Z - V (T (V^T Z)) with the forward compact-WY factor T.  The result
-// is written transposed: Ut (kk x m) row t = eigenvector t of G.
-// One workgroup per matrix, thread t owns column t of Z.  LDS: V (NB x m), T.
-template <int NB>
-__global__ __launch_bounds__(256) void k_ormtr(const double *__restrict__ Ab, int64_t sA, int m,
-                                               const double *__restrict__ taub, int64_t sv,
-                                               double *__restrict__ Zb, int64_t sZ, int kk,
-                                               double *__restrict__ Utb, int64_t sU) {
-  extern __shared__ double lds[];
-  double *V = lds;              // NB x m (row p = reflector i0 + p over rows 0..m-1)
-  double *T = V + NB * m;       // NB x NB
-  double *tv = T + NB * NB;     // NB taus
-  const double *A = Ab + (int64_t)blockIdx.x * sA;
-  const double *tau = taub + (int64_t)blockIdx.x * sv;
-  double *Z = Zb + (int64_t)blockIdx.x * sZ;
-  double *Ut = Utb + (int64_t)blockIdx.x * sU;
-  const int tid = threadIdx.x;
-  const int nref = m - 2;  // reflectors 0..m-3
-  const int nblk = nref > 0 ? (nref + NB - 1) / NB : 0;
-  for (int bi = nblk - 1; bi >= 0; --bi) {
-    const int i0 = bi * NB;
-    const int pb = (nref - i0) < NB ? (nref - i0) : NB;
-    for (int e = tid; e < NB * m; e += blockDim.x) {
-      const int p = e / m, r = e % m;
-      const int i = i0 + p;
-      double x = 0.0;
-      if (p < pb) {
-        if (r == i + 1) x = 1.0;
-        else if (r > i + 1) x = A[(int64_t)r * m + i];
-      }
-      V[e] = x;
-    }
-    if (tid < NB) tv[tid] = (tid < pb) ? tau[i0 + tid] : 0.0;
-    __syncthreads();
-    // Y = V^T V (NB x NB) in parallel, then the triangular recursion for T
-    for (int e = tid; e < NB * NB; e += blockDim.x) {
-      const int q = e / NB, p = e % NB;
-      double s = 0.0;
-      if (q < p)
-        for (int r = i0 + p + 1; r < m; ++r) s += V[q * m + r] * V[p * m + r];
-      T[e] = s;  // upper part holds V^T V temporarily
-    }
-    __syncthreads();
-    if (tid == 0) {
-      // T[0:p,p] = -tau_p T[0:p,0:p] (V^T v_p)[0:p], T[p][p] = tau_p
-      for (int p = 0; p < NB; ++p) {
-        double y[NB];
-        for (int q = 0; q < p; ++q) y[q] = T[q * NB + p];
-        for (int q = 0; q < p; ++q) {
-          double acc = 0.0;
-          for (int r2 = q; r2 < p; ++r2) acc += T[q * NB + r2] * y[r2];
-          T[q * NB + p] = -tv[p] * acc;
-        }
-        T[p * NB + p] = tv[p];
-        for (int q = p + 1; q < NB; ++q) T[q * NB + p] = 0.0;
-      }
-    }
-    __syncthreads();
-    for (int c = tid; c < kk; c += blockDim.x) {
-      double W[NB];
-#pragma unroll
-      for (int p = 0; p < NB; ++p) W[p] = 0.0;
-      for (int r = i0 + 1; r < m; ++r) {
-        const double z = Z[(int64_t)r * kk + c];
-#pragma unroll
-        for (int p = 0; p < NB; ++p) W[p] = fma(V[p * m + r], z, W[p]);
-      }
-      double X[NB];
-#pragma unroll
-      for (int p = 0; p < NB; ++p) {
-        double a = 0.0;
-#pragma unroll
-        for (int q = 0; q < NB; ++q) a += (q >= p) ? T[p * NB + q] * W[q] : 0.0;
-        X[p] = a;
-      }
-      for (int r = i0 + 1; r < m; ++r) {
-        double s = 0.0;
-#pragma unroll
-        for (int p = 0; p < NB; ++p) s = fma(V[p * m + r], X[p], s);
-        Z[(int64_t)r * kk + c] -= s;
-      }
-    }
-    __syncthreads();
-  }
-  // transposed write
-  for (int64_t e = tid; e < (int64_t)kk * m; e += blockDim.x) {
-    const int t = (int)(e / m), r = (int)(e % m);
-    Ut[e] = Z[(int64_t)r * kk + t];
-  }
-}
+
 
 // svd_finish2: C (kk x n) holds Qz Y.  Row norms s_t; cutoff relative to the
 // largest; rows with s_t <= cutoff * s_max are zeroed together with column t
@@ -1620,7 +1596,7 @@ __global__ __launch_bounds__(256) void k_svd_finish2(const double *__restrict__ 
                                                      double *__restrict__ Cb, int64_t sC, int n, double cutoff,
                                                      const double *__restrict__ db, int64_t sv,
                                                      double *__restrict__ Ub, int64_t sU,
-                                                     int *__restrict__ rank_out, double *__restrict__ disc_out) {
+                                                     int *__restrict__ rank_out, double *__restrict__ disc_out, int qt) {
   __shared__ double nr[1024];
   __shared__ int s_rank;
   __shared__ double s_keep2, s_smax;
@@ -1658,7 +1634,7 @@ __global__ __launch_bounds__(256) void k_svd_finish2(const double *__restrict__ 
   __syncthreads();
   for (int64_t e = tid; e < (int64_t)m * kk; e += blockDim.x) {
     const int row = (int)(e / kk), t = (int)(e % kk);
-    U[e] = (nr[t] >= 0.0) ? Q[(int64_t)t * m + row] : 0.0;
+    U[e] = (nr[t] >= 0.0) ? (qt ? Q[e] : Q[(int64_t)t * m + row]) : 0.0;
   }
   for (int64_t e = tid; e < (int64_t)kk * n; e += blockDim.x) {
     const int t = (int)(e / n);
@@ -1681,13 +1657,30 @@ void launch_construct(hipStream_t st, const CJob *jobs, int nb, int site, int n_
                      ra, lb, rb, out, out_stride, lo, ro);
 }
 
-void launch_gemm(hipStream_t st, int nb, bool transB, const double *A, int64_t sA, int lda, const double *B,
+template <int MODE>
+static void gemm_mode(hipStream_t st, int nb, const double *A, int64_t sA, int lda, const double *B, int64_t sB,
+                      int ldb, double *C, int64_t sC, int ldc, int M, int N, int K) {
+  if (M > 64 && N > 64) {
+    const int tm = (M + 127) / 128, tn = (N + 127) / 128;
+    hipLaunchKernelGGL((k_gemm_mfma<MODE, 128, 128>), dim3(nb * tm * tn), dim3(256), 0, st, A, sA, lda, B, sB, ldb,
+                       C, sC, ldc, M, N, K, tm, tn);
+  } else {
+    const int tm = (M + 63) / 64, tn = (N + 63) / 64;
+    hipLaunchKernelGGL((k_gemm_mfma<MODE, 64, 64>), dim3(nb * tm * tn), dim3(256), 0, st, A, sA, lda, B, sB, ldb,
+                       C, sC, ldc, M, N, K, tm, tn);
+  }
+}
+
+void launch_gemm(hipStream_t st, int nb, int mode, const double *A, int64_t sA, int lda, const double *B,
                  int64_t sB, int ldb, double *C, int64_t sC, int ldc, int M, int N, int K) {
-  dim3 grid(cdiv64(N, 64), cdiv64(M, 64), nb);
-  if (transB)
-    hipLaunchKernelGGL(k_gemm_f64<true>, grid, dim3(256), 0, st, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K);
-  else
-    hipLaunchKernelGGL(k_gemm_f64<false>, grid, dim3(256), 0, st, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K);
+  if (nb <= 0 || M <= 0 || N <= 0) return;
+  switch (mode) {
+    case 0: gemm_mode<0>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K); break;
+    case GEMM_TB: gemm_mode<GEMM_TB>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K); break;
+    case GEMM_TA: gemm_mode<GEMM_TA>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K); break;
+    case GEMM_ST2: gemm_mode<GEMM_ST2>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K); break;
+    default: break;
+  }
 }
 
 int lq_t_stride(int k) {
@@ -1695,38 +1688,29 @@ int lq_t_stride(int k) {
   return ((k + NB - 1) / NB) * (NB * NB + NB);  // covers both LQ kernels (k_lq2 uses NB*NB per panel)
 }
 
-int launch_lq(hipStream_t st, int nb, double *X, int64_t sX, int m, int n, double *L, int64_t sL, double *Q,
-              int64_t sQ, double *Tw, int64_t sT) {
-  if (n <= 1024) {
-    constexpr int NMAX = 1024, NWV = 8;
-    size_t lds = (16 * (NMAX + 1) + 256 + 256 + (NWV + 1) * 256 + 256 + 16) * sizeof(double);
-    static bool attr2 = false;
-    if (!attr2) {
-      (void)hipFuncSetAttribute((const void *)k_lq2<NMAX>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      attr2 = true;
-    }
-    hipLaunchKernelGGL((k_lq2<NMAX>), dim3(nb), dim3(512), lds, st, X, sX, m, n, L, sL, Q, sQ, Tw, sT);
-    return 0;
-  }
-  return -1;
+template <class K>
+static void set_lds(K kern, size_t lds) {
+  (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-int launch_lq_v1(hipStream_t st, int nb, double *X, int64_t sX, int m, int n, double *L, int64_t sL, double *Q,
-                 int64_t sQ, double *Tw, int64_t sT) {
-  constexpr int NB = 16;
-  if (n <= 1024) {
-    constexpr int NMAX = 1024;
-    size_t lds = (NB * NMAX + NB * NB + NB + 4) * sizeof(double);
-    static bool attr = false;
-    if (!attr) {
-      (void)hipFuncSetAttribute((const void *)k_lq<NB, NMAX>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      attr = true;
-    }
-    hipLaunchKernelGGL((k_lq<NB, NMAX>), dim3(nb), dim3(256), lds, st, X, sX, m, n, L, sL, Q, sQ, Tw, sT);
-    return 0;
+int launch_lq(hipStream_t st, int nb, double *X, int64_t sX, int m, int n, double *L, int64_t sL, double *Q,
+              int64_t sQ, double *Tw, int64_t sT, bool tr) {
+  if (n > 1024) return -1;
+  constexpr int NMAX = 1024, NWV = 8;
+  const size_t lds = (16 * (NMAX + 1) + 256 + 256 + (NWV + 1) * 256 + 256 + 16 + 256) * sizeof(double);
+  static bool attr[2] = {false, false};
+  if (!attr[tr]) {
+    if (tr) set_lds(k_lq2<NMAX, true>, lds);
+    else set_lds(k_lq2<NMAX, false>, lds);
+    attr[tr] = true;
   }
-  return -1;
+  if (tr)
+    hipLaunchKernelGGL((k_lq2<NMAX, true>), dim3(nb), dim3(512), lds, st, X, sX, m, n, L, sL, Q, sQ, Tw, sT);
+  else
+    hipLaunchKernelGGL((k_lq2<NMAX, false>), dim3(nb), dim3(512), lds, st, X, sX, m, n, L, sL, Q, sQ, Tw, sT);
+  return 0;
 }
+
 
 int launch_jacobi(hipStream_t st, int nb, double *Y, int64_t sY, int m, int n, double *s, int64_t ss,
                   int *sweeps, int max_sweeps) {
@@ -1773,6 +1757,13 @@ void launch_svd_finish(hipStream_t st, int nb, const double *Q, int64_t sQ, int 
   hipLaunchKernelGGL(k_svd_finish, dim3(gx, nb), dim3(256), 0, st, Q, sQ, m, kk, rank, U, sU, C, sC, n);
 }
 
+void launch_transpose(hipStream_t st, int nb, const double *src, int64_t ss, int r, int c, double *dst, int64_t sd) {
+  int gx = (int)cdiv64((int64_t)r * c, 256);
+  if (gx > 1024) gx = 1024;
+  if (gx < 1) gx = 1;
+  hipLaunchKernelGGL(k_transpose, dim3(gx, nb), dim3(256), 0, st, src, ss, r, c, dst, sd);
+}
+
 void launch_copy(hipStream_t st, int nb, const double *src, int64_t ssrc, double *dst, int64_t sdst, int64_t count) {
   int gx = cdiv64(count, 256);
   if (gx > 2048) gx = 2048;
@@ -1814,10 +1805,6 @@ void launch_scale(hipStream_t st, double *p, int64_t count, double c) {
   hipLaunchKernelGGL(k_scale_range, dim3(gx), dim3(256), 0, st, p, count, c);
 }
 
-template <class K>
-static void set_lds(K kern, size_t lds) {
-  (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-}
 
 int launch_sytrd(hipStream_t st, int nb, double *A, int64_t sA, int m, double *d, double *e, double *tau, int64_t sv) {
   if (m > 512) return -1;
@@ -1837,21 +1824,23 @@ int launch_tri_eig(hipStream_t st, int nb, const double *d, const double *e, int
 }
 
 int launch_ormtr(hipStream_t st, int nb, const double *A, int64_t sA, int m, const double *tau, int64_t sv, double *Z,
-                 int64_t sZ, int kk, double *Ut, int64_t sU) {
-  constexpr int NB = 16;
-  if (m > 1024) return -1;
-  size_t lds = ((size_t)NB * m + NB * NB + NB) * sizeof(double);
+                 int64_t sZ, int kk, double *Ut, int64_t sU, bool zout) {
+  if (m > 512) return -1;
+  const size_t lds = (16 * 516 + 8 * 16 * 64 + 2 * 16 * 64 + 2 * 256 + 16) * sizeof(double);
   static bool attr = false;
-  if (!attr) { set_lds(k_ormtr<NB>, (NB * 1024 + NB * NB + NB) * sizeof(double)); attr = true; }
-  hipLaunchKernelGGL(k_ormtr<NB>, dim3(nb), dim3(256), lds, st, A, sA, m, tau, sv, Z, sZ, kk, Ut, sU);
+  if (!attr) { set_lds(k_ormtr2, lds); attr = true; }
+  const int nslab = (kk + 63) / 64;
+  if (nslab == 0) return 0;
+  hipLaunchKernelGGL(k_ormtr2, dim3(nb * nslab), dim3(512), lds, st, A, sA, m, tau, sv, Z, sZ, kk, Ut, sU, nslab,
+                     zout ? 1 : 0);
   return 0;
 }
 
 void launch_svd_finish2(hipStream_t st, int nb, const double *Q, int64_t sQ, int m, int kk, double *C, int64_t sC,
                         int n, double cutoff, const double *d, int64_t sv, double *U, int64_t sU, int *rank,
-                        double *disc) {
+                        double *disc, bool qt) {
   hipLaunchKernelGGL(k_svd_finish2, dim3(nb), dim3(256), 0, st, Q, sQ, m, kk, C, sC, n, cutoff, d, sv, U, sU, rank,
-                     disc);
+                     disc, qt ? 1 : 0);
 }
 
 int64_t tri_eig_scratch(int m, int kk) { return 4 * (int64_t)m * kk + ((int64_t)m * kk + 1) / 2 + 8; }
