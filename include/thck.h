@@ -86,6 +86,23 @@ typedef struct {
  * Jacobi on Y itself (high relative accuracy, slower). */
 #define THC_FLAG_SVD_JACOBI 1ull
 
+/* opts.flags: record a pair of HIP events (on the call's stream) around each
+ * launch of the compression kernels and return, per kernel class, the summed
+ * device time, the launch count and the algorithmic flops of those launches
+ * (LAPACK operation counts: LQ with thin Q 4nk^2 - 4k^3/3 for an m x n matrix,
+ * k = min(m, n), n >= m; tridiagonalisation 4m^3/3; back-transformation
+ * 2m^2 k; GEMM 2MNK) in thc_stats.kernel_*.  Off by default. */
+#define THC_FLAG_TIME_KERNELS 2ull
+
+enum {
+  THC_K_LQ = 0,      /* Householder LQ with Q formation (canonical sweep and re-orthonormalisation) */
+  THC_K_SYTRD = 1,   /* tridiagonalisation of the Gram matrix */
+  THC_K_TRI_EIG = 2, /* bisection + inverse iteration */
+  THC_K_ORMTR = 3,   /* back-transformation of the eigenvectors */
+  THC_K_GEMM = 4,    /* batched GEMMs of the compression */
+  THC_NK = 5
+};
+
 typedef struct {
   double discarded_weight_max; /* max over compressions and bonds of sum_{i>k} s_i^2 */
   double flops_model;          /* algorithmic flops (LAPACK-formula model) of the call */
@@ -95,6 +112,9 @@ typedef struct {
   int32_t jacobi_sweeps_max;   /* most Jacobi sweeps any SVD needed */
   int32_t nonconverged;        /* SVDs that hit the sweep limit */
   int32_t reserved;
+  double kernel_ms[THC_NK];        /* THC_FLAG_TIME_KERNELS: summed device time per kernel class */
+  double kernel_flops[THC_NK];     /* algorithmic flops of those launches */
+  int64_t kernel_launches[THC_NK];
 } thc_stats;
 
 typedef struct thc_ctx thc_ctx;

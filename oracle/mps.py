@@ -41,7 +41,9 @@ def overlap(a, b) -> float:
     """<a|b> by the left transfer-matrix chain E_j = sum_n A^nT E_{j-1} B^n."""
     E = np.ones((1, 1))
     for x, y in zip(a, b):
-        E = np.einsum("ab,anc,bnd->cd", E, x, y)
+        # E'_cd = sum_{a,n,b} E_ab x_anc y_bnd, contracted in two steps
+        F = np.einsum("ab,anc->bnc", E, x)
+        E = np.einsum("bnc,bnd->cd", F, y)
     return float(E[0, 0])
 
 

@@ -13,7 +13,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdint>
 #include <cstring>
+#include <chrono>
 #include <map>
 #include <memory>
 #include <string>
@@ -316,6 +318,53 @@ struct CallStats {
   int64_t compressions = 0;
   int64_t launches = 0;
   double flops = 0.0;
+  double kms[THC_NK] = {};
+  double kflops[THC_NK] = {};
+  int64_t kn[THC_NK] = {};
+};
+
+// Event pairs around kernel launches (THC_FLAG_TIME_KERNELS): recorded on
+// the compression stream, resolved after the batch's synchronisation.
+struct KernelTimer {
+  struct Rec {
+    hipEvent_t a, b;
+    int cls;
+    double flops;
+  };
+  std::vector<hipEvent_t> pool;
+  std::vector<Rec> pending;
+  size_t used = 0;
+  ~KernelTimer() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+  hipEvent_t get() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  template <class F>
+  void run(hipStream_t st, int cls, double flops, F &&launch) {
+    Rec r{get(), get(), cls, flops};
+    HIPCHK(hipEventRecord(r.a, st));
+    launch();
+    HIPCHK(hipEventRecord(r.b, st));
+    pending.push_back(r);
+  }
+  // call after the stream has been synchronised
+  void resolve(CallStats &cs) {
+    for (const Rec &r : pending) {
+      float ms = 0.0f;
+      HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+      cs.kms[r.cls] += ms;
+      cs.kflops[r.cls] += r.flops;
+      cs.kn[r.cls] += 1;
+    }
+    pending.clear();
+    used = 0;
+  }
 };
 
 struct Engine {
@@ -329,7 +378,46 @@ struct Engine {
   std::vector<double> h_disc;
   std::vector<int> h_sw;
   // pending stats readbacks are done synchronously per batch only in debug
-  Engine(thc_ctx *c_, hipStream_t s_, const thc_opts &o_) : c(c_), st(s_), o(o_) {}
+  KernelTimer kt;
+  bool timing = false;
+  Engine(thc_ctx *c_, hipStream_t s_, const thc_opts &o_)
+      : c(c_), st(s_), o(o_), timing((o_.flags & THC_FLAG_TIME_KERNELS) != 0) {}
+  // launch through the timer when kernel timing is on
+  template <class F>
+  void timed(int cls, double flops, F &&launch) {
+    if (timing) kt.run(st, cls, flops, launch);
+    else launch();
+  }
+  // launchers of the timed kernel classes, with their algorithmic flops
+  void gemm(int nb, int mode, const double *A, int64_t sA, int lda, const double *B, int64_t sB, int ldb, double *C,
+            int64_t sC, int ldc, int M, int N, int K) {
+    timed(THC_K_GEMM, 2.0 * M * N * (double)K * nb,
+          [&] { launch_gemm(st, nb, mode, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K); });
+  }
+  int lq(int nb, double *X, int64_t sX, int m, int n, double *L, int64_t sL, double *Q, int64_t sQ, double *T,
+         int64_t sT, bool tr = false) {
+    int rc = 0;
+    timed(THC_K_LQ, lq_flops(m, n) * nb, [&] { rc = launch_lq(st, nb, X, sX, m, n, L, sL, Q, sQ, T, sT, tr); });
+    return rc;
+  }
+  int sytrd(int nb, double *A, int64_t sA, int m, double *d, double *e, double *tau, int64_t sv) {
+    int rc = 0;
+    timed(THC_K_SYTRD, 4.0 / 3.0 * m * (double)m * m * nb, [&] { rc = launch_sytrd(st, nb, A, sA, m, d, e, tau, sv); });
+    return rc;
+  }
+  int tri_eig(int nb, const double *d, const double *e, int64_t sv, int m, int kk, double *Z, int64_t sZ, double *lam,
+              int64_t sl, double *scr, int64_t sscr) {
+    int rc = 0;
+    timed(THC_K_TRI_EIG, 0.0, [&] { rc = launch_tri_eig(st, nb, d, e, sv, m, kk, Z, sZ, lam, sl, scr, sscr); });
+    return rc;
+  }
+  int ormtr(int nb, const double *A, int64_t sA, int m, const double *tau, int64_t sv, double *Z, int64_t sZ, int kk,
+            double *Ut, int64_t sU, bool zout) {
+    int rc = 0;
+    timed(THC_K_ORMTR, 2.0 * m * (double)m * kk * nb,
+          [&] { rc = launch_ormtr(st, nb, A, sA, m, tau, sv, Z, sZ, kk, Ut, sU, zout); });
+    return rc;
+  }
 
   int max_sweeps() const { return o.max_sweeps > 0 ? o.max_sweeps : 40; }
   double cutoff() const { return o.rel_cutoff > 0 ? o.rel_cutoff : 0.0; }
@@ -385,11 +473,11 @@ struct Engine {
       if (j == n - 1) {
         launch_transpose(st, nb, Bb, S, P.bo[j], 2, Tb, S);
       } else {
-        launch_gemm(st, nb, GEMM_ST2, Bb, S, P.bo[j + 1], Lb, S, P.c[j + 1], Tb, S, P.bo[j], P.bo[j] * 2, P.c[j + 1],
+        gemm(nb, GEMM_ST2, Bb, S, P.bo[j + 1], Lb, S, P.c[j + 1], Tb, S, P.bo[j], P.bo[j] * 2, P.c[j + 1],
                     P.bo[j + 1]);
       }
       ++launches;
-      if (launch_lq(st, nb, Tb, S, P.bo[j], 2 * P.c[j + 1], Lb, S, Qs + P.qs_off[j], S, Tf, S, true) != 0)
+      if (lq(nb, Tb, S, P.bo[j], 2 * P.c[j + 1], Lb, S, Qs + P.qs_off[j], S, Tf, S, true) != 0)
         raise(THC_EINVAL, "site matrix too wide for the LQ kernel (2*bond > 1024)");
     }
     // site 0: M_0 = B_0 * L_1 (1, 2, c_1)
@@ -399,7 +487,7 @@ struct Engine {
       launch_construct(st, dj, nb, 0, n, P.pa.off[0], P.kind ? P.pb.off[0] : 0, la, ra, lb, rb, Bb, S, P.bo[0],
                        P.bo[1]);
       if (n > 1)
-        launch_gemm(st, nb, 0, Bb, S, P.bo[1], Lb, S, P.c[1], Mb, S, P.c[1], 2, P.c[1], P.bo[1]);
+        gemm(nb, 0, Bb, S, P.bo[1], Lb, S, P.c[1], Mb, S, P.c[1], 2, P.c[1], P.bo[1]);
       else
         launch_copy(st, nb, Bb, S, Mb, S, 2);
       launches += 2;
@@ -414,23 +502,23 @@ struct Engine {
     for (int j = 0; j + 1 < n && !jacobi; ++j) {
       const int m = 2 * P.k[j], nc = P.c[j + 1], kk = P.k[j + 1];
       // Gram G = Y Y^T, Y = M_j (m x nc)
-      launch_gemm(st, nb, GEMM_TB, Mb, S, nc, Mb, S, nc, Gb, S, m, m, m, nc);
-      if (launch_sytrd(st, nb, Gb, S, m, Db, Eb, Taub, S) != 0) raise(THC_EINVAL, "site matrix too tall for sytrd");
-      if (launch_tri_eig(st, nb, Db, Eb, S, m, kk, Zm, S, Lam, S, Scr, S) != 0)
+      gemm(nb, GEMM_TB, Mb, S, nc, Mb, S, nc, Gb, S, m, m, m, nc);
+      if (sytrd(nb, Gb, S, m, Db, Eb, Taub, S) != 0) raise(THC_EINVAL, "site matrix too tall for sytrd");
+      if (tri_eig(nb, Db, Eb, S, m, kk, Zm, S, Lam, S, Scr, S) != 0)
         raise(THC_EINVAL, "site matrix too tall for the tridiagonal eigensolver");
       // eigenvectors as the columns of Z (m x kk)
-      if (launch_ormtr(st, nb, Gb, S, m, Taub, S, Zm, S, kk, Zb, S, true) != 0) raise(THC_EINVAL, "ormtr size");
+      if (ormtr(nb, Gb, S, m, Taub, S, Zm, S, kk, Zb, S, true) != 0) raise(THC_EINVAL, "ormtr size");
       // orthonormal rows spanning the top-kk eigenvectors: LQ of Z^T, given
       // transposed; Qz holds Q^T (m x kk)
-      if (launch_lq(st, nb, Zb, S, kk, m, Lz, S, Qz, S, Tf, S, true) != 0)
+      if (lq(nb, Zb, S, kk, m, Lz, S, Qz, S, Tf, S, true) != 0)
         raise(THC_EINVAL, "site matrix too wide for the LQ kernel");
       // C = Q (kk x m) * M (m x nc)
-      launch_gemm(st, nb, GEMM_TA, Qz, S, kk, Mb, S, nc, Cb, S, nc, kk, nc, m);
+      gemm(nb, GEMM_TA, Qz, S, kk, Mb, S, nc, Cb, S, nc, kk, nc, m);
       launch_svd_finish2(st, nb, Qz, S, m, kk, Cb, S, nc, cutoff(), Db, S, Ub, S, rk_d + (size_t)j * nb,
                          dw_d + (size_t)j * nb, true);
       launch_scatter(st, nb, dj, P.out.off[j], Ub, S, (int64_t)m * kk);
       // M_{j+1} = C (kk x c_{j+1}) * Q_{j+1} (Q_{j+1} stored transposed)
-      launch_gemm(st, nb, GEMM_TB, Cb, S, nc, Qs + P.qs_off[j + 1], S, nc, Mb, S, 2 * P.c[j + 2], kk, 2 * P.c[j + 2],
+      gemm(nb, GEMM_TB, Cb, S, nc, Qs + P.qs_off[j + 1], S, nc, Mb, S, 2 * P.c[j + 2], kk, 2 * P.c[j + 2],
                   nc);
       launches += 10;
     }
@@ -443,15 +531,15 @@ struct Engine {
       launch_svd_select(st, nb, Yb, S, m, nc, Sb, S, kk, cutoff(), Wb, S, rk_d + (size_t)j * nb,
                         dw_d + (size_t)j * nb, nullptr, 0);
       // Z = W (kk x nc) * M^T (nc x m)
-      launch_gemm(st, nb, GEMM_TB, Wb, S, nc, Mb, S, nc, Zb, S, m, kk, m, nc);
-      if (launch_lq(st, nb, Zb, S, kk, m, Lz, S, Qz, S, Tf, S) != 0)
+      gemm(nb, GEMM_TB, Wb, S, nc, Mb, S, nc, Zb, S, m, kk, m, nc);
+      if (lq(nb, Zb, S, kk, m, Lz, S, Qz, S, Tf, S) != 0)
         raise(THC_EINVAL, "site matrix too wide for the LQ kernel");
       // C = Qz (kk x m) * M (m x nc)
-      launch_gemm(st, nb, 0, Qz, S, m, Mb, S, nc, Cb, S, nc, kk, nc, m);
+      gemm(nb, 0, Qz, S, m, Mb, S, nc, Cb, S, nc, kk, nc, m);
       launch_svd_finish(st, nb, Qz, S, m, kk, rk_d + (size_t)j * nb, Ub, S, Cb, S, nc);
       launch_scatter(st, nb, dj, P.out.off[j], Ub, S, (int64_t)m * kk);
       // M_{j+1} = C (kk x c_{j+1}) * Q_{j+1} (Q_{j+1} stored transposed)
-      launch_gemm(st, nb, GEMM_TB, Cb, S, nc, Qs + P.qs_off[j + 1], S, nc, Mb, S, 2 * P.c[j + 2], kk, 2 * P.c[j + 2],
+      gemm(nb, GEMM_TB, Cb, S, nc, Qs + P.qs_off[j + 1], S, nc, Mb, S, 2 * P.c[j + 2], kk, 2 * P.c[j + 2],
                   nc);
       launches += 9;
     }
@@ -467,6 +555,8 @@ struct Engine {
     HIPCHK(hipMemcpyAsync(h_disc.data(), dw_d, (size_t)nb * (n - 1) * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(h_sw.data(), sw_d, (size_t)nb * (n - 1) * sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    if (timing) kt.resolve(cs);
+    report_progress(nb);
     for (size_t i = 0; i < (size_t)nb * (n - 1); ++i) {
       cs.disc_max = std::max(cs.disc_max, h_disc[i]);
       cs.max_bond = std::max(cs.max_bond, h_rank[i]);
@@ -480,6 +570,26 @@ struct Engine {
     cs.compressions += nb;
     cs.launches += launches;
     cs.flops += P.flops_per_job * nb;
+  }
+  // THCK_PROGRESS=1: a line on stderr after a compression batch, at most
+  // every 30 s, so that long calls show that they advance
+  void report_progress(int nb) {
+    static const bool on = [] {
+      const char *e = getenv("THCK_PROGRESS");
+      return e && *e && *e != '0';
+    }();
+    if (!on) return;
+    using clk = std::chrono::steady_clock;
+    static clk::time_point t0 = clk::now(), last = t0;
+    static int64_t done = 0;
+    done += nb;
+    const clk::time_point now = clk::now();
+    if (std::chrono::duration<double>(now - last).count() >= 30.0) {
+      last = now;
+      fprintf(stderr, "[thck] %lld compressions done, %.0f s since the first\n", (long long)done,
+              std::chrono::duration<double>(now - t0).count());
+      fflush(stderr);
+    }
   }
   // debugging aid: append every job of the batch (inputs, metadata, output) to a file
   void trace_batch(const char *path, const Plan &P, const std::vector<CJob> &hj) {
@@ -523,9 +633,12 @@ struct Engine {
 
   int batch_limit(const Plan &P) {
     if (o.batch > 0) return o.batch;
-    // keep the batch workspace under ~48 GiB
-    const double budget = 48.0 * (1ull << 30);
+    // keep the batch workspace under ~96 GiB; the big kernels run one
+    // workgroup per job on one CU each, so a batch of 256 or 512 fills the
+    // 256 CUs evenly, while e.g. 300 would leave a nearly empty second round
+    const double budget = 96.0 * (1ull << 30);
     int b = (int)std::max(1.0, std::min(512.0, budget / (P.per_job * 8.0)));
+    if (b >= 256) b = b / 256 * 256;
     return b;
   }
 };
@@ -693,13 +806,15 @@ struct Reducer {
     for (auto &q : levels) r += q.size();
     return r;
   }
-  // one batch: every pair that is ready now
-  void step() {
+  // one batch: the ready pairs, lowest level first, at most max_pairs
+  void step(size_t max_pairs = SIZE_MAX) {
     std::vector<JobSpec> specs;
     std::vector<std::pair<size_t, size_t>> where;  // (level, pair index)
     std::vector<std::vector<Node>> taken(levels.size());
+    size_t budget = max_pairs;
     for (size_t l = 0; l < levels.size(); ++l) {
-      size_t np = levels[l].size() / 2;
+      size_t np = std::min(levels[l].size() / 2, budget);
+      budget -= np;
       taken[l].assign(levels[l].begin(), levels[l].begin() + 2 * np);
       levels[l].erase(levels[l].begin(), levels[l].begin() + 2 * np);
     }
@@ -717,7 +832,8 @@ struct Reducer {
     for (size_t i = 0; i < res.size(); ++i) levels[where[i].first + 1].push_back(res[i]);
   }
   void flush(size_t min_pairs) {
-    while (ready_pairs() >= std::max<size_t>(1, min_pairs)) step();
+    const size_t b = std::max<size_t>(1, min_pairs);
+    while (ready_pairs() >= b) step(b);
   }
   Node finish() {
     for (;;) {
@@ -782,6 +898,11 @@ void fill_stats(thc_stats *st, const CallStats &cs) {
   st->max_bond = cs.max_bond;
   st->jacobi_sweeps_max = cs.sweeps_max;
   st->nonconverged = cs.nonconv;
+  for (int k = 0; k < THC_NK; ++k) {
+    st->kernel_ms[k] = cs.kms[k];
+    st->kernel_flops[k] = cs.kflops[k];
+    st->kernel_launches[k] = cs.kn[k];
+  }
   st->reserved = 0;
 }
 
@@ -884,8 +1005,8 @@ Node apply_H_nodes(Engine &E, const Node &psi, int D, int D_sum) {
     std::vector<Node> a2 = run_jobs(E, s2, D);
     for (auto &nd : a1) release(c, nd);
     for (auto &nd : a2) red.push(nd);
-    // batch the ready sums once half a batch is available (or the queues grow long)
-    red.flush(std::max<size_t>(1, std::min<size_t>(B / 2, red.queued() > (size_t)(4 * B) ? 1 : B / 2)));
+    // batch the ready sums once a full batch of pairs is available
+    red.flush(std::max<size_t>(1, (size_t)B));
   }
   Node root = red.finish();
   for (auto &nd : prefix) release(c, nd);
@@ -1355,6 +1476,11 @@ thc_status krylov_step(thc_krylov *k, double *ritz_gen, double *ritz_tri, double
       st->max_bond = std::max(s1.max_bond, s2.max_bond);
       st->jacobi_sweeps_max = std::max(s1.jacobi_sweeps_max, s2.jacobi_sweeps_max);
       st->nonconverged = s1.nonconverged + s2.nonconverged;
+      for (int q = 0; q < THC_NK; ++q) {
+        st->kernel_ms[q] = s1.kernel_ms[q] + s2.kernel_ms[q];
+        st->kernel_flops[q] = s1.kernel_flops[q] + s2.kernel_flops[q];
+        st->kernel_launches[q] = s1.kernel_launches[q] + s2.kernel_launches[q];
+      }
     }
   });
 }

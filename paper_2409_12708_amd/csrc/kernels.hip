@@ -22,10 +22,26 @@ namespace thck {
 
 static constexpr int WAVE = 64;
 
+// Wave-wide reductions (all 64 lanes active; the result is returned in every
+// lane).  Within each row of 16 lanes, an inclusive scan by DPP row shifts of
+// 1, 2, 4, 8 (zeros shifted in) leaves the row total in lane 15 of the row;
+// the four row totals are then read with readlane.
+template <int CTRL>
+__device__ __forceinline__ double dpp_shift(double v, double fill) {
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(fill), __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(fill), __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double read_lane(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
-  return v;
+  v += dpp_shift<0x111>(v, 0.0);  // row_shr:1
+  v += dpp_shift<0x112>(v, 0.0);  // row_shr:2
+  v += dpp_shift<0x114>(v, 0.0);  // row_shr:4
+  v += dpp_shift<0x118>(v, 0.0);  // row_shr:8
+  return (read_lane(v, 15) + read_lane(v, 31)) + (read_lane(v, 47) + read_lane(v, 63));
 }
 
 // Round-robin (circle method) schedule over P players (P even): in round r
@@ -40,9 +56,12 @@ __device__ __forceinline__ void rr_pair(int k, int r, int P, int &p, int &q) {
 }
 
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int off = WAVE / 2; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, WAVE));
-  return v;
+  // lanes shifted in from outside the row take the lane's own value
+  v = fmax(v, dpp_shift<0x111>(v, v));
+  v = fmax(v, dpp_shift<0x112>(v, v));
+  v = fmax(v, dpp_shift<0x114>(v, v));
+  v = fmax(v, dpp_shift<0x118>(v, v));
+  return fmax(fmax(read_lane(v, 15), read_lane(v, 31)), fmax(read_lane(v, 47), read_lane(v, 63)));
 }
 
 // ---------------------------------------------------------------------------
@@ -272,23 +291,32 @@ __device__ __forceinline__ void block_reflect_rows(double *__restrict__ X, int l
   const int ce = min(w, cb + chunk);
   const int li = lane % 16, lk = lane / 16;
   const int S = (ce > cb) ? (ce - cb + 3) / 4 : 0;
-  for (int rt = r_begin; rt < r_end; rt += 16) {
-    // this wave's 16 x chunk tile in registers: xa[s] = X[rt+li][cb+4s+lk]
+  // this wave's 16 x chunk tile in registers: xa[s] = X[rt+li][cb+4s+lk];
+  // element (row, c0 + kc): row-major X[row * ldx + c0 + kc], or with TR
+  // (X stored transposed) X[(c0 + kc) * ldx + row]; 16 lanes then read 16
+  // consecutive doubles.  The next tile is loaded while this one is reduced
+  // and updated.
+  const int so = 8 * (TR ? 4 * ldx : 4);
+  auto load_tile = [&](int rt, double (&dst)[SMAX]) {
     const int row = rt + li;
     const bool rok = row < r_end;
-    // element (row, c0 + kc): row-major X[row * ldx + c0 + kc], or with TR
-    // (X stored transposed) X[(c0 + kc) * ldx + row]; 16 lanes then read 16
-    // consecutive doubles
     const int vo = 8 * (TR ? (c0 + cb + lk) * ldx + row : row * ldx + c0 + cb + lk);
-    const int so = 8 * (TR ? 4 * ldx : 4);
-    double xa[SMAX];
 #pragma unroll
     for (int s = 0; s < SMAX; ++s) {
       const int kc = cb + 4 * s + lk;
       double x = 0.0;
       if (s < S) x = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, vo, s * so, 0));
-      xa[s] = (rok && kc < ce) ? x : 0.0;
+      dst[s] = (rok && kc < ce) ? x : 0.0;
     }
+  };
+  double xa[SMAX], xn[SMAX];
+  if (r_begin < r_end) load_tile(r_begin, xn);
+  for (int rt = r_begin; rt < r_end; rt += 16) {
+    const int row = rt + li;
+    const bool rok = row < r_end;
+    const int vo = 8 * (TR ? (c0 + cb + lk) * ldx + row : row * ldx + c0 + cb + lk);
+#pragma unroll
+    for (int s = 0; s < SMAX; ++s) xa[s] = xn[s];
     // partial W = X V^T over this wave's columns
     d4_t acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -301,6 +329,7 @@ __device__ __forceinline__ void block_reflect_rows(double *__restrict__ X, int l
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) Wp[wv * 256 + (lk + 4 * r) * 16 + li] = acc[r];
+    if (rt + 16 < r_end) load_tile(rt + 16, xn);
     __syncthreads();
     if (tid < 256) {
       const int i = tid / 16, p = tid % 16;
@@ -344,8 +373,10 @@ __device__ __forceinline__ void block_reflect_rows(double *__restrict__ X, int l
       if (s < S && rok && kc < ce)
         __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2_t, xa[s]), rs, vo, s * so, 0);
     }
-    __syncthreads();
+    // no barrier here: the next tile writes Wp / WT only after barriers that
+    // every reader of this tile's values has passed
   }
+  __syncthreads();
 }
 
 // lq2: X (m x n) = L Q by blocked Householder (panels of 16 rows, compact WY),
@@ -1074,7 +1105,8 @@ __global__ void k_ritz(const double *__restrict__ Mm, const double *__restrict__
 //              iteration with partial-pivoting tridiagonal LU
 //   ormtr      U^T = Z^T Q_H^T, blocked compact-WY application
 // ---------------------------------------------------------------------------
-// ormtr2: the same product U = Q_H Z as k_ormtr, for m <= 512.  Z is cut
+// ormtr2: U = Q_H Z = H_0 H_1 ... H_{m-3} Z for the reflectors left by
+// sytrd2 (v_i[i+1] = 1, v_i[r] = A[i][r] for r >= i+2) and m <= 512.  Z is cut
 // into slabs of 64 columns, one workgroup (8 waves) per slab; wave w keeps
 // rows [64w, 64w + 64) of its slab in registers for the whole pass, as 4 x 4
 // MFMA blocks in the accumulator layout (lane l, register r <-> row
@@ -1126,12 +1158,12 @@ __global__ __launch_bounds__(512) void k_ormtr2(const double *__restrict__ Ab, i
     const int pb = (nref - i0) < NB ? (nref - i0) : NB;
     // reflectors of the block: 16 consecutive columns of A per row (coalesced)
     for (int e = tid; e < NB * 512; e += 512) {
-      const int r = e / NB, q = e % NB;
+      const int q = e / 512, r = e % 512;
       const int i = i0 + q;
       double x = 0.0;
       if (q < pb && r < m) {
         if (r == i + 1) x = 1.0;
-        else if (r > i + 1) x = A[(int64_t)r * m + i];
+        else if (r > i + 1) x = A[(int64_t)i * m + r];
       }
       V[q * VL + r] = x;
     }
@@ -1208,176 +1240,268 @@ __global__ __launch_bounds__(512) void k_ormtr2(const double *__restrict__ Ab, i
 }
 
 // ---------------------------------------------------------------------------
-
-// sytrd: one workgroup (1024 threads) per matrix.  A (m x m, row-major,
-// symmetric) is read and written in its lower triangle only.  Step i:
-// (a) apply the pending rank-2 update (v_{i-1}, w_{i-1}) to column i,
-// (b) reflector v_i from column i below the diagonal (v_i[i+1] = 1, the
-//     rest stored in A[i+2:, i]), d_i = A[i][i], e_i = beta, tau_i,
-// (c) one pass over the trailing lower triangle that applies the pending
-//     update and accumulates p = A22 v_i (each stored entry feeds p_r and
-//     p_c), (d) w_i = tau p - (tau^2/2 (p.v)) v  (LAPACK dsytd2 'L').
+// sytrd2: Householder tridiagonalisation of a symmetric A (m <= MMAX), the
+// blocked scheme of LAPACK dsytrd/dlatrd.  Panels of NB reflectors: inside
+// a panel the trailing matrix is only read, y = A22 v corrected by the
+// panel's earlier reflectors (y -= V (W^T v) + W (V^T v)); after the panel
+// it is updated once, A22 -= V W^T + W V^T.  The kernel reads and writes the
+// upper triangle (row c, columns r >= c): the part of column i below the
+// diagonal is then the contiguous row i.  One workgroup (512 threads) per
+// matrix.  Outputs: d (m), e (m-1), tau (m-1); reflector i is
+// v_i = e_{i+1} + tail with the tail stored in A[i][i+2:].
+// ---------------------------------------------------------------------------
 template <int MMAX>
-__global__ __launch_bounds__(1024) void k_sytrd(double *__restrict__ Ab, int64_t sA, int m,
-                                                double *__restrict__ db, double *__restrict__ eb,
-                                                double *__restrict__ taub, int64_t sv) {
-  constexpr int NW = 16, CPL = MMAX / WAVE;  // columns per lane
+__global__ __launch_bounds__(512) void k_sytrd2(double *__restrict__ Ab, int64_t sA, int m,
+                                                 double *__restrict__ db, double *__restrict__ eb,
+                                                 double *__restrict__ taub, int64_t sv) {
+  constexpr int NB = 8, NT = 512, NW = NT / WAVE, CPL = MMAX / WAVE, RU = 4;
   extern __shared__ double lds[];
-  double *v = lds;              // MMAX
-  double *vp = v + MMAX;        // MMAX pending v
-  double *w = vp + MMAX;        // MMAX pending w
-  double *prow = w + MMAX;      // MMAX
-  double *pp = prow + MMAX;     // NW x MMAX column partials
-  double *red = pp + NW * MMAX; // 64
+  double *VL = lds;                 // NB x MMAX reflectors of the panel
+  double *WL = VL + NB * MMAX;      // NB x MMAX
+  double *x = WL + NB * MMAX;       // updated column i, then v
+  double *y = x + MMAX;
+  double *prow = y + MMAX;          // row sums of the symmetric product
+  double *pp = prow + MMAX;         // NW x MMAX column partials
+  double *red = pp + NW * MMAX;     // reductions: 2 NW + 2 NB
+  __shared__ double s_tau, s_sc, s_alpha;
+  __shared__ int s_slow;
   double *A = Ab + (int64_t)blockIdx.x * sA;
   double *d = db + (int64_t)blockIdx.x * sv;
   double *e = eb + (int64_t)blockIdx.x * sv;
   double *tau = taub + (int64_t)blockIdx.x * sv;
   const int tid = threadIdx.x, lane = tid % WAVE, wid = tid / WAVE;
-  __shared__ int s_pending;
-  __shared__ double s_tau, s_beta;
-  if (tid == 0) s_pending = 0;
-  for (int r = tid; r < MMAX; r += blockDim.x) { vp[r] = 0.0; w[r] = 0.0; }
-  __syncthreads();
-  for (int i = 0; i + 2 < m; ++i) {
-    const int pend = s_pending;
-    // (a) column i, rows i..m-1
-    if (pend) {
-      const double vpi = vp[i], wi = w[i];
-      for (int r = i + tid; r < m; r += blockDim.x) A[(int64_t)r * m + i] -= vp[r] * wi + w[r] * vpi;
-    }
-    __syncthreads();
-    // (b) reflector from x = A[i+1:, i], norm taken on the scaled column
-    {
-      double amax = 0.0;
-      for (int r = i + 2 + tid; r < m; r += blockDim.x) amax = fmax(amax, fabs(A[(int64_t)r * m + i]));
-      amax = wave_max(amax);
-      if (lane == 0) red[32 + wid] = amax;
-      __syncthreads();
-      double am = 0.0;
-      for (int q = 0; q < NW; ++q) am = fmax(am, red[32 + q]);
-      const double alpha0 = A[(int64_t)(i + 1) * m + i];
-      const double scl = fmax(am, fabs(alpha0));
-      if (!(am > 1e-290)) am = 0.0;  // only denormal dust below the subdiagonal: no reflection
-      const double inv = (am > 0.0) ? 1.0 / scl : 0.0;
-      double ss = 0.0;
-      for (int r = i + 2 + tid; r < m; r += blockDim.x) {
-        const double x = A[(int64_t)r * m + i] * inv;
-        ss += x * x;
+  const int nref = m - 2;
+  for (int i0 = 0; i0 < nref; i0 += NB) {
+    const int nbp = (nref - i0) < NB ? (nref - i0) : NB;
+    for (int j = 0; j < nbp; ++j) {
+      const int i = i0 + j;
+      // (1) row i updated by the panel's earlier reflectors
+      double am = 0.0, ss = 0.0;
+      for (int r = i + tid; r < m; r += NT) {
+        double a = A[(int64_t)i * m + r];
+        for (int q = 0; q < j; ++q) a -= VL[q * MMAX + r] * WL[q * MMAX + i] + WL[q * MMAX + r] * VL[q * MMAX + i];
+        x[r] = a;
+        if (r >= i + 2) {
+          am = fmax(am, fabs(a));
+          ss += a * a;
+        }
       }
+      am = wave_max(am);
       ss = wave_sum(ss);
-      if (lane == 0) red[wid] = ss;
+      if (lane == 0) {
+        red[wid] = am;
+        red[NW + wid] = ss;
+      }
       __syncthreads();
       if (tid == 0) {
-        double s = 0.0;
-        for (int q = 0; q < NW; ++q) s += red[q];
-        const double alpha = alpha0;
-        double t_, beta;
-        if (!(am > 0.0)) {
-          t_ = 0.0;
-          beta = alpha;
+        double amx = 0.0, s2 = 0.0;
+        for (int q = 0; q < NW; ++q) {
+          amx = fmax(amx, red[q]);
+          s2 += red[NW + q];
+        }
+        const double alpha = x[i + 1];
+        d[i] = x[i];
+        s_alpha = alpha;
+        s_slow = 0;
+        if (!(amx > 1e-290)) {  // only denormal dust below the subdiagonal: no reflection
+          s_tau = 0.0;
+          s_sc = 0.0;
+          e[i] = alpha;
+          tau[i] = 0.0;
+        } else if (s2 > 1e-280 && s2 < 1e280 && fabs(alpha) < 1e140) {
+          const double bs = -copysign(sqrt(alpha * alpha + s2), alpha);
+          s_tau = (bs - alpha) / bs;
+          s_sc = 1.0 / (alpha - bs);
+          e[i] = bs;
+          tau[i] = s_tau;
         } else {
-          const double as = alpha * inv;
-          const double bs = -copysign(sqrt(as * as + s), alpha);
-          beta = bs * scl;
-          t_ = (bs - as) / bs;
-          red[NW] = inv / (as - bs);
+          s_slow = 1;
+          red[2 * NW] = amx;
         }
-        s_tau = t_;
-        s_beta = beta;
-        d[i] = A[(int64_t)i * m + i];
-        e[i] = beta;
-        tau[i] = t_;
       }
       __syncthreads();
-      const double t_ = s_tau;
-      const double sc = (t_ != 0.0) ? red[NW] : 0.0;
-      for (int r = tid; r < MMAX; r += blockDim.x) {
+      if (s_slow) {  // squares out of range: norm of the scaled column
+        const double scl = fmax(red[2 * NW], fabs(s_alpha)), inv = 1.0 / scl;
+        double s3 = 0.0;
+        for (int r = i + 2 + tid; r < m; r += NT) {
+          const double t = x[r] * inv;
+          s3 += t * t;
+        }
+        s3 = wave_sum(s3);
+        if (lane == 0) red[NW + wid] = s3;
+        __syncthreads();
+        if (tid == 0) {
+          double s2 = 0.0;
+          for (int q = 0; q < NW; ++q) s2 += red[NW + q];
+          const double as = s_alpha * inv;
+          const double bs = -copysign(sqrt(as * as + s2), as);
+          s_tau = (bs - as) / bs;
+          s_sc = inv / (as - bs);
+          e[i] = bs * scl;
+          tau[i] = s_tau;
+        }
+        __syncthreads();
+      }
+      const double tp = s_tau, sc = s_sc;
+      // (2) v: unit at i+1, scaled tail (stored in row i for the back-transformation)
+      for (int r = tid; r < MMAX; r += NT) {
         double vr = 0.0;
-        if (r == i + 1) vr = 1.0;
-        else if (r > i + 1 && r < m) {
-          const double x = A[(int64_t)r * m + i] * sc;
-          vr = (t_ != 0.0) ? x : 0.0;
-          if (t_ != 0.0) A[(int64_t)r * m + i] = x;
+        if (r == i + 1) {
+          vr = 1.0;
+        } else if (r > i + 1 && r < m && tp != 0.0) {
+          vr = x[r] * sc;
+          A[(int64_t)i * m + r] = vr;
         }
-        v[r] = vr;
-        prow[r] = 0.0;
+        VL[j * MMAX + r] = vr;
+        x[r] = vr;
       }
       __syncthreads();
-    }
-    const double t_ = s_tau;
-    // (c) fused pass over rows r >= i+1, columns i+1..r
-    {
-      double pc[CPL];
+      // (3) y = A22 v over the trailing rows c > i (upper triangle), RU rows
+      //     per pass; dot products W_q.v and V_q.v of the earlier reflectors
+      {
+        double pc[CPL];
 #pragma unroll
-      for (int q = 0; q < CPL; ++q) pc[q] = 0.0;
-      for (int r = i + 1 + wid; r < m; r += NW) {
-        double *row = A + (int64_t)r * m;
-        const double vpr = vp[r], wr = w[r], vr = v[r];
-        double acc = 0.0;
+        for (int t = 0; t < CPL; ++t) pc[t] = 0.0;
+        // rows c0 .. c0 + RU - 1 per pass; the next pass's rows are loaded
+        // while this one is reduced.  Chunks t with t * 64 + 63 < c hold no
+        // element of row c (upper triangle) and are skipped (wave-uniform).
+        double av[RU][CPL], an[RU][CPL];
+        auto load_rows = [&](int cb, double (&dst)[RU][CPL]) {
 #pragma unroll
-        for (int q = 0; q < CPL; ++q) {
-          const int c = q * WAVE + lane;
-          if (c >= i + 1 && c <= r) {
-            double a = row[c];
-            if (pend) {
-              a -= vpr * w[c] + wr * vp[c];
-              row[c] = a;
+          for (int u = 0; u < RU; ++u) {
+            const int c = cb + u;
+            const double *row = A + (int64_t)c * m;
+#pragma unroll
+            for (int t = 0; t < CPL; ++t) {
+              const int r = t * WAVE + lane;
+              dst[u][t] = 0.0;
+              if (t * WAVE + WAVE - 1 >= cb) dst[u][t] = (c < m && r >= c && r < m) ? row[r] : 0.0;
             }
-            acc += a * v[c];
-            if (c < r) pc[q] += a * vr;
+          }
+        };
+        load_rows(i + 1 + RU * wid, an);
+        for (int c0 = i + 1 + RU * wid; c0 < m; c0 += RU * NW) {
+#pragma unroll
+          for (int u = 0; u < RU; ++u)
+#pragma unroll
+            for (int t = 0; t < CPL; ++t) av[u][t] = an[u][t];
+          if (c0 + RU * NW < m) load_rows(c0 + RU * NW, an);
+#pragma unroll
+          for (int u = 0; u < RU; ++u) {
+            const int c = c0 + u;
+            const double vc = (c < m) ? x[c] : 0.0;
+            double acc = 0.0;
+#pragma unroll
+            for (int t = 0; t < CPL; ++t) {
+              if (t * WAVE + WAVE - 1 >= c0) {
+                const int r = t * WAVE + lane;
+                acc += av[u][t] * x[r];
+                if (r > c) pc[t] += av[u][t] * vc;
+              }
+            }
+            acc = wave_sum(acc);
+            if (lane == 0 && c < m) prow[c] = acc;
           }
         }
-        acc = wave_sum(acc);
-        if (lane == 0) prow[r] = acc;
-      }
 #pragma unroll
-      for (int q = 0; q < CPL; ++q) pp[wid * MMAX + q * WAVE + lane] = pc[q];
+        for (int t = 0; t < CPL; ++t) pp[wid * MMAX + t * WAVE + lane] = pc[t];
+        for (int dq = wid; dq < 2 * j; dq += NW) {
+          const double *a = (dq < j) ? WL + dq * MMAX : VL + (dq - j) * MMAX;
+          double sacc = 0.0;
+          for (int r = i + 1 + lane; r < m; r += WAVE) sacc += a[r] * x[r];
+          sacc = wave_sum(sacc);
+          if (lane == 0) red[2 * NW + dq] = sacc;
+        }
+      }
+      __syncthreads();
+      // (4) y = tau (A22 v - V (W^T v) - W (V^T v)), then y.v
+      double yv = 0.0;
+      for (int r = tid; r < MMAX; r += NT) {
+        double yr = 0.0;
+        if (r >= i + 1 && r < m) {
+          yr = prow[r];
+#pragma unroll
+          for (int w = 0; w < NW; ++w) yr += pp[w * MMAX + r];
+          for (int q = 0; q < j; ++q) yr -= VL[q * MMAX + r] * red[2 * NW + q] + WL[q * MMAX + r] * red[2 * NW + j + q];
+          yr *= tp;
+          yv += yr * x[r];
+        }
+        y[r] = yr;
+      }
+      yv = wave_sum(yv);
+      if (lane == 0) red[wid] = yv;
+      __syncthreads();
+      double K = 0.0;
+      for (int q = 0; q < NW; ++q) K += red[q];
+      K *= -0.5 * tp;
+      // (5) w = y + K v
+      for (int r = tid; r < MMAX; r += NT) WL[j * MMAX + r] = (r >= i + 1 && r < m) ? y[r] + K * x[r] : 0.0;
+      __syncthreads();
     }
-    __syncthreads();
-    // (d) p = tau (prow + sum of column partials); K = tau/2 p.v; w = p - K v
-    double dotpv = 0.0;
-    for (int r = i + 1 + tid; r < m; r += blockDim.x) {
-      double p = prow[r];
-      for (int q = 0; q < NW; ++q) p += pp[q * MMAX + r];
-      p *= t_;
-      prow[r] = p;
-      dotpv += p * v[r];
+    // (6) A22 -= V W^T + W V^T on the rows / columns after the panel: each
+    //     wave takes RS rows at a time with their V, W entries in registers,
+    //     loads all their live chunks at once, and per chunk reads the
+    //     lane's V, W entries once for the RS rows
+    {
+      constexpr int RS = 2;
+      const int c1 = i0 + nbp;
+      for (int c0 = c1 + RS * wid; c0 < m; c0 += RS * NW) {
+        double av[RS][CPL], vc[RS][NB], wc[RS][NB];
+#pragma unroll
+        for (int u = 0; u < RS; ++u) {
+          const int c = c0 + u;
+#pragma unroll
+          for (int t = 0; t < CPL; ++t) {
+            const int r = t * WAVE + lane;
+            av[u][t] = 0.0;
+            if (t * WAVE + WAVE - 1 >= c0 && c < m && r >= c && r < m) av[u][t] = A[(int64_t)c * m + r];
+          }
+#pragma unroll
+          for (int q = 0; q < NB; ++q) {
+            vc[u][q] = (q < nbp && c < m) ? VL[q * MMAX + c] : 0.0;
+            wc[u][q] = (q < nbp && c < m) ? WL[q * MMAX + c] : 0.0;
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < CPL; ++t) {
+          if (t * WAVE + WAVE - 1 >= c0) {
+            const int r = t * WAVE + lane;
+            double vr[NB], wr[NB];
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+              vr[q] = VL[q * MMAX + r];
+              wr[q] = WL[q * MMAX + r];
+            }
+#pragma unroll
+            for (int u = 0; u < RS; ++u) {
+              const int c = c0 + u;
+              if (c < m && r >= c && r < m) {
+                double a = av[u][t];
+#pragma unroll
+                for (int q = 0; q < NB; ++q) a -= vc[u][q] * wr[q] + wc[u][q] * vr[q];
+                A[(int64_t)c * m + r] = a;
+              }
+            }
+          }
+        }
+      }
     }
-    dotpv = wave_sum(dotpv);
-    if (lane == 0) red[wid] = dotpv;
-    __syncthreads();
-    double K = 0.0;
-    for (int q = 0; q < NW; ++q) K += red[q];
-    K *= 0.5 * t_;
-    for (int r = tid; r < MMAX; r += blockDim.x) {
-      const bool act = (r >= i + 1 && r < m);
-      w[r] = act ? prow[r] - K * v[r] : 0.0;
-      vp[r] = act ? v[r] : 0.0;
-    }
-    if (tid == 0) s_pending = (t_ != 0.0) ? 1 : 0;
     __syncthreads();
   }
-  // trailing 2x2 (or 1x1) block
   if (tid == 0) {
-    const int pend = s_pending;
     if (m >= 2) {
-      double a00 = A[(int64_t)(m - 2) * m + (m - 2)], a10 = A[(int64_t)(m - 1) * m + (m - 2)],
-             a11 = A[(int64_t)(m - 1) * m + (m - 1)];
-      if (pend) {
-        a00 -= 2.0 * vp[m - 2] * w[m - 2];
-        a10 -= vp[m - 1] * w[m - 2] + w[m - 1] * vp[m - 2];
-        a11 -= 2.0 * vp[m - 1] * w[m - 1];
-      }
-      d[m - 2] = a00;
-      d[m - 1] = a11;
-      e[m - 2] = a10;
+      d[m - 2] = A[(int64_t)(m - 2) * m + (m - 2)];
+      d[m - 1] = A[(int64_t)(m - 1) * m + (m - 1)];
+      e[m - 2] = A[(int64_t)(m - 2) * m + (m - 1)];
       tau[m - 2] = 0.0;
-    } else {
+    } else if (m == 1) {
       d[0] = A[0];
     }
   }
 }
+
+// ---------------------------------------------------------------------------
+
 
 // Sturm count: number of eigenvalues of the symmetric tridiagonal (d, e) below x.
 __device__ __forceinline__ int sturm_count(const double *d, const double *e2, int m, double x, double pivmin) {
@@ -1807,12 +1931,12 @@ void launch_scale(hipStream_t st, double *p, int64_t count, double c) {
 
 
 int launch_sytrd(hipStream_t st, int nb, double *A, int64_t sA, int m, double *d, double *e, double *tau, int64_t sv) {
-  if (m > 512) return -1;
   constexpr int MMAX = 512;
-  size_t lds = (4 * MMAX + 16 * MMAX + 64) * sizeof(double);
+  if (m > MMAX) return -1;
+  const size_t lds = (2 * 8 * MMAX + 3 * MMAX + 8 * MMAX + 2 * 8 + 2 * 8 + 8) * sizeof(double);
   static bool attr = false;
-  if (!attr) { set_lds(k_sytrd<MMAX>, lds); attr = true; }
-  hipLaunchKernelGGL(k_sytrd<MMAX>, dim3(nb), dim3(1024), lds, st, A, sA, m, d, e, tau, sv);
+  if (!attr) { set_lds(k_sytrd2<MMAX>, lds); attr = true; }
+  hipLaunchKernelGGL(k_sytrd2<MMAX>, dim3(nb), dim3(512), lds, st, A, sA, m, d, e, tau, sv);
   return 0;
 }
 

@@ -61,11 +61,22 @@ class ThcStats(C.Structure):
         ("jacobi_sweeps_max", C.c_int32),
         ("nonconverged", C.c_int32),
         ("reserved", C.c_int32),
+        ("kernel_ms", C.c_double * 5),
+        ("kernel_flops", C.c_double * 5),
+        ("kernel_launches", C.c_int64 * 5),
     ]
+    KERNELS = ("lq", "sytrd", "tri_eig", "ormtr", "gemm")
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved" and not f.startswith("kernel_")}
 
+    def kernels(self):
+        """Per kernel class: (summed ms, algorithmic flops, launches); filled with THC_FLAG_TIME_KERNELS."""
+        return {k: (self.kernel_ms[i], self.kernel_flops[i], self.kernel_launches[i]) for i, k in enumerate(self.KERNELS)}
+
+
+FLAG_SVD_JACOBI = 1      # one-sided Jacobi SVD in the truncation step
+FLAG_TIME_KERNELS = 2    # per-kernel-class device times / flops in ThcStats.kernels()
 
 EXPORTS = [
     "thc_default_opts", "thc_mps_capacity", "thc_load_factors", "thc_destroy", "mps_apply_thc_H",

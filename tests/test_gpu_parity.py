@@ -180,3 +180,42 @@ def test_lanczos_small_matches_oracle(thck, flags, tol):
         assert np.allclose(g, rg, atol=atol, rtol=0), (i, g, rg)
         assert np.allclose(tt, rt, atol=atol, rtol=0), (i, tt, rt)
         assert abs(bb - b) < atol
+
+
+def test_apply_H_untruncated_at_tile_size(thck):
+    # L=8 (16 sites), N=32, D=256: the largest Schmidt rank of 16 sites is
+    # 2^8 = 256, so the compressed result is exact; the interior site matrices
+    # have the full 512 x 1024 LQ and 512 x 512 SVD shapes of the L=20 run.
+    t, chi, zeta, sites = synth.make_workload("L8_N32_D256")
+    psi = M.scale(sites, 1.0 / M.norm(sites))
+    ctx = thck.Context(t, chi, zeta)
+    st = thck.ThcStats()
+    out = ctx.apply_H(thck.DeviceMPS.from_sites(psi), D=256, stats=st)
+    got = M.to_dense(out.to_sites())
+    ref = F.apply_H_dense(M.to_dense(psi), t, TH.thc_v(chi, zeta))
+    err = _rel(got, ref)
+    print(f"L8 N32 D256: rel err {err:.3e}, compressions {st.n_compressions}, max bond {st.max_bond}")
+    assert err < 1e-12
+    assert st.n_compressions == 2 * 2 * 32 + 2 * 4 * 32 * 32 + 2 * 2 * 8 + (4 * 32 * 32 + 2 * 8 - 1)
+
+
+def test_kernel_timing_flag(thck):
+    # THC_FLAG_TIME_KERNELS fills per-kernel device times and flops without
+    # changing the result
+    t, chi, zeta, sites = synth.make_workload("L4_N8_D16")
+    psi = M.scale(sites, 1.0 / M.norm(sites))
+    ctx = thck.Context(t, chi, zeta)
+    d = thck.DeviceMPS.from_sites(psi)
+    s0, s1 = thck.ThcStats(), thck.ThcStats()
+    a = M.to_dense(ctx.apply_H(d, D=16, stats=s0).to_sites())
+    b = M.to_dense(ctx.apply_H(d, D=16, stats=s1, flags=thck.FLAG_TIME_KERNELS).to_sites())
+    assert _rel(b, a) < 1e-14
+    k0, k1 = s0.kernels(), s1.kernels()
+    assert all(v == (0.0, 0.0, 0) for v in k0.values())
+    for name in ("lq", "sytrd", "tri_eig", "ormtr", "gemm"):
+        ms, fl, n = k1[name]
+        assert n > 0 and ms > 0.0, (name, k1[name])
+        if name != "tri_eig":
+            assert fl > 0.0
+    # one LQ per site of the canonical sweep and one per bond of the SVD sweep
+    assert k1["lq"][2] == 2 * k1["sytrd"][2] or k1["lq"][2] > k1["sytrd"][2]
