@@ -294,8 +294,8 @@ __device__ __forceinline__ void block_reflect_rows(double *__restrict__ X, int l
   // this wave's 16 x chunk tile in registers: xa[s] = X[rt+li][cb+4s+lk];
   // element (row, c0 + kc): row-major X[row * ldx + c0 + kc], or with TR
   // (X stored transposed) X[(c0 + kc) * ldx + row]; 16 lanes then read 16
-  // consecutive doubles.  The next tile is loaded while this one is reduced
-  // and updated.
+  // consecutive doubles.  The next tile is loaded while this one is
+  // updated and stored.
   const int so = 8 * (TR ? 4 * ldx : 4);
   auto load_tile = [&](int rt, double (&dst)[SMAX]) {
     const int row = rt + li;
@@ -329,7 +329,6 @@ __device__ __forceinline__ void block_reflect_rows(double *__restrict__ X, int l
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) Wp[wv * 256 + (lk + 4 * r) * 16 + li] = acc[r];
-    if (rt + 16 < r_end) load_tile(rt + 16, xn);
     __syncthreads();
     if (tid < 256) {
       const int i = tid / 16, p = tid % 16;
@@ -352,6 +351,9 @@ __device__ __forceinline__ void block_reflect_rows(double *__restrict__ X, int l
     double bw[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) bw[q] = WT[li * 16 + 4 * q + lk];
+    // the next tile's loads go out here, after the previous tile's stores
+    // have had the reduction phase to drain
+    if (rt + 16 < r_end) load_tile(rt + 16, xn);
 #pragma unroll
     for (int b4 = 0; b4 < SMAX / 4; ++b4) {
       if (4 * b4 < S) {
@@ -1517,16 +1519,18 @@ __device__ __forceinline__ int sturm_count(const double *d, const double *e2, in
   return cnt;
 }
 
-// tri_eig: top-kk eigenpairs of the tridiagonal (d, e), one workgroup per
-// matrix.  Eigenvalues: bisection on Sturm counts to full precision, thread t
-// owning the t-th largest.  Eigenvectors: inverse iteration (three steps)
-// with a partial-pivoting LU of (T - lambda I), zero pivots replaced by
-// eps*||T||, from a deterministic pseudo-random start.  Eigenvalues closer
-// than 1e-7*||T|| form a cluster whose members are iterated by one thread in
-// turn, each iterate orthogonalised (MGS) against the earlier members, as in
-// LAPACK's stein; eigenvalues below the noise floor 1e-14*||T|| are not
-// clustered (their vectors only need to complete an orthonormal basis,
-// which the re-orthonormalisation that follows provides).
+// tri_eig: top-kk eigenpairs of the tridiagonal (d, e), one workgroup of
+// 1024 threads per matrix, kk <= 256.  Eigenvalues: multisection on Sturm
+// counts to full precision, four lanes per eigenvalue (the t-th largest).
+// Eigenvectors: inverse iteration (three steps) with a partial-pivoting LU
+// of (T - lambda I), zero pivots replaced by eps*||T||, from a
+// deterministic pseudo-random start.  Consecutive eigenvalues within a
+// relative gap of 1e-6 form a cluster (at most 32 members) whose members are
+// iterated by one thread in turn, each iterate orthogonalised (MGS) against
+// the earlier members, as in LAPACK's stein; eigenvalues below the noise
+// floor 1e-14*||T|| get pseudo-random vectors (they only need to complete
+// an orthonormal basis, which the re-orthonormalisation that follows
+// provides).
 // Output Z (m x kk, column t = eigenvector t) and lambda (kk, descending).
 // Scratch per job: 4 m kk doubles + m kk ints, laid out [r][t].
 __device__ void inv_iter_one(const double *sd, const double *se, int m, int kk, int t, double lm, double tiny,
@@ -1611,7 +1615,7 @@ __device__ void inv_iter_one(const double *sd, const double *se, int m, int kk, 
   }
 }
 
-__global__ __launch_bounds__(256) void k_tri_eig(const double *__restrict__ db, const double *__restrict__ eb,
+__global__ __launch_bounds__(1024) void k_tri_eig(const double *__restrict__ db, const double *__restrict__ eb,
                                                  int64_t sv, int m, int kk, double *__restrict__ Zb, int64_t sZ,
                                                  double *__restrict__ lamb, int64_t sl, double *__restrict__ scrb,
                                                  int64_t sscr) {
@@ -1669,23 +1673,40 @@ __global__ __launch_bounds__(256) void k_tri_eig(const double *__restrict__ db, 
   if (tid == 0) s_nsig = (tn > 0.0) ? m - sturm_count(sd, se2, m, noise, pivmin) : 0;
   __syncthreads();
   const int nsig = s_nsig;
-  for (int t = tid; t < kk; t += blockDim.x) {
-    if (t >= nsig) {
-      slam[t] = 0.0;
-      lam[t] = 0.0;
-      continue;
-    }
+  // multisection: four consecutive lanes share eigenvalue t and each
+  // evaluates the Sturm count at one of the points a + (b - a) (s + 1) / 5,
+  // so every step shrinks the bracket five-fold; the four lanes agree on the
+  // new bracket through the wave ballot
+  const int lane = tid % WAVE;
+  for (int g = tid / 4; g < ((kk + 63) / 64) * 64; g += blockDim.x / 4) {
+    const int t = g, sub = tid % 4;
+    const bool act = t < kk && t < nsig;
     const int j = m - 1 - t;  // index in ascending order
     double a = fmax(lo_s - pad, noise), b = hi_s + pad;
-    for (int it = 0; it < 80; ++it) {
-      const double mid = 0.5 * (a + b);
-      if (!(mid > a && mid < b)) break;
-      if (b - a <= 2.2e-16 * fmax(fabs(a), fabs(b)) + 1e-18 * tn) break;
-      if (sturm_count(sd, se2, m, mid, pivmin) <= j) a = mid;
-      else b = mid;
+    bool done = !act;
+    for (int it = 0; it < 40; ++it) {
+      if (!done && !(b - a > 2.2e-16 * fmax(fabs(a), fabs(b)) + 1e-18 * tn)) done = true;
+      if (__ballot(!done) == 0ull) break;
+      const double x = a + (b - a) * (double)(sub + 1) * 0.2;
+      const bool above = done ? false : (sturm_count(sd, se2, m, x, pivmin) > j);
+      const unsigned long long bal = __ballot(above);
+      if (!done) {
+        const unsigned int grp = (unsigned int)((bal >> (lane & ~3)) & 0xFull);
+        if (grp == 0u) {
+          a = a + (b - a) * 0.8;
+        } else {
+          const int s0 = __builtin_ctz(grp);
+          const double lo2 = (s0 == 0) ? a : a + (b - a) * (double)s0 * 0.2;
+          const double hi2 = a + (b - a) * (double)(s0 + 1) * 0.2;
+          a = lo2;
+          b = hi2;
+        }
+      }
     }
-    slam[t] = 0.5 * (a + b);
-    lam[t] = slam[t] * tn_raw;
+    if (t < kk && sub == 0) {
+      slam[t] = act ? 0.5 * (a + b) : 0.0;
+      lam[t] = act ? slam[t] * tn_raw : 0.0;
+    }
   }
   __syncthreads();
   for (int t = tid; t < kk; t += blockDim.x) {
@@ -1942,8 +1963,8 @@ int launch_sytrd(hipStream_t st, int nb, double *A, int64_t sA, int m, double *d
 
 int launch_tri_eig(hipStream_t st, int nb, const double *d, const double *e, int64_t sv, int m, int kk, double *Z,
                    int64_t sZ, double *lam, int64_t sl, double *scr, int64_t sscr) {
-  if (m > 1024) return -1;
-  hipLaunchKernelGGL(k_tri_eig, dim3(nb), dim3(256), 0, st, d, e, sv, m, kk, Z, sZ, lam, sl, scr, sscr);
+  if (m > 1024 || kk > 256) return -1;
+  hipLaunchKernelGGL(k_tri_eig, dim3(nb), dim3(1024), 0, st, d, e, sv, m, kk, Z, sZ, lam, sl, scr, sscr);
   return 0;
 }
 

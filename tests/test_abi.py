@@ -67,3 +67,35 @@ def test_default_opts():
     from paper_2409_12708_amd import thck
     o = thck.make_opts(64)
     assert o.D_max == 64 and o.rel_cutoff == 1e-14 and o.include_T == 1 and o.include_V == 1 and o.prec == 0
+
+
+def test_struct_layouts_match_header(tmp_path):
+    # the ctypes structures must have the C sizes and field offsets of thck.h
+    import ctypes as C
+    import shutil
+    import subprocess
+    from paper_2409_12708_amd import thck as T
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "layout.c"
+    fields = {
+        "thc_mps": [f for f, _ in T.ThcMps._fields_],
+        "thc_opts": [f for f, _ in T.ThcOpts._fields_],
+        "thc_stats": [f for f, _ in T.ThcStats._fields_],
+    }
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "thck.h"', "int main(void) {"]
+    for s, fs in fields.items():
+        lines.append(f'  printf("{s} %zu\\n", sizeof({s}));')
+        for f in fs:
+            lines.append(f'  printf("{s}.{f} %zu\\n", offsetof({s}, {f}));')
+    lines += ["  return 0;", "}"]
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                         check=True).stdout.split("\n") if l)
+    for s, cls in (("thc_mps", T.ThcMps), ("thc_opts", T.ThcOpts), ("thc_stats", T.ThcStats)):
+        assert int(out[s]) == C.sizeof(cls), s
+        for f, _ in cls._fields_:
+            assert int(out[f"{s}.{f}"]) == getattr(cls, f).offset, (s, f)
