@@ -153,6 +153,7 @@ struct thc_ctx {
   std::vector<std::unique_ptr<DevBuf>> slot_store;
   // batch workspace
   DevBuf ws, jobs_dev, small_dev;
+  DevBuf ovl;  // transfer matrices of mps_overlap
   PinnedBuf jobs_host;
   size_t jobs_host_used = 0;
   // statistics accumulated on the host from device readbacks
@@ -473,8 +474,11 @@ struct Engine {
       if (j == n - 1) {
         launch_transpose(st, nb, Bb, S, P.bo[j], 2, Tb, S);
       } else {
-        gemm(nb, GEMM_ST2, Bb, S, P.bo[j + 1], Lb, S, P.c[j + 1], Tb, S, P.bo[j], P.bo[j] * 2, P.c[j + 1],
-                    P.bo[j + 1]);
+        // X_j^T = [(B_j^0 L)^T ; (B_j^1 L)^T], B_j^s = B_j[:, s, :]: one GEMM per
+        // physical index with both operands read transposed
+        for (int sg = 0; sg < 2; ++sg)
+          gemm(nb, GEMM_TA | GEMM_TB, Lb, S, P.c[j + 1], Bb + sg * P.bo[j + 1], S, 2 * P.bo[j + 1],
+               Tb + (int64_t)sg * P.c[j + 1] * P.bo[j], S, P.bo[j], P.c[j + 1], P.bo[j], P.bo[j + 1]);
       }
       ++launches;
       if (lq(nb, Tb, S, P.bo[j], 2 * P.c[j + 1], Lb, S, Qs + P.qs_off[j], S, Tf, S, true) != 0)
@@ -1256,30 +1260,24 @@ thc_status mps_overlap(thc_ctx *ctx, const thc_mps *a, const thc_mps *b, double 
     const int n = a->n_sites;
     int maxb = 1;
     for (int j = 0; j <= n; ++j) maxb = std::max(maxb, std::max(a->bonds[j], b->bonds[j]));
-    int64_t s_scr = 3 * (int64_t)maxb * maxb;
-    DevBuf scr, meta, res;
-    scr.ensure((size_t)s_scr * sizeof(double));
-    size_t mbytes = sizeof(OJob) + 2 * (n + 1) * sizeof(int) + 2 * n * sizeof(int64_t) + 64;
-    meta.ensure(mbytes);
-    std::vector<char> h(mbytes);
-    OJob oj{a->data, b->data};
-    size_t p = 0;
-    memcpy(h.data() + p, &oj, sizeof(OJob));
-    size_t pba = (p + sizeof(OJob) + 7) / 8 * 8;
-    memcpy(h.data() + pba, a->bonds, (n + 1) * sizeof(int));
-    size_t pbb = pba + (n + 1) * sizeof(int);
-    memcpy(h.data() + pbb, b->bonds, (n + 1) * sizeof(int));
-    size_t poa = (pbb + (n + 1) * sizeof(int) + 7) / 8 * 8;
-    memcpy(h.data() + poa, a->offsets, n * sizeof(int64_t));
-    size_t pob = poa + n * sizeof(int64_t);
-    memcpy(h.data() + pob, b->offsets, n * sizeof(int64_t));
-    HIPCHK(hipMemcpyAsync(meta.p, h.data(), mbytes, hipMemcpyHostToDevice, s));
-    res.ensure(sizeof(double));
-    char *mp = (char *)meta.p;
-    launch_overlap(s, 1, (const OJob *)mp, n, (const int *)(mp + pba), (const int64_t *)(mp + poa),
-                   (const int *)(mp + pbb), (const int64_t *)(mp + pob), scr.as<double>(), s_scr, res.as<double>());
+    // transfer-matrix chain E_{j+1} = sum_s A_j^{sT} E_j B_j^s as two GEMMs
+    // per site: F = E B_j ((la) x (2 rb)), viewed as ((la 2) x rb), then
+    // E' = A_j^T F with A_j viewed as ((la 2) x ra)
+    const int64_t sz = (int64_t)maxb * maxb;
+    DevBuf &w = ctx->ovl;
+    w.ensure((size_t)(4 * sz + 32) * sizeof(double));
+    double *E = w.as<double>(), *E2 = E + sz, *F = E + 2 * sz;
+    static const double one = 1.0;
+    HIPCHK(hipMemcpyAsync(E, &one, sizeof(double), hipMemcpyHostToDevice, s));
+    for (int j = 0; j < n; ++j) {
+      const int la = a->bonds[j], ra = a->bonds[j + 1], lb = b->bonds[j], rb = b->bonds[j + 1];
+      const double *Aj = a->data + a->offsets[j], *Bj = b->data + b->offsets[j];
+      launch_gemm(s, 1, 0, E, 0, lb, Bj, 0, 2 * rb, F, 0, 2 * rb, la, 2 * rb, lb);
+      launch_gemm(s, 1, GEMM_TA, Aj, 0, ra, F, 0, rb, E2, 0, rb, ra, rb, 2 * la);
+      std::swap(E, E2);
+    }
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(result, res.p, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(result, E, sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
   });
 }

@@ -20,11 +20,6 @@ struct CJob {
   int dag;
 };
 
-struct OJob {
-  const double *a;
-  const double *b;
-};
-
 constexpr int RITZ_MAX = 32;
 
 int lq_t_stride(int k);
@@ -32,9 +27,8 @@ int lq_t_stride(int k);
 void launch_construct(hipStream_t st, const CJob *jobs, int nb, int site, int n_sites, int64_t in_off_a,
                       int64_t in_off_b, int la, int ra, int lb, int rb, double *out, int64_t out_stride, int lo,
                       int ro);
-// GEMM modes (bits): B given transposed, A given transposed, split-transposed
-// store (see k_gemm_mfma).
-constexpr int GEMM_TB = 1, GEMM_TA = 2, GEMM_ST2 = 4;
+// GEMM modes (bits): B given transposed, A given transposed.
+constexpr int GEMM_TB = 1, GEMM_TA = 2;
 void launch_gemm(hipStream_t st, int nb, int mode, const double *A, int64_t sA, int lda, const double *B,
                  int64_t sB, int ldb, double *C, int64_t sC, int ldc, int M, int N, int K);
 void launch_transpose(hipStream_t st, int nb, const double *src, int64_t ss, int r, int c, double *dst, int64_t sd);
@@ -55,8 +49,6 @@ void launch_gather(hipStream_t st, int nb, const CJob *jobs, int which, int64_t 
                    int64_t count);
 void launch_scatter(hipStream_t st, int nb, const CJob *jobs, int64_t off, const double *src, int64_t ssrc,
                     int64_t count);
-void launch_overlap(hipStream_t st, int nb, const OJob *jobs, int n_sites, const int *bonds_a, const int64_t *off_a,
-                    const int *bonds_b, const int64_t *off_b, double *scratch, int64_t s_scr, double *out);
 void launch_scale(hipStream_t st, double *p, int64_t count, double c);
 void launch_repack(hipStream_t st, int gx, const double *src, int64_t soff, int ks_l, int ks_r, double *dst,
                    int64_t doff, int rl, int rr);

@@ -133,9 +133,7 @@ __device__ __forceinline__ d4_t mfma16(double a, double b, d4_t c) {
 // ---------------------------------------------------------------------------
 // gemm: C = op(A) * op(B), row-major FP64, batched.  A is M x K (lda), or
 // with TA given as its transpose (K x M, lda).  B is K x N (ldb), or with TB
-// given as N x K.  ST2: the M rows are (a, s) pairs (M = 2 M2) and C is
-// stored as the transpose of the M2 x (2N) matrix [C_(a,0) | C_(a,1)], i.e.
-// element (2a + s, n) goes to C[(s N + n) ldc + a].  MFMA 16x16x4 tiles:
+// given as N x K.  MFMA 16x16x4 tiles:
 // BM x BN output tile per workgroup of 4 waves (2 x 2, each wave BM/2 x
 // BN/2), K in chunks of 16 staged in LDS, the next chunk prefetched into
 // registers while the current one is multiplied.  A and B^T chunks sit in
@@ -150,7 +148,7 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(const double *__restrict__ A,
                                                    const double *__restrict__ B, int64_t sB, int ldb,
                                                    double *__restrict__ C, int64_t sC, int ldc, int M, int N,
                                                    int K, int tiles_m, int tiles_n) {
-  constexpr bool TB = (MODE & GEMM_TB) != 0, TA = (MODE & GEMM_TA) != 0, ST2 = (MODE & GEMM_ST2) != 0;
+  constexpr bool TB = (MODE & GEMM_TB) != 0, TA = (MODE & GEMM_TA) != 0;
   constexpr int BK = 16;
   constexpr int WM = BM / 32, WN = BN / 32;  // 16x16 blocks per wave
   constexpr int LA = BK + 1;                 // row stride of [rows][k] chunks
@@ -260,10 +258,7 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(const double *__restrict__ A,
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int gr = m0 + wm * (BM / 2) + 16 * i + lk + 4 * r;
-        if (gr < M && gc < N) {
-          if (ST2) C[((int64_t)(gr & 1) * N + gc) * ldc + (gr >> 1)] = acc[i][j][r];
-          else C[(int64_t)gr * ldc + gc] = acc[i][j][r];
-        }
+        if (gr < M && gc < N) C[(int64_t)gr * ldc + gc] = acc[i][j][r];
       }
     }
 }
@@ -886,50 +881,6 @@ __global__ void k_scatter(const CJob *__restrict__ jobs, int64_t off, const doub
     d[e] = s[e];
 }
 
-// ---------------------------------------------------------------------------
-// overlap: E_j = sum_n A_j^{nT} E_{j-1} B_j^n for a batch of MPS pairs, one
-// workgroup per pair, E held in global scratch (ping-pong).  FP64.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_overlap(const OJob *__restrict__ jobs, int n_sites,
-                                                 const int *__restrict__ bonds_a, const int64_t *__restrict__ off_a,
-                                                 const int *__restrict__ bonds_b, const int64_t *__restrict__ off_b,
-                                                 double *__restrict__ scratch, int64_t s_scr, double *__restrict__ out) {
-  const OJob jb = jobs[blockIdx.x];
-  double *E0 = scratch + (int64_t)blockIdx.x * s_scr;
-  double *F = E0 + s_scr / 3;        // F = E A^n stage  (la x? ) sized by caller
-  double *E1 = E0 + 2 * (s_scr / 3);
-  const int tid = threadIdx.x;
-  if (tid == 0) E0[0] = 1.0;
-  __syncthreads();
-  double *Ecur = E0, *Enext = E1;
-  for (int j = 0; j < n_sites; ++j) {
-    const int la = bonds_a[j], ra = bonds_a[j + 1], lb = bonds_b[j], rb = bonds_b[j + 1];
-    const double *A = jb.a + off_a[j];
-    const double *B = jb.b + off_b[j];
-    // Enext[c][d] = sum_n sum_a (sum_b E[a][b] B[b][n][d]) A[a][n][c]
-    for (int e = tid; e < ra * rb; e += blockDim.x) Enext[e] = 0.0;
-    __syncthreads();
-    for (int nn = 0; nn < 2; ++nn) {
-      // F[a][d] = sum_b E[a][b] B[b][nn][d]
-      for (int e = tid; e < la * rb; e += blockDim.x) {
-        int a = e / rb, d = e % rb;
-        double acc = 0.0;
-        for (int b = 0; b < lb; ++b) acc = fma(Ecur[a * lb + b], B[((int64_t)b * 2 + nn) * rb + d], acc);
-        F[e] = acc;
-      }
-      __syncthreads();
-      for (int e = tid; e < ra * rb; e += blockDim.x) {
-        int c = e / rb, d = e % rb;
-        double acc = 0.0;
-        for (int a = 0; a < la; ++a) acc = fma(A[((int64_t)a * 2 + nn) * ra + c], F[a * rb + d], acc);
-        Enext[e] += acc;
-      }
-      __syncthreads();
-    }
-    double *t = Ecur; Ecur = Enext; Enext = t;
-  }
-  if (tid == 0) out[blockIdx.x] = Ecur[0];
-}
 
 // repack: dst (bonds rl x 2 x rr, packed at doff) <- leading block of src
 // stored with static bonds (ks_l x 2 x ks_r) at soff.
@@ -1823,7 +1774,9 @@ void launch_gemm(hipStream_t st, int nb, int mode, const double *A, int64_t sA, 
     case 0: gemm_mode<0>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K); break;
     case GEMM_TB: gemm_mode<GEMM_TB>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K); break;
     case GEMM_TA: gemm_mode<GEMM_TA>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K); break;
-    case GEMM_ST2: gemm_mode<GEMM_ST2>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K); break;
+    case GEMM_TA | GEMM_TB:
+      gemm_mode<GEMM_TA | GEMM_TB>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K);
+      break;
     default: break;
   }
 }
@@ -1932,11 +1885,6 @@ void launch_scatter(hipStream_t st, int nb, const CJob *jobs, int64_t off, const
   hipLaunchKernelGGL(k_scatter, dim3(gx, nb), dim3(256), 0, st, jobs, off, src, ssrc, count);
 }
 
-void launch_overlap(hipStream_t st, int nb, const OJob *jobs, int n_sites, const int *bonds_a, const int64_t *off_a,
-                    const int *bonds_b, const int64_t *off_b, double *scratch, int64_t s_scr, double *out) {
-  hipLaunchKernelGGL(k_overlap, dim3(nb), dim3(256), 0, st, jobs, n_sites, bonds_a, off_a, bonds_b, off_b, scratch,
-                     s_scr, out);
-}
 
 void launch_repack(hipStream_t st, int gx, const double *src, int64_t soff, int ks_l, int ks_r, double *dst,
                    int64_t doff, int rl, int rr) {
