@@ -57,7 +57,15 @@ typedef enum {
 /* Caller-owned MPS view.  On input, bonds/offsets describe the data.  On
  * output, the library writes bonds[0..n] and offsets[0..n-1] (packed, in
  * elements) and fills data; capacity (elements) must be at least
- * thc_mps_capacity(n_sites, D). */
+ * thc_mps_capacity(n_sites, D).
+ *
+ * canonical: on input, nonzero declares that sites 1..n-1 are
+ * right-canonical (for every site j >= 1 the rows a of A_j[a][s][b] are
+ * orthonormal over (s, b); the norm sits at site 0).  The library then
+ * keeps those rows as they are in the right-to-left orthogonalisation of
+ * the compression (Sec. 3.1) and factorises only the rest.  It is not
+ * checked: a wrong declaration gives wrong results.  Zero is always safe.
+ * On output the library writes 1: every MPS it returns is in that form. */
 typedef struct {
   int32_t n_sites;
   int32_t d;          /* must be 2 */
@@ -65,6 +73,8 @@ typedef struct {
   int64_t *offsets;   /* host, n_sites entries (elements) */
   double *data;       /* device */
   int64_t capacity;   /* elements available at data */
+  int32_t canonical;  /* see above */
+  int32_t reserved;   /* set to 0 */
 } thc_mps;
 
 typedef struct {

@@ -186,6 +186,16 @@ def left_canonical_error(psi) -> float:
     return err
 
 
+def right_canonical_error(psi) -> float:
+    """max_j || sum_n A_j^n A_j^nT - I || over sites 1..n-1."""
+    err = 0.0
+    for a in psi[1:]:
+        l, d, r = a.shape
+        m = a.reshape(l, d * r)
+        err = max(err, float(np.max(np.abs(m @ m.T - np.eye(l)))))
+    return err
+
+
 def schmidt_values(psi):
     """Schmidt values at every bond (exact, via right-canonical form + SVD sweep)."""
     rec = []

@@ -206,6 +206,11 @@ void slot_free(thc_ctx *c, double *p) {
 struct Plan {
   int n = 0;
   int kind = 0;
+  // mode 1: inputs right-canonical, structured LQ sweep (canonical rows kept,
+  // only the rest rows factorised); mode 0: the plain LQ sweep
+  int mode = 0;
+  std::vector<int> lc, lr, c0;  // per site: canonical rows, rest rows, new Q rows
+  int64_t oLt = 0, sLt = 0;     // two L' blocks (ping-pong), each sLt elements
   Profile pa, pb;            // input profiles
   std::vector<int> bo;       // constructed bonds (2D)
   std::vector<int> c;        // right-canonical bonds
@@ -229,7 +234,7 @@ double svd_flops(double m, double n) {  // Golub-Reinsch thin SVD with U and V (
   return 14.0 * M * k * k + 8.0 * k * k * k;
 }
 
-Plan make_plan(int kind, const Profile &pa, const Profile *pb, int D) {
+Plan make_plan(int kind, const Profile &pa, const Profile *pb, int D, bool rc_in = false) {
   Plan P;
   P.kind = kind;
   P.n = pa.n();
@@ -242,6 +247,31 @@ Plan make_plan(int kind, const Profile &pa, const Profile *pb, int D) {
   for (int j = n - 1; j >= 1; --j) P.c[j] = std::min(P.bo[j], 2 * P.c[j + 1]);
   P.k.assign(n + 1, 1);
   for (int j = 0; j + 1 < n; ++j) P.k[j + 1] = std::min(std::min(2 * P.k[j], P.c[j + 1]), D);
+  // structured sweep: rows [A_j | 0] (orthonormal for a right-canonical
+  // input) are kept as the first lc_j rows of Q_j; the lr_j rest rows are
+  // projected on their complement and factorised, giving c0_j more rows.
+  // Usable when every c0_j is 0 or lr_j (then c_j = lc_j + c0_j equals the
+  // plain sweep's c_j).
+  if (rc_in && n >= 2) {
+    P.lc.assign(n + 1, 0);
+    P.lr.assign(n + 1, 0);
+    P.c0.assign(n + 1, 0);
+    P.lc[n] = 1;
+    P.lr[n] = (kind == 0) ? 0 : 1;
+    bool ok = true;
+    for (int j = n - 1; j >= 1 && ok; --j) {
+      P.lc[j] = pa.b[j];
+      P.lr[j] = (kind == 0) ? pa.b[j] : pb->b[j];
+      const int room = 2 * P.c[j + 1] - P.lc[j];
+      if (room < 0) { ok = false; break; }
+      P.c0[j] = std::min(P.lr[j], room);
+      if (P.c0[j] != 0 && P.c0[j] != P.lr[j]) ok = false;
+      if (P.lc[j] + P.c0[j] != P.c[j]) ok = false;
+      if (j + 1 < n && pa.b[j + 1] != P.lc[j + 1]) ok = false;
+      if (j + 1 < n && ((kind == 0) ? pa.b[j + 1] : pb->b[j + 1]) != P.lr[j + 1]) ok = false;
+    }
+    if (ok) P.mode = 1;
+  }
   P.out.b = P.k;
   P.out.pack();
   int64_t mB = 0, mT = 0, mL = 0, mM = 0, mW = 0, mZ = 0, mQz = 0, mLz = 0, mS = 0, mTf = 0, mU = 0, mG = 0,
@@ -256,9 +286,20 @@ Plan make_plan(int kind, const Profile &pa, const Profile *pb, int D) {
     if (j >= 1) {
       P.qs_off[j] = qs;
       qs += (int64_t)P.c[j] * 2 * P.c[j + 1];
-      fl += lq_flops(P.bo[j], 2.0 * P.c[j + 1]);
-      if (j + 1 < n) fl += 2.0 * (2.0 * P.bo[j - 1]) * P.bo[j] * P.c[j];  // absorb L into site j-1
+      if (P.mode == 1) {
+        const double c1 = P.c[j + 1], lcj = P.lc[j], lrj = P.lr[j];
+        fl += 2.0 * (2.0 * c1) * lrj * P.lr[j + 1];  // rest rows: source x L'
+        fl += 2.0 * 2.0 * (2.0 * c1) * lrj * lcj;    // projection on the canonical rows
+        if (P.c0[j] > 0) fl += lq_flops(lrj, 2.0 * c1);
+      } else {
+        fl += lq_flops(P.bo[j], 2.0 * P.c[j + 1]);
+        if (j + 1 < n) fl += 2.0 * (2.0 * P.bo[j - 1]) * P.bo[j] * P.c[j];  // absorb L into site j-1
+      }
+      // right-canonical output: LQ of U_j L_{j+1} (k_j x 2 k_{j+1})
+      fl += lq_flops(P.k[j], 2.0 * P.k[j + 1]);
+      fl += 2.0 * (2.0 * P.k[j - 1]) * P.k[j] * P.k[j];
     }
+    if (P.mode == 1 && j >= 1) P.sLt = std::max(P.sLt, (int64_t)P.lr[j] * P.c[j]);
     if (j + 1 < n) {
       const int m = 2 * P.k[j], nc = P.c[j + 1], kk = P.k[j + 1];
       mM = std::max(mM, (int64_t)m * nc);
@@ -304,6 +345,10 @@ Plan make_plan(int kind, const Profile &pa, const Profile *pb, int D) {
   P.oZm = take(std::max<int64_t>(mZm, 1));
   P.oLam = take(std::max<int64_t>(mS, 1));
   P.oScr = take(std::max<int64_t>(mScr, 1));
+  if (P.mode == 1) {
+    P.sLt = std::max<int64_t>(P.sLt, 1);
+    P.oLt = take(2 * ((P.sLt + 31) / 32 * 32));
+  }
   P.per_job = o;
   P.flops_per_job = fl;
   return P;
@@ -391,14 +436,15 @@ struct Engine {
   }
   // launchers of the timed kernel classes, with their algorithmic flops
   void gemm(int nb, int mode, const double *A, int64_t sA, int lda, const double *B, int64_t sB, int ldb, double *C,
-            int64_t sC, int ldc, int M, int N, int K) {
+            int64_t sC, int ldc, int M, int N, int K, double alpha = 1.0, double beta = 0.0) {
     timed(THC_K_GEMM, 2.0 * M * N * (double)K * nb,
-          [&] { launch_gemm(st, nb, mode, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K); });
+          [&] { launch_gemm(st, nb, mode, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta); });
   }
   int lq(int nb, double *X, int64_t sX, int m, int n, double *L, int64_t sL, double *Q, int64_t sQ, double *T,
-         int64_t sT, bool tr = false) {
+         int64_t sT, bool tr = false, int ldl = 0, int ldq = 0) {
     int rc = 0;
-    timed(THC_K_LQ, lq_flops(m, n) * nb, [&] { rc = launch_lq(st, nb, X, sX, m, n, L, sL, Q, sQ, T, sT, tr); });
+    timed(THC_K_LQ, lq_flops(m, n) * nb,
+          [&] { rc = launch_lq(st, nb, X, sX, m, n, L, sL, Q, sQ, T, sT, tr, ldl, ldq); });
     return rc;
   }
   int sytrd(int nb, double *A, int64_t sA, int m, double *d, double *e, double *tau, int64_t sv) {
@@ -445,6 +491,94 @@ struct Engine {
     return (CJob *)d;
   }
 
+  // Structured R->L sweep for right-canonical inputs: Q_j = [[A_j | 0] ; Q0_j]
+  // with Q0_j from the LQ of the rest rows projected on the complement of
+  // [A_j | 0]; L'_j = [P_j | L0_j] carries the rest rows to site j-1.  Q_j
+  // is stored transposed, as in the plain sweep.
+  int64_t structured_sweep(const Plan &P, CJob *dj, int nb) {
+    const int n = P.n;
+    const int64_t S = P.per_job;
+    double *W = c->ws.as<double>();
+    double *Bb = W + P.oB, *Tb = W + P.oT, *Qs = W + P.oQs, *Mb = W + P.oM, *Tf = W + P.oTf;
+    const int64_t slt = (P.sLt + 31) / 32 * 32;
+    double *Lt[2] = {W + P.oLt, W + P.oLt + slt};
+    int cur = 0;  // Lt[cur]: L' of site j+1
+    int64_t launches = 0;
+    // right boundary: no rest part for a layer, the shared boundary state for a sum
+    if (P.lr[n] > 0) {
+      launch_fill(st, nb, Lt[cur], S, 1, 1.0);
+      ++launches;
+    }
+    const int srcw = (P.kind == 0) ? 0 : 1;  // input holding the rest rows' source
+    for (int j = n - 1; j >= 1; --j) {
+      const int lc = P.lc[j], lr = P.lr[j], c1 = P.c[j + 1], cj = P.c[j], lr1 = P.lr[j + 1];
+      const int ra = P.pa.b[j + 1];
+      const int rsrc = (P.kind == 0) ? P.pa.b[j + 1] : P.pb.b[j + 1];
+      const int64_t off_src = (P.kind == 0) ? P.pa.off[j] : P.pb.off[j];
+      double *Qt = Qs + P.qs_off[j];
+      double *Lnew = Lt[1 - cur];
+      // canonical rows [A_j | 0] -> columns 0..lc-1 of Q_j^T
+      launch_canon_pack(st, nb, dj, P.pa.off[j], lc, ra, c1, Qt, S, cj);
+      // rest rows, transposed: RT = (src L')^T (2 c1 x lr), one GEMM per physical index
+      launch_gather(st, nb, dj, srcw, off_src, Bb, S, (int64_t)lr * 2 * rsrc);
+      for (int sg = 0; sg < 2; ++sg)
+        gemm(nb, GEMM_TA | GEMM_TB, Lt[cur], S, c1, Bb + sg * rsrc, S, 2 * rsrc, Tb + (int64_t)sg * c1 * lr, S, lr,
+             c1, lr, lr1);
+      if (P.kind == 0) launch_rest_post(st, nb, dj, j, P.pa.off[j], lr, ra, c1, Tb, S);
+      // P_j = X_rest X_canon^T (lr x lc) -> columns 0..lc-1 of L'_j
+      gemm(nb, GEMM_TA, Tb, S, lr, Qt, S, cj, Lnew, S, cj, lr, lc, 2 * c1);
+      // X_rest -= P_j X_canon (transposed: RT -= X_canon^T P_j^T)
+      gemm(nb, GEMM_TB, Qt, S, cj, Lnew, S, cj, Tb, S, lr, 2 * c1, lr, lc, -1.0, 1.0);
+      // LQ of the remainder: Q0_j -> columns lc.. of Q_j^T, L0_j -> columns lc.. of L'_j
+      if (P.c0[j] > 0) {
+        if (lq(nb, Tb, S, lr, 2 * c1, Lnew + lc, S, Qt + lc, S, Tf, S, true, cj, cj) != 0)
+          raise(THC_EINVAL, "site matrix too wide for the LQ kernel (2*bond > 1024)");
+      }
+      launches += 8;
+      cur = 1 - cur;
+    }
+    // site 0: M_0 (2 x c_1)
+    {
+      const int lr1 = P.lr[1], c1 = P.c[1];
+      const int rsrc = (P.kind == 0) ? P.pa.b[1] : P.pb.b[1];
+      const int64_t off_src = (P.kind == 0) ? P.pa.off[0] : P.pb.off[0];
+      launch_gather(st, nb, dj, srcw, off_src, Bb, S, (int64_t)2 * rsrc);
+      gemm(nb, 0, Bb, S, rsrc, Lt[cur], S, c1, Mb, S, c1, 2, c1, lr1);
+      launch_site0(st, nb, dj, P.pa.off[0], P.pa.b[1], c1, Mb, S);
+      launches += 3;
+    }
+    return launches;
+  }
+
+  // Right-canonical form of the compressed outputs (in their slots): R->L
+  // LQ sweep X_j = U_j L_{j+1} = L_j Q_j, site 0 absorbs L_1 and carries the
+  // norm.  The state is unchanged (a change of gauge).
+  int64_t recanon(const Plan &P, CJob *dj, int nb) {
+    const int n = P.n;
+    if (n < 2) return 0;
+    const int64_t S = P.per_job;
+    double *W = c->ws.as<double>();
+    double *Bb = W + P.oB, *Tb = W + P.oT, *Lb = W + P.oL, *Yb = W + P.oY, *Tf = W + P.oTf;
+    int64_t launches = 0;
+    for (int j = n - 1; j >= 1; --j) {
+      const int kj = P.k[j], kj1 = P.k[j + 1];
+      if (j == n - 1) {
+        launch_gather(st, nb, dj, 2, P.out.off[j], Tb, S, (int64_t)kj * 2 * kj1);
+      } else {
+        launch_gather(st, nb, dj, 2, P.out.off[j], Bb, S, (int64_t)kj * 2 * kj1);
+        gemm(nb, 0, Bb, S, kj1, Lb, S, kj1, Tb, S, kj1, 2 * kj, kj1, kj1);
+      }
+      if (lq(nb, Tb, S, kj, 2 * kj1, Lb, S, Yb, S, Tf, S) != 0)
+        raise(THC_EINVAL, "site matrix too wide for the LQ kernel (2*bond > 1024)");
+      launch_scatter(st, nb, dj, P.out.off[j], Yb, S, (int64_t)kj * 2 * kj1);
+      launches += 4;
+    }
+    launch_gather(st, nb, dj, 2, P.out.off[0], Bb, S, (int64_t)2 * P.k[1]);
+    gemm(nb, 0, Bb, S, P.k[1], Lb, S, P.k[1], Yb, S, P.k[1], 2, P.k[1], P.k[1]);
+    launch_scatter(st, nb, dj, P.out.off[0], Yb, S, (int64_t)2 * P.k[1]);
+    return launches + 3;
+  }
+
   // Run the compression of nb jobs (same plan).  Output slots in jobs[].out.
   void compress(const Plan &P, const std::vector<CJob> &hjobs, int D) {
     const int nb = (int)hjobs.size();
@@ -462,39 +596,43 @@ struct Engine {
            *Wb = W + P.oW, *Zb = W + P.oZ, *Cb = W + P.oC, *Lz = W + P.oLz, *Qz = W + P.oQz, *Tf = W + P.oTf,
            *Sb = W + P.oS, *Ub = W + P.oU;
     int64_t launches = 0;
-    // ---- right -> left LQ sweep ----
-    for (int j = n - 1; j >= 1; --j) {
-      const int la = P.pa.b[j], ra = P.pa.b[j + 1];
-      const int lb = P.kind ? P.pb.b[j] : 0, rb = P.kind ? P.pb.b[j + 1] : 0;
-      launch_construct(st, dj, nb, j, n, P.pa.off[j], P.kind ? P.pb.off[j] : 0, la, ra, lb, rb, Bb, S, P.bo[j],
-                       P.bo[j + 1]);
-      ++launches;
-      // X_j = B_j L_{j+1} (bo_j x 2 c_{j+1}) is handed to the LQ kernel
-      // transposed; the kernel returns Q_j transposed (2 c_{j+1} x c_j)
-      if (j == n - 1) {
-        launch_transpose(st, nb, Bb, S, P.bo[j], 2, Tb, S);
-      } else {
-        // X_j^T = [(B_j^0 L)^T ; (B_j^1 L)^T], B_j^s = B_j[:, s, :]: one GEMM per
-        // physical index with both operands read transposed
-        for (int sg = 0; sg < 2; ++sg)
-          gemm(nb, GEMM_TA | GEMM_TB, Lb, S, P.c[j + 1], Bb + sg * P.bo[j + 1], S, 2 * P.bo[j + 1],
-               Tb + (int64_t)sg * P.c[j + 1] * P.bo[j], S, P.bo[j], P.c[j + 1], P.bo[j], P.bo[j + 1]);
+    if (P.mode == 1) {
+      launches += structured_sweep(P, dj, nb);
+    } else {
+      // ---- right -> left LQ sweep ----
+      for (int j = n - 1; j >= 1; --j) {
+        const int la = P.pa.b[j], ra = P.pa.b[j + 1];
+        const int lb = P.kind ? P.pb.b[j] : 0, rb = P.kind ? P.pb.b[j + 1] : 0;
+        launch_construct(st, dj, nb, j, n, P.pa.off[j], P.kind ? P.pb.off[j] : 0, la, ra, lb, rb, Bb, S, P.bo[j],
+                         P.bo[j + 1]);
+        ++launches;
+        // X_j = B_j L_{j+1} (bo_j x 2 c_{j+1}) is handed to the LQ kernel
+        // transposed; the kernel returns Q_j transposed (2 c_{j+1} x c_j)
+        if (j == n - 1) {
+          launch_transpose(st, nb, Bb, S, P.bo[j], 2, Tb, S);
+        } else {
+          // X_j^T = [(B_j^0 L)^T ; (B_j^1 L)^T], B_j^s = B_j[:, s, :]: one GEMM per
+          // physical index with both operands read transposed
+          for (int sg = 0; sg < 2; ++sg)
+            gemm(nb, GEMM_TA | GEMM_TB, Lb, S, P.c[j + 1], Bb + sg * P.bo[j + 1], S, 2 * P.bo[j + 1],
+                 Tb + (int64_t)sg * P.c[j + 1] * P.bo[j], S, P.bo[j], P.c[j + 1], P.bo[j], P.bo[j + 1]);
+        }
+        ++launches;
+        if (lq(nb, Tb, S, P.bo[j], 2 * P.c[j + 1], Lb, S, Qs + P.qs_off[j], S, Tf, S, true) != 0)
+          raise(THC_EINVAL, "site matrix too wide for the LQ kernel (2*bond > 1024)");
       }
-      ++launches;
-      if (lq(nb, Tb, S, P.bo[j], 2 * P.c[j + 1], Lb, S, Qs + P.qs_off[j], S, Tf, S, true) != 0)
-        raise(THC_EINVAL, "site matrix too wide for the LQ kernel (2*bond > 1024)");
-    }
-    // site 0: M_0 = B_0 * L_1 (1, 2, c_1)
-    {
-      const int la = P.pa.b[0], ra = P.pa.b[1];
-      const int lb = P.kind ? P.pb.b[0] : 0, rb = P.kind ? P.pb.b[1] : 0;
-      launch_construct(st, dj, nb, 0, n, P.pa.off[0], P.kind ? P.pb.off[0] : 0, la, ra, lb, rb, Bb, S, P.bo[0],
-                       P.bo[1]);
-      if (n > 1)
-        gemm(nb, 0, Bb, S, P.bo[1], Lb, S, P.c[1], Mb, S, P.c[1], 2, P.c[1], P.bo[1]);
-      else
-        launch_copy(st, nb, Bb, S, Mb, S, 2);
-      launches += 2;
+      // site 0: M_0 = B_0 * L_1 (1, 2, c_1)
+      {
+        const int la = P.pa.b[0], ra = P.pa.b[1];
+        const int lb = P.kind ? P.pb.b[0] : 0, rb = P.kind ? P.pb.b[1] : 0;
+        launch_construct(st, dj, nb, 0, n, P.pa.off[0], P.kind ? P.pb.off[0] : 0, la, ra, lb, rb, Bb, S, P.bo[0],
+                         P.bo[1]);
+        if (n > 1)
+          gemm(nb, 0, Bb, S, P.bo[1], Lb, S, P.c[1], Mb, S, P.c[1], 2, P.c[1], P.bo[1]);
+        else
+          launch_copy(st, nb, Bb, S, Mb, S, 2);
+        launches += 2;
+      }
     }
     int *rk_d = rk.as<int>();
     double *dw_d = dw.as<double>();
@@ -550,6 +688,8 @@ struct Engine {
     // last site
     launch_scatter(st, nb, dj, P.out.off[n - 1], Mb, S, (int64_t)P.k[n - 1] * 2);
     ++launches;
+    // outputs in right-canonical form (inputs of later structured sweeps)
+    launches += recanon(P, dj, nb);
     HIPCHK(hipGetLastError());
     // statistics: read back ranks/disc/sweeps of this batch (async into host arrays after sync at end)
     h_rank.resize((size_t)nb * n);
@@ -654,6 +794,7 @@ struct Node {
   Profile prof;
   double coef = 1.0;
   bool owned = true;       // slot from the pool (vs caller memory)
+  bool rc = false;         // sites 1..n-1 right-canonical
   std::vector<int> ranks;  // numerical ranks at bonds 1..n-1 (empty: unknown)
 };
 
@@ -713,39 +854,45 @@ struct JobSpec {
   const Node *b;
   const double *y;
   int dag;
-  double scale;  // for layer jobs (multiplies the last site)
+  double scale;  // for layer jobs (multiplies site 0)
 };
 
 // Run a list of job specs (any mix of signatures); returns output nodes in order.
 std::vector<Node> run_jobs(Engine &E, const std::vector<JobSpec> &specs, int D) {
   thc_ctx *c = E.c;
   std::vector<Node> out(specs.size());
-  // group by signature
+  // a sum is symmetric: put a right-canonical term first, where the
+  // structured sweep can use it
+  std::vector<JobSpec> sp = specs;
+  for (JobSpec &s : sp)
+    if (s.kind == 1 && !s.a->rc && s.b->rc) std::swap(s.a, s.b);
+  // group by signature (kind, bonds, canonical form of the first input)
   std::map<std::pair<int, std::pair<std::vector<int>, std::vector<int>>>, std::vector<size_t>> groups;
-  for (size_t i = 0; i < specs.size(); ++i) {
-    const JobSpec &s = specs[i];
-    auto key = std::make_pair(s.kind, std::make_pair(s.a->prof.b, s.kind ? s.b->prof.b : std::vector<int>()));
+  for (size_t i = 0; i < sp.size(); ++i) {
+    const JobSpec &s = sp[i];
+    const int kk = s.kind + (s.a->rc ? 2 : 0);
+    auto key = std::make_pair(kk, std::make_pair(s.a->prof.b, s.kind ? s.b->prof.b : std::vector<int>()));
     groups[key].push_back(i);
   }
   for (auto &g : groups) {
-    const JobSpec &s0 = specs[g.second[0]];
+    const JobSpec &s0 = sp[g.second[0]];
     // all members share offsets too? profiles with equal bonds in slots are packed the same way;
     // caller-owned inputs may have other offsets, so split by offsets as well
     std::map<std::pair<std::vector<int64_t>, std::vector<int64_t>>, std::vector<size_t>> sub;
     for (size_t i : g.second) {
-      const JobSpec &s = specs[i];
+      const JobSpec &s = sp[i];
       sub[{s.a->prof.off, s.kind ? s.b->prof.off : std::vector<int64_t>()}].push_back(i);
     }
     for (auto &sg : sub) {
-      const JobSpec &sf = specs[sg.second[0]];
-      Plan P = make_plan(sf.kind, sf.a->prof, sf.kind ? &sf.b->prof : nullptr, D);
+      const JobSpec &sf = sp[sg.second[0]];
+      Plan P = make_plan(sf.kind, sf.a->prof, sf.kind ? &sf.b->prof : nullptr, D, sf.a->rc);
       int B = E.batch_limit(P);
       for (size_t i0 = 0; i0 < sg.second.size(); i0 += B) {
         size_t i1 = std::min(sg.second.size(), i0 + B);
         std::vector<CJob> hj;
         for (size_t t = i0; t < i1; ++t) {
           size_t i = sg.second[t];
-          const JobSpec &s = specs[i];
+          const JobSpec &s = sp[i];
           CJob j{};
           j.kind = s.kind;
           j.in_a = s.a->data;
@@ -763,6 +910,7 @@ std::vector<Node> run_jobs(Engine &E, const std::vector<JobSpec> &specs, int D) 
           out[i].prof = P.out;
           out[i].coef = 1.0;
           out[i].owned = true;
+          out[i].rc = true;
           j.out = out[i].data;
           hj.push_back(j);
         }
@@ -875,13 +1023,15 @@ void emit(Engine &E, const Node &nd, thc_mps *out) {
   std::vector<int64_t> doff;
   repack(E.st, nd.data, nd.prof, out->data, r, doff);
   if (nd.coef != 1.0) {
-    // apply a pending coefficient to the last site
-    int64_t cnt = (int64_t)r[n - 1] * 2 * r[n];
-    launch_scale(E.st, out->data + doff[n - 1], cnt, nd.coef);
+    // apply a pending coefficient to site 0 (keeps sites 1..n-1 as they are)
+    int64_t cnt = (int64_t)r[0] * 2 * r[1];
+    launch_scale(E.st, out->data + doff[0], cnt, nd.coef);
   }
   HIPCHK(hipGetLastError());
   for (int j = 0; j <= n; ++j) out->bonds[j] = r[j];
   for (int j = 0; j < n; ++j) out->offsets[j] = doff[j];
+  out->canonical = nd.rc ? 1 : 0;
+  out->reserved = 0;
 }
 
 Node caller_node(const thc_mps *m) {
@@ -890,6 +1040,7 @@ Node caller_node(const thc_mps *m) {
   nd.prof = profile_of(m);
   nd.coef = 1.0;
   nd.owned = false;
+  nd.rc = m->canonical != 0;
   return nd;
 }
 
@@ -1295,6 +1446,7 @@ struct thc_krylov {
   std::vector<std::unique_ptr<DevBuf>> vbuf, wbuf;
   std::vector<std::vector<int>> vb, wb;          // bonds
   std::vector<std::vector<int64_t>> vo, wo;      // offsets
+  std::vector<int> vc, wc;                       // right-canonical flags
   std::vector<double> Mm, S, alpha, beta;        // host mirrors, (K+1)^2
   DevBuf dM, dS, dA, dB, dOutG, dOutT, dInfo;
 };
@@ -1310,6 +1462,7 @@ thc_mps view(thc_krylov *k, bool isw, int i) {
   m.offsets = o.data();
   m.data = (isw ? k->wbuf[i] : k->vbuf[i])->as<double>();
   m.capacity = k->cap;
+  m.canonical = isw ? k->wc[i] : k->vc[i];
   return m;
 }
 }  // namespace
@@ -1340,25 +1493,27 @@ thc_status krylov_create(thc_ctx *ctx, const thc_mps *psi0, int32_t K, const thc
       k->vbuf.back()->ensure((size_t)k->cap * sizeof(double));
       k->vb.push_back(std::vector<int>(k->n + 1, 1));
       k->vo.push_back(std::vector<int64_t>(k->n, 0));
+      k->vc.push_back(0);
     }
     for (int i = 0; i < K; ++i) {
       k->wbuf.push_back(std::make_unique<DevBuf>());
       k->wbuf.back()->ensure((size_t)k->cap * sizeof(double));
       k->wb.push_back(std::vector<int>(k->n + 1, 1));
       k->wo.push_back(std::vector<int64_t>(k->n, 0));
+      k->wc.push_back(0);
     }
     hipStream_t st = (hipStream_t)hip_stream;
-    // v_0 = psi0 / ||psi0|| (copied as given, then scaled on the last site)
+    // v_0 = psi0 / ||psi0|| (copied as given, then scaled on site 0)
     k->vb[0].assign(psi0->bonds, psi0->bonds + k->n + 1);
     k->vo[0].assign(psi0->offsets, psi0->offsets + k->n);
+    k->vc[0] = psi0->canonical != 0;
     HIPCHK(hipMemcpyAsync(k->vbuf[0]->p, psi0->data, (size_t)in_size * sizeof(double), hipMemcpyDeviceToDevice, st));
     thc_mps v0 = view(k.get(), false, 0);
     double nn = 0.0;
     thc_status r = mps_overlap(ctx, &v0, &v0, &nn, hip_stream);
     if (r != THC_OK) raise(r, thc_last_error());
     if (!(nn > 0.0) || !std::isfinite(nn)) raise(THC_EINVAL, "start vector has zero or non-finite norm");
-    const int nl = k->n - 1;
-    launch_scale(st, k->vbuf[0]->as<double>() + k->vo[0][nl], (int64_t)k->vb[0][nl] * 2 * k->vb[0][nl + 1],
+    launch_scale(st, k->vbuf[0]->as<double>() + k->vo[0][0], (int64_t)k->vb[0][0] * 2 * k->vb[0][1],
                  1.0 / std::sqrt(nn));
     int R = K + 1;
     k->Mm.assign(R * R, 0.0);
@@ -1401,6 +1556,7 @@ thc_status krylov_step(thc_krylov *k, double *ritz_gen, double *ritz_tri, double
     thc_mps wi = view(k, true, i);
     thc_status r = mps_apply_thc_H(ctx, &vi, &wi, &k->o, &s1, hip_stream);
     if (r != THC_OK) raise(r, thc_last_error());
+    k->wc[i] = wi.canonical;
     // h_ji = <v_j|w_i>
     for (int j = 0; j <= i; ++j) {
       thc_mps vj = view(k, false, j);
@@ -1422,6 +1578,7 @@ thc_status krylov_step(thc_krylov *k, double *ritz_gen, double *ritz_tri, double
     thc_mps vn = view(k, false, i + 1);
     r = mps_sum_compress(ctx, (int)co.size(), co.data(), ptrs.data(), &vn, &k->o, &s2, hip_stream);
     if (r != THC_OK) raise(r, thc_last_error());
+    k->vc[i + 1] = vn.canonical;
     double rr = 0.0;
     r = mps_overlap(ctx, &vn, &vn, &rr, hip_stream);
     if (r != THC_OK) raise(r, thc_last_error());
@@ -1429,9 +1586,8 @@ thc_status krylov_step(thc_krylov *k, double *ritz_gen, double *ritz_tri, double
     k->beta.push_back(b);
     hipStream_t st_ = (hipStream_t)hip_stream;
     if (b > 0.0) {
-      const int nl = k->n - 1;
-      launch_scale(st_, k->vbuf[i + 1]->as<double>() + k->vo[i + 1][nl],
-                   (int64_t)k->vb[i + 1][nl] * 2 * k->vb[i + 1][nl + 1], 1.0 / b);
+      launch_scale(st_, k->vbuf[i + 1]->as<double>() + k->vo[i + 1][0],
+                   (int64_t)k->vb[i + 1][0] * 2 * k->vb[i + 1][1], 1.0 / b);
       HIPCHK(hipGetLastError());
       for (int j = 0; j <= i + 1; ++j) {
         thc_mps a = view(k, false, i + 1), bj = view(k, false, j);
@@ -1494,6 +1650,8 @@ thc_status krylov_get_vector(thc_krylov *k, int32_t i, thc_mps *out, void *hip_s
                           (hipStream_t)hip_stream));
     for (int j = 0; j <= k->n; ++j) out->bonds[j] = k->vb[i][j];
     for (int j = 0; j < k->n; ++j) out->offsets[j] = k->vo[i][j];
+    out->canonical = k->vc[i];
+    out->reserved = 0;
     HIPCHK(hipStreamSynchronize((hipStream_t)hip_stream));
   });
 }

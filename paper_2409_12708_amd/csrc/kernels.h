@@ -9,7 +9,7 @@ namespace thck {
 
 // One compression job: construct a bond-2D MPS from one or two inputs, then
 // compress it.  kind 0 = layer  sum_j y_j a_j (dag 0) or a+_j (dag 1) applied
-// to in_a, the last site scaled by ca; kind 1 = direct sum ca*in_a + cb*in_b.
+// to in_a, site 0 scaled by ca; kind 1 = direct sum ca*in_a + cb*in_b.
 struct CJob {
   const double *in_a;
   const double *in_b;
@@ -29,14 +29,17 @@ void launch_construct(hipStream_t st, const CJob *jobs, int nb, int site, int n_
                       int ro);
 // GEMM modes (bits): B given transposed, A given transposed.
 constexpr int GEMM_TB = 1, GEMM_TA = 2;
+// C = alpha op(A) op(B) + beta C (beta = 0: C is not read).
 void launch_gemm(hipStream_t st, int nb, int mode, const double *A, int64_t sA, int lda, const double *B,
-                 int64_t sB, int ldb, double *C, int64_t sC, int ldc, int M, int N, int K);
+                 int64_t sB, int ldb, double *C, int64_t sC, int ldc, int M, int N, int K, double alpha = 1.0,
+                 double beta = 0.0);
 void launch_transpose(hipStream_t st, int nb, const double *src, int64_t ss, int r, int c, double *dst, int64_t sd);
-// LQ of X (m x n): L (m x min(m,n), row-major), Q (min(m,n) x n).  With tr,
-// X is given transposed (n x m row-major) and Q is returned transposed
-// (n x min(m,n) row-major); L keeps its layout.
+// LQ of X (m x n), k = min(m, n): L (m x k, row stride ldl), Q (k x n, row
+// stride ldq).  With tr, X is given transposed (n x m row-major) and Q is
+// returned transposed (n x k, row stride ldq); L keeps its layout.  ldl /
+// ldq <= 0 select the dense strides.
 int launch_lq(hipStream_t st, int nb, double *X, int64_t sX, int m, int n, double *L, int64_t sL, double *Q,
-              int64_t sQ, double *Tw, int64_t sT, bool tr = false);
+              int64_t sQ, double *Tw, int64_t sT, bool tr = false, int ldl = 0, int ldq = 0);
 int launch_jacobi(hipStream_t st, int nb, double *Y, int64_t sY, int m, int n, double *s, int64_t ss, int *sweeps,
                   int max_sweeps);
 void launch_svd_select(hipStream_t st, int nb, const double *Y, int64_t sY, int m, int n, const double *s,
@@ -44,7 +47,15 @@ void launch_svd_select(hipStream_t st, int nb, const double *Y, int64_t sY, int 
                        double *sv_out, int64_t ssv);
 void launch_svd_finish(hipStream_t st, int nb, const double *Q, int64_t sQ, int m, int kk, const int *rank,
                        double *U, int64_t sU, double *C, int64_t sC, int n);
+// Structured LQ sweep for right-canonical inputs (see kernels.hip).
+void launch_canon_pack(hipStream_t st, int nb, const CJob *jobs, int64_t in_off, int lc, int ra, int c1, double *Qt,
+                       int64_t sQ, int ldq);
+void launch_rest_post(hipStream_t st, int nb, const CJob *jobs, int site, int64_t in_off, int lr, int ra, int c1,
+                      double *RT, int64_t sR);
+void launch_site0(hipStream_t st, int nb, const CJob *jobs, int64_t in_off, int ra, int c1, double *M, int64_t sM);
+void launch_fill(hipStream_t st, int nb, double *p, int64_t stride, int64_t count, double v);
 void launch_copy(hipStream_t st, int nb, const double *src, int64_t ssrc, double *dst, int64_t sdst, int64_t count);
+// which: 0 = in_a, 1 = in_b, 2 = out
 void launch_gather(hipStream_t st, int nb, const CJob *jobs, int which, int64_t off, double *dst, int64_t sdst,
                    int64_t count);
 void launch_scatter(hipStream_t st, int nb, const CJob *jobs, int64_t off, const double *src, int64_t ssrc,

@@ -68,7 +68,7 @@ __device__ __forceinline__ double wave_max(double v) {
 // construct: layer MPO applied to one site, or direct sum of two MPS.
 // Layer: W_j = [[Z, y_j o], [0, I]], o = c (annihilation) or c^T (creation).
 // Output bond index (alpha, a) -> alpha * la + a; site 0 keeps alpha = 0,
-// site n-1 keeps beta = 1.  The job scale multiplies the last site.
+// site n-1 keeps beta = 1.  The job scale multiplies site 0.
 // ---------------------------------------------------------------------------
 __global__ void k_construct(const CJob *__restrict__ jobs, int site, int n_sites, int64_t in_off_a,
                             int64_t in_off_b, int la, int ra, int lb, int rb, double *__restrict__ out,
@@ -97,7 +97,7 @@ __global__ void k_construct(const CJob *__restrict__ jobs, int site, int n_sites
       } else if (alpha == 1 && beta == 1) {
         val = A[base + (int64_t)m * ra];
       }
-      if (site == n_sites - 1) val *= jb.ca;
+      if (site == 0) val *= jb.ca;
     } else {
       // direct sum: A (la,2,ra), B (lb,2,rb)
       const double *A = jb.in_a + in_off_a;
@@ -147,7 +147,7 @@ template <int MODE, int BM, int BN>
 __global__ __launch_bounds__(256) void k_gemm_mfma(const double *__restrict__ A, int64_t sA, int lda,
                                                    const double *__restrict__ B, int64_t sB, int ldb,
                                                    double *__restrict__ C, int64_t sC, int ldc, int M, int N,
-                                                   int K, int tiles_m, int tiles_n) {
+                                                   int K, int tiles_m, int tiles_n, double alpha, double beta) {
   constexpr bool TB = (MODE & GEMM_TB) != 0, TA = (MODE & GEMM_TA) != 0;
   constexpr int BK = 16;
   constexpr int WM = BM / 32, WN = BN / 32;  // 16x16 blocks per wave
@@ -258,7 +258,10 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(const double *__restrict__ A,
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int gr = m0 + wm * (BM / 2) + 16 * i + lk + 4 * r;
-        if (gr < M && gc < N) C[(int64_t)gr * ldc + gc] = acc[i][j][r];
+        if (gr < M && gc < N) {
+          double *cp = C + (int64_t)gr * ldc + gc;
+          *cp = (beta != 0.0) ? alpha * acc[i][j][r] + beta * *cp : alpha * acc[i][j][r];
+        }
       }
     }
 }
@@ -382,7 +385,7 @@ __device__ __forceinline__ void block_reflect_rows(double *__restrict__ X, int l
 template <int NMAX, bool TR>
 __global__ __launch_bounds__(512) void k_lq2(double *__restrict__ Xb, int64_t sX, int m, int n,
                                              double *__restrict__ Lb, int64_t sL, double *__restrict__ Qb,
-                                             int64_t sQ, double *__restrict__ Tb, int64_t sT) {
+                                             int64_t sQ, double *__restrict__ Tb, int64_t sT, int ldl, int ldq) {
   constexpr int NB = 16, NWV = 8;
   constexpr int VLD = NMAX + 1;     // padded row stride: rows of V fall in different LDS banks
   extern __shared__ double lds[];
@@ -519,11 +522,11 @@ __global__ __launch_bounds__(512) void k_lq2(double *__restrict__ Xb, int64_t sX
 
   for (int64_t e = tid; e < (int64_t)m * k; e += blockDim.x) {
     const int r = (int)(e / k), c = (int)(e % k);
-    Lo[e] = (c <= r) ? X[XI(r, c)] : 0.0;
+    Lo[(int64_t)r * ldl + c] = (c <= r) ? X[XI(r, c)] : 0.0;
   }
   for (int64_t e = tid; e < (int64_t)k * n; e += blockDim.x) {
     const int r = (int)(e / n), c = (int)(e % n);
-    Qo[TR ? (int64_t)c * k + r : e] = (r == c) ? 1.0 : 0.0;
+    Qo[TR ? (int64_t)c * ldq + r : (int64_t)r * ldq + c] = (r == c) ? 1.0 : 0.0;
   }
   __syncthreads();
   const int npanel = (k + NB - 1) / NB;
@@ -546,7 +549,8 @@ __global__ __launch_bounds__(512) void k_lq2(double *__restrict__ Xb, int64_t sX
     }
     __syncthreads();
     // Q_r <- Q_r - (Q_r V^T) T^T V for rows i0..k-1
-    block_reflect_rows<NWV, TR>(Qo, TR ? k : n, (int64_t)k * n * 8, i0, k, i0, w, P, VLD, TT, Wp, WT);
+    block_reflect_rows<NWV, TR>(Qo, ldq, (int64_t)(TR ? (int64_t)(n - 1) * ldq + k : (int64_t)(k - 1) * ldq + n) * 8,
+                                i0, k, i0, w, P, VLD, TT, Wp, WT);
   }
 }
 
@@ -862,10 +866,92 @@ __global__ void k_transpose(const double *__restrict__ src, int64_t ss, int r, i
   }
 }
 
+// ---------------------------------------------------------------------------
+// Right-canonical inputs (rows of sites 1..n-1 orthonormal): kernels of the
+// structured LQ sweep.  At site j the rows of the constructed tensor split
+// into "canonical" rows, [A_j | 0] with A_j the first input's site (layer:
+// the rows where the operator has already acted; sum: the first MPS), and
+// the "rest" (layer: Z A_j L' + y o A_j [I | 0]; sum: B_j L'), where
+// L' = [P | L0] is the rest block of the previous site's L factor.
+//
+// canon_pack: Qt (2 c1 x ldq, transposed Q of the site) columns 0..lc-1 get
+//   [A_j | 0]^T: Qt[(s c1 + col) ldq + a] = A_j[a][s][col] for col < ra.
+__global__ void k_canon_pack(const CJob *__restrict__ jobs, int64_t in_off, int lc, int ra, int c1,
+                             double *__restrict__ Qt, int64_t sQ, int ldq) {
+  const CJob jb = jobs[blockIdx.y];
+  const double *A = jb.in_a + in_off;
+  double *Q = Qt + (int64_t)blockIdx.y * sQ;
+  const int64_t total = (int64_t)2 * c1 * lc;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int a = (int)(e % lc);
+    const int rowq = (int)(e / lc);  // s * c1 + col
+    const int sg = rowq / c1, col = rowq % c1;
+    Q[(int64_t)rowq * ldq + a] = (col < ra) ? A[((int64_t)a * 2 + sg) * ra + col] : 0.0;
+  }
+}
+
+// rest_post (layer jobs): RT (2 c1 x lr, transposed rest rows) holds
+// (A_j L')^T; apply Z on the physical index and add y_j (o A_j) in the
+// canonical columns col < ra: RT[(s c1 + col) lr + a] = Z_s RT[..] + y_j (oA)[a][s][col].
+__global__ void k_rest_post(const CJob *__restrict__ jobs, int site, int64_t in_off, int lr, int ra, int c1,
+                            double *__restrict__ RT, int64_t sR) {
+  const CJob jb = jobs[blockIdx.y];
+  const double *A = jb.in_a + in_off;
+  double *R = RT + (int64_t)blockIdx.y * sR;
+  const double y = jb.y[site];
+  const int64_t total = (int64_t)2 * c1 * lr;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int a = (int)(e % lr);
+    const int rowq = (int)(e / lr);
+    const int sg = rowq / c1, col = rowq % c1;
+    double v = (sg == 0 ? 1.0 : -1.0) * R[e];
+    if (col < ra) {
+      // o = c (dag 0): |1> -> |0>;  o = c^T (dag 1): |0> -> |1>
+      if (jb.dag == 0 && sg == 0) v += y * A[((int64_t)a * 2 + 1) * ra + col];
+      if (jb.dag == 1 && sg == 1) v += y * A[((int64_t)a * 2 + 0) * ra + col];
+    }
+    R[e] = v;
+  }
+}
+
+// site0: M (2 x c1, the first site of the canonical-form sweep) holds T0 =
+// (rest source of site 0) L'; layer: M = ca (Z T0 + y_0 [o A_0 | 0]);
+// sum: M = cb T0 + ca [A_0 | 0].
+__global__ void k_site0(const CJob *__restrict__ jobs, int64_t in_off, int ra, int c1, double *__restrict__ Mb,
+                        int64_t sM) {
+  const CJob jb = jobs[blockIdx.y];
+  const double *A = jb.in_a + in_off;
+  double *M = Mb + (int64_t)blockIdx.y * sM;
+  for (int e = threadIdx.x; e < 2 * c1; e += blockDim.x) {
+    const int sg = e / c1, col = e % c1;
+    double v;
+    if (jb.kind == 0) {
+      v = (sg == 0 ? 1.0 : -1.0) * M[e];
+      if (col < ra) {
+        const double y = jb.y[0];
+        if (jb.dag == 0 && sg == 0) v += y * A[1 * ra + col];
+        if (jb.dag == 1 && sg == 1) v += y * A[0 * ra + col];
+      }
+      v *= jb.ca;
+    } else {
+      v = jb.cb * M[e];
+      if (col < ra) v += jb.ca * A[sg * ra + col];
+    }
+    M[e] = v;
+  }
+}
+
+// fill: p[b * stride + e] = v for e < count, batched.
+__global__ void k_fill(double *__restrict__ p, int64_t stride, int64_t count, double v) {
+  double *q = p + (int64_t)blockIdx.y * stride;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x)
+    q[e] = v;
+}
+
 __global__ void k_gather(const CJob *__restrict__ jobs, int which, int64_t off, double *__restrict__ dst,
                          int64_t sdst, int64_t count) {
   const CJob jb = jobs[blockIdx.y];
-  const double *s = (which == 0 ? jb.in_a : jb.in_b) + off;
+  const double *s = (which == 0 ? jb.in_a : (which == 1 ? jb.in_b : jb.out)) + off;
   double *d = dst + (int64_t)blockIdx.y * sdst;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x)
     d[e] = s[e];
@@ -1755,27 +1841,28 @@ void launch_construct(hipStream_t st, const CJob *jobs, int nb, int site, int n_
 
 template <int MODE>
 static void gemm_mode(hipStream_t st, int nb, const double *A, int64_t sA, int lda, const double *B, int64_t sB,
-                      int ldb, double *C, int64_t sC, int ldc, int M, int N, int K) {
+                      int ldb, double *C, int64_t sC, int ldc, int M, int N, int K, double alpha, double beta) {
   if (M > 64 && N > 64) {
     const int tm = (M + 127) / 128, tn = (N + 127) / 128;
     hipLaunchKernelGGL((k_gemm_mfma<MODE, 128, 128>), dim3(nb * tm * tn), dim3(256), 0, st, A, sA, lda, B, sB, ldb,
-                       C, sC, ldc, M, N, K, tm, tn);
+                       C, sC, ldc, M, N, K, tm, tn, alpha, beta);
   } else {
     const int tm = (M + 63) / 64, tn = (N + 63) / 64;
     hipLaunchKernelGGL((k_gemm_mfma<MODE, 64, 64>), dim3(nb * tm * tn), dim3(256), 0, st, A, sA, lda, B, sB, ldb,
-                       C, sC, ldc, M, N, K, tm, tn);
+                       C, sC, ldc, M, N, K, tm, tn, alpha, beta);
   }
 }
 
 void launch_gemm(hipStream_t st, int nb, int mode, const double *A, int64_t sA, int lda, const double *B,
-                 int64_t sB, int ldb, double *C, int64_t sC, int ldc, int M, int N, int K) {
+                 int64_t sB, int ldb, double *C, int64_t sC, int ldc, int M, int N, int K, double alpha,
+                 double beta) {
   if (nb <= 0 || M <= 0 || N <= 0) return;
   switch (mode) {
-    case 0: gemm_mode<0>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K); break;
-    case GEMM_TB: gemm_mode<GEMM_TB>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K); break;
-    case GEMM_TA: gemm_mode<GEMM_TA>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K); break;
+    case 0: gemm_mode<0>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta); break;
+    case GEMM_TB: gemm_mode<GEMM_TB>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta); break;
+    case GEMM_TA: gemm_mode<GEMM_TA>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta); break;
     case GEMM_TA | GEMM_TB:
-      gemm_mode<GEMM_TA | GEMM_TB>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K);
+      gemm_mode<GEMM_TA | GEMM_TB>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta);
       break;
     default: break;
   }
@@ -1792,7 +1879,10 @@ static void set_lds(K kern, size_t lds) {
 }
 
 int launch_lq(hipStream_t st, int nb, double *X, int64_t sX, int m, int n, double *L, int64_t sL, double *Q,
-              int64_t sQ, double *Tw, int64_t sT, bool tr) {
+              int64_t sQ, double *Tw, int64_t sT, bool tr, int ldl, int ldq) {
+  const int k = m < n ? m : n;
+  if (ldl <= 0) ldl = k;
+  if (ldq <= 0) ldq = tr ? k : n;
   if (n > 1024) return -1;
   constexpr int NMAX = 1024, NWV = 8;
   const size_t lds = (16 * (NMAX + 1) + 256 + 256 + (NWV + 1) * 256 + 256 + 16 + 256) * sizeof(double);
@@ -1803,9 +1893,11 @@ int launch_lq(hipStream_t st, int nb, double *X, int64_t sX, int m, int n, doubl
     attr[tr] = true;
   }
   if (tr)
-    hipLaunchKernelGGL((k_lq2<NMAX, true>), dim3(nb), dim3(512), lds, st, X, sX, m, n, L, sL, Q, sQ, Tw, sT);
+    hipLaunchKernelGGL((k_lq2<NMAX, true>), dim3(nb), dim3(512), lds, st, X, sX, m, n, L, sL, Q, sQ, Tw, sT, ldl,
+                       ldq);
   else
-    hipLaunchKernelGGL((k_lq2<NMAX, false>), dim3(nb), dim3(512), lds, st, X, sX, m, n, L, sL, Q, sQ, Tw, sT);
+    hipLaunchKernelGGL((k_lq2<NMAX, false>), dim3(nb), dim3(512), lds, st, X, sX, m, n, L, sL, Q, sQ, Tw, sT, ldl,
+                       ldq);
   return 0;
 }
 
@@ -1860,6 +1952,36 @@ void launch_transpose(hipStream_t st, int nb, const double *src, int64_t ss, int
   if (gx > 1024) gx = 1024;
   if (gx < 1) gx = 1;
   hipLaunchKernelGGL(k_transpose, dim3(gx, nb), dim3(256), 0, st, src, ss, r, c, dst, sd);
+}
+
+void launch_canon_pack(hipStream_t st, int nb, const CJob *jobs, int64_t in_off, int lc, int ra, int c1, double *Qt,
+                       int64_t sQ, int ldq) {
+  const int64_t total = (int64_t)2 * c1 * lc;
+  if (nb <= 0 || total <= 0) return;
+  int gx = (int)cdiv64(total, 256);
+  if (gx > 1024) gx = 1024;
+  hipLaunchKernelGGL(k_canon_pack, dim3(gx, nb), dim3(256), 0, st, jobs, in_off, lc, ra, c1, Qt, sQ, ldq);
+}
+
+void launch_rest_post(hipStream_t st, int nb, const CJob *jobs, int site, int64_t in_off, int lr, int ra, int c1,
+                      double *RT, int64_t sR) {
+  const int64_t total = (int64_t)2 * c1 * lr;
+  if (nb <= 0 || total <= 0) return;
+  int gx = (int)cdiv64(total, 256);
+  if (gx > 1024) gx = 1024;
+  hipLaunchKernelGGL(k_rest_post, dim3(gx, nb), dim3(256), 0, st, jobs, site, in_off, lr, ra, c1, RT, sR);
+}
+
+void launch_site0(hipStream_t st, int nb, const CJob *jobs, int64_t in_off, int ra, int c1, double *M, int64_t sM) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL(k_site0, dim3(1, nb), dim3(256), 0, st, jobs, in_off, ra, c1, M, sM);
+}
+
+void launch_fill(hipStream_t st, int nb, double *p, int64_t stride, int64_t count, double v) {
+  if (nb <= 0 || count <= 0) return;
+  int gx = (int)cdiv64(count, 256);
+  if (gx > 1024) gx = 1024;
+  hipLaunchKernelGGL(k_fill, dim3(gx, nb), dim3(256), 0, st, p, stride, count, v);
 }
 
 void launch_copy(hipStream_t st, int nb, const double *src, int64_t ssrc, double *dst, int64_t sdst, int64_t count) {

@@ -34,6 +34,8 @@ class ThcMps(C.Structure):
         ("offsets", C.POINTER(C.c_int64)),
         ("data", C.c_void_p),
         ("capacity", C.c_int64),
+        ("canonical", C.c_int32),
+        ("reserved", C.c_int32),
     ]
 
 
@@ -164,9 +166,12 @@ class DeviceMPS:
         self.offsets = (C.c_int64 * self.n)()
         for j in range(self.n):
             self.offsets[j] = 2 * j
+        # sites 1..n-1 right-canonical (declared by the caller, or set by the
+        # library on the MPS it writes)
+        self.canonical = False
 
     @classmethod
-    def from_sites(cls, sites, device="cuda", capacity_elems=None):
+    def from_sites(cls, sites, device="cuda", capacity_elems=None, canonical=False):
         n = len(sites)
         sizes = [int(np.prod(a.shape)) for a in sites]
         cap = sum(sizes) if capacity_elems is None else max(capacity_elems, sum(sizes))
@@ -179,6 +184,7 @@ class DeviceMPS:
             m.offsets[j] = o
             o += sizes[j]
         m.bonds[n] = sites[-1].shape[2]
+        m.canonical = bool(canonical)
         return m
 
     def bond_list(self):
@@ -201,7 +207,13 @@ class DeviceMPS:
         d.offsets = C.cast(self.offsets, C.POINTER(C.c_int64))
         d.data = C.c_void_p(self.buf.data_ptr())
         d.capacity = self.buf.numel()
+        d.canonical = int(bool(self.canonical))
+        d.reserved = 0
         return d
+
+    def _written(self, d: ThcMps) -> "DeviceMPS":
+        self.canonical = bool(d.canonical)
+        return self
 
 
 class Context:
@@ -241,7 +253,7 @@ class Context:
         pd, od = psi.desc(), out.desc()
         _check(self.lib.mps_apply_thc_H(self.h, C.byref(pd), C.byref(od), C.byref(o),
                                         C.byref(stats) if stats is not None else None, _stream()))
-        return out
+        return out._written(od)
 
     def sum_compress(self, coeffs, terms, D: int, stats: ThcStats | None = None, **kw) -> DeviceMPS:
         o = make_opts(D, **kw)
@@ -253,7 +265,7 @@ class Context:
         od = out.desc()
         _check(self.lib.mps_sum_compress(self.h, k, co, arr, C.byref(od), C.byref(o),
                                          C.byref(stats) if stats is not None else None, _stream()))
-        return out
+        return out._written(od)
 
     def compress(self, psi: DeviceMPS, D: int, stats: ThcStats | None = None, **kw) -> DeviceMPS:
         o = make_opts(D, **kw)
@@ -261,7 +273,7 @@ class Context:
         pd, od = psi.desc(), out.desc()
         _check(self.lib.mps_compress(self.h, C.byref(pd), C.byref(od), C.byref(o),
                                      C.byref(stats) if stats is not None else None, _stream()))
-        return out
+        return out._written(od)
 
     def apply_layer(self, psi: DeviceMPS, y, dag: bool, D: int, stats: ThcStats | None = None, **kw) -> DeviceMPS:
         o = make_opts(D, **kw)
@@ -270,7 +282,7 @@ class Context:
         pd, od = psi.desc(), out.desc()
         _check(self.lib.mps_apply_layer(self.h, C.byref(pd), _dptr(y), int(bool(dag)), C.byref(od), C.byref(o),
                                         C.byref(stats) if stats is not None else None, _stream()))
-        return out
+        return out._written(od)
 
     def overlap(self, a: DeviceMPS, b: DeviceMPS) -> float:
         r = C.c_double()
@@ -309,7 +321,7 @@ class Krylov:
         out = DeviceMPS(self.ctx.n, max(capacity(self.ctx.n, D), 1), self.ctx.device)
         od = out.desc()
         _check(self.ctx.lib.krylov_get_vector(self.h, int(i), C.byref(od), _stream()))
-        return out
+        return out._written(od)
 
     def matrices(self):
         m = C.c_int32()

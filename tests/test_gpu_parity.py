@@ -101,8 +101,9 @@ def test_sum_compress_untruncated(thck, k):
     out = ctx.sum_compress(coeffs, [thck.DeviceMPS.from_sites(x) for x in terms], D=16)
     ref = sum(c * M.to_dense(x) for c, x in zip(coeffs, terms))
     assert _rel(M.to_dense(out.to_sites()), ref) < 1e-12
-    # the output is left-canonical (sites 0..n-2 are isometries)
-    assert M.left_canonical_error(out.to_sites()) < 1e-12
+    # the output is right-canonical (sites 1..n-1 have orthonormal rows) and says so
+    assert M.right_canonical_error(out.to_sites()) < 1e-12
+    assert out.canonical
 
 
 def test_sum_compress_truncated_tree_order(thck):
@@ -219,3 +220,93 @@ def test_kernel_timing_flag(thck):
             assert fl > 0.0
     # one LQ per site of the canonical sweep and one per bond of the SVD sweep
     assert k1["lq"][2] == 2 * k1["sytrd"][2] or k1["lq"][2] > k1["sytrd"][2]
+
+
+# ---------------------------------------------------------------------------
+# Right-canonical inputs: the structured orthogonalisation sweep keeps the
+# input's orthonormal rows and factorises only the rest.  The compressed
+# state must be the one the plain sweep gives.
+# ---------------------------------------------------------------------------
+
+def _rc_mps(rng, n, D):
+    return M.right_canonicalize(_norm_mps(rng, n, D))
+
+
+@pytest.mark.parametrize("dag", [0, 1])
+@pytest.mark.parametrize("D", [16, 4])
+def test_layer_compress_canonical_input(thck, dag, D):
+    rng = np.random.default_rng(40 + dag)
+    n = 10
+    psi = _rc_mps(rng, n, 16)
+    assert M.right_canonical_error(psi) < 1e-13
+    y = rng.standard_normal(n)
+    t, chi, zeta = synth.thc_factors(np.random.default_rng(0), n // 2, 2)
+    ctx = thck.Context(t, chi, zeta)
+    ref_state = M.compress(M.apply_layer(psi, y, bool(dag)), D)
+    ref = M.to_dense(ref_state)
+    tol = 1e-12 if D >= 16 else 1e-9
+    outs = {}
+    for decl in (False, True):
+        out = ctx.apply_layer(thck.DeviceMPS.from_sites(psi, canonical=decl), y, dag, D)
+        outs[decl] = out
+        err = _rel(M.to_dense(out.to_sites()), ref)
+        print(f"layer dag={dag} D={D} declared canonical={decl}: rel err {err:.3e}")
+        assert err < tol
+        assert out.bond_list() == M.bonds(ref_state)
+        assert out.canonical and M.right_canonical_error(out.to_sites()) < 1e-12
+
+
+@pytest.mark.parametrize("D", [32, 6])
+def test_sum_compress_canonical_inputs(thck, D):
+    rng = np.random.default_rng(50)
+    n = 10
+    terms = [_rc_mps(rng, n, 8) for _ in range(3)]
+    coeffs = [0.7, -1.3, 0.4]
+    t, chi, zeta = synth.thc_factors(np.random.default_rng(0), n // 2, 2)
+    ctx = thck.Context(t, chi, zeta)
+    ref = M.to_dense(OH.sum_compress(coeffs, terms, D=D))
+    for decl in ((False, False, False), (True, True, True), (False, True, False)):
+        out = ctx.sum_compress(coeffs, [thck.DeviceMPS.from_sites(x, canonical=c) for x, c in zip(terms, decl)], D=D)
+        err = _rel(M.to_dense(out.to_sites()), ref)
+        print(f"sum D={D} declared {decl}: rel err {err:.3e}")
+        assert err < (1e-12 if D >= 32 else 1e-9)
+        assert M.right_canonical_error(out.to_sites()) < 1e-12
+
+
+# Gram SVD on rank-deficient sums: the top-k eigenvectors of G = Y Y^T are
+# chosen among eigenvalues with absolute noise ~ m eps s_1^2, so a singular
+# value below ~sqrt(m eps) s_1 (~1e-7 s_1 at m = 32) cannot be told from an
+# exact zero and may be dropped for a noise direction; over the levels of
+# the tree sum this bounds the state error by ~1e-6.  Jacobi keeps eps.
+@pytest.mark.parametrize("flags,tol", [(0, 1e-6), (1, 1e-12)])
+def test_canonical_rank_deficient_product_state(thck, flags, tol):
+    # a product state is right-canonical; every layer output and sum in H is
+    # rank deficient in its padding, so the rest rows of the structured sweep
+    # have exact linear dependencies
+    L, N = 4, 8
+    t, chi, zeta = synth.thc_factors(np.random.default_rng(8), L, N)
+    occ = synth.hartree_fock_occupation(L, 4)
+    hf = synth.occupation_mps_tensors(occ)
+    ctx = thck.Context(t, chi, zeta)
+    ref = F.apply_H_dense(M.to_dense(hf), t, TH.thc_v(chi, zeta))
+    for decl in (False, True):
+        out = ctx.apply_H(thck.DeviceMPS.from_sites(hf, canonical=decl), D=16, flags=flags)
+        err = _rel(M.to_dense(out.to_sites()), ref)
+        print(f"H|HF> flags={flags} declared canonical={decl}: rel err {err:.3e}")
+        assert err < tol
+        assert M.right_canonical_error(out.to_sites()) < 1e-12
+
+
+def test_apply_H_canonical_input_matches_plain(thck):
+    # truncated H|psi> (D=8): declared-canonical input against the oracle tree
+    L, N = 4, 6
+    rng = np.random.default_rng(30)
+    t, chi, zeta = synth.thc_factors(rng, L, N)
+    psi = M.right_canonicalize(_norm_mps(rng, 2 * L, 16))
+    ctx = thck.Context(t, chi, zeta)
+    ref = M.to_dense(OH.apply_H(psi, t, chi, zeta, D=8, mode="tree"))
+    for decl in (False, True):
+        out = ctx.apply_H(thck.DeviceMPS.from_sites(psi, canonical=decl), D=8)
+        err = _rel(M.to_dense(out.to_sites()), ref)
+        print(f"truncated H|psi> declared canonical={decl}: rel err vs oracle tree {err:.3e}")
+        assert err < 1e-8

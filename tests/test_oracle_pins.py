@@ -203,6 +203,20 @@ def test_compress_exact_when_untruncated():
     assert M.left_canonical_error(c) < 1e-13
 
 
+def test_right_canonical_form_checker():
+    # the QR sweep gives orthonormal rows at sites 1..n-1 and the same state;
+    # a generic random MPS is far from that form
+    rng = np.random.default_rng(12)
+    psi = _normalised_random_mps(rng, 8, 8)
+    rc = M.right_canonicalize(psi)
+    assert M.right_canonical_error(rc) < 1e-13
+    assert M.right_canonical_error(psi) > 1e-2
+    assert np.max(np.abs(M.to_dense(rc) - M.to_dense(psi))) < 1e-13
+    # the norm sits on site 0
+    a0 = rc[0].reshape(-1)
+    assert abs(np.linalg.norm(a0) - M.norm(psi)) < 1e-13
+
+
 def test_compress_discarded_weight_and_idempotence():
     rng = np.random.default_rng(10)
     n = 10
