@@ -369,6 +369,51 @@ struct CallStats {
   int64_t kn[THC_NK] = {};
 };
 
+// Per-shape totals of the timed kernels, printed on stderr at process exit
+// when THCK_KSTATS=1 (a tuning aid; THC_FLAG_TIME_KERNELS must be set).
+struct ShapeKey {
+  int cls, nb, m, n, k, mode;
+  bool operator<(const ShapeKey &o) const {
+    return std::tie(cls, nb, m, n, k, mode) < std::tie(o.cls, o.nb, o.m, o.n, o.k, o.mode);
+  }
+};
+struct ShapeStat {
+  int64_t calls = 0;
+  double ms = 0.0, flops = 0.0;
+};
+std::map<ShapeKey, ShapeStat> &shape_stats() {
+  // never destroyed: the exit handler below reads it after static destructors may have run
+  static auto *m = new std::map<ShapeKey, ShapeStat>();
+  return *m;
+}
+void print_shape_stats() {
+  static const char *names[THC_NK] = {"lq", "sytrd", "tri_eig", "ormtr", "gemm"};
+  std::vector<std::pair<ShapeKey, ShapeStat>> v(shape_stats().begin(), shape_stats().end());
+  std::sort(v.begin(), v.end(), [](const auto &a, const auto &b) { return a.second.ms > b.second.ms; });
+  double tot = 0.0;
+  for (auto &e : v) tot += e.second.ms;
+  fprintf(stderr, "[thck] timed kernels by shape (total %.2f s)\n", tot / 1e3);
+  for (size_t i = 0; i < v.size() && i < 40; ++i) {
+    const ShapeKey &k = v[i].first;
+    const ShapeStat &s = v[i].second;
+    fprintf(stderr, "[thck] %-7s nb %4d  %4d x %4d x %4d  mode %d  calls %7lld  %8.2f s (%4.1f%%)  avg %7.3f ms  %6.2f TF/s\n",
+            names[k.cls], k.nb, k.m, k.n, k.k, k.mode, (long long)s.calls, s.ms / 1e3, 100.0 * s.ms / tot,
+            s.ms / s.calls, s.ms > 0 ? s.flops / (s.ms * 1e-3) / 1e12 : 0.0);
+  }
+}
+bool shape_stats_on() {
+  static const bool on = [] {
+    const char *e = getenv("THCK_KSTATS");
+    const bool v = e && e[0] == '1';
+    if (v) {
+      (void)shape_stats();
+      atexit(print_shape_stats);
+    }
+    return v;
+  }();
+  return on;
+}
+
 // Event pairs around kernel launches (THC_FLAG_TIME_KERNELS): recorded on
 // the compression stream, resolved after the batch's synchronisation.
 struct KernelTimer {
@@ -376,6 +421,7 @@ struct KernelTimer {
     hipEvent_t a, b;
     int cls;
     double flops;
+    ShapeKey key;
   };
   std::vector<hipEvent_t> pool;
   std::vector<Rec> pending;
@@ -392,8 +438,8 @@ struct KernelTimer {
     return pool[used++];
   }
   template <class F>
-  void run(hipStream_t st, int cls, double flops, F &&launch) {
-    Rec r{get(), get(), cls, flops};
+  void run(hipStream_t st, int cls, double flops, const ShapeKey &key, F &&launch) {
+    Rec r{get(), get(), cls, flops, key};
     HIPCHK(hipEventRecord(r.a, st));
     launch();
     HIPCHK(hipEventRecord(r.b, st));
@@ -407,6 +453,12 @@ struct KernelTimer {
       cs.kms[r.cls] += ms;
       cs.kflops[r.cls] += r.flops;
       cs.kn[r.cls] += 1;
+      if (shape_stats_on()) {
+        ShapeStat &s = shape_stats()[r.key];
+        s.calls += 1;
+        s.ms += ms;
+        s.flops += r.flops;
+      }
     }
     pending.clear();
     used = 0;
@@ -430,38 +482,38 @@ struct Engine {
       : c(c_), st(s_), o(o_), timing((o_.flags & THC_FLAG_TIME_KERNELS) != 0) {}
   // launch through the timer when kernel timing is on
   template <class F>
-  void timed(int cls, double flops, F &&launch) {
-    if (timing) kt.run(st, cls, flops, launch);
+  void timed(int cls, double flops, const ShapeKey &key, F &&launch) {
+    if (timing) kt.run(st, cls, flops, key, launch);
     else launch();
   }
   // launchers of the timed kernel classes, with their algorithmic flops
   void gemm(int nb, int mode, const double *A, int64_t sA, int lda, const double *B, int64_t sB, int ldb, double *C,
             int64_t sC, int ldc, int M, int N, int K, double alpha = 1.0, double beta = 0.0) {
-    timed(THC_K_GEMM, 2.0 * M * N * (double)K * nb,
+    timed(THC_K_GEMM, 2.0 * M * N * (double)K * nb, ShapeKey{THC_K_GEMM, nb, M, N, K, mode + (beta != 0.0 ? 4 : 0)},
           [&] { launch_gemm(st, nb, mode, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta); });
   }
   int lq(int nb, double *X, int64_t sX, int m, int n, double *L, int64_t sL, double *Q, int64_t sQ, double *T,
          int64_t sT, bool tr = false, int ldl = 0, int ldq = 0) {
     int rc = 0;
-    timed(THC_K_LQ, lq_flops(m, n) * nb,
+    timed(THC_K_LQ, lq_flops(m, n) * nb, ShapeKey{THC_K_LQ, nb, m, n, 0, tr ? 1 : 0},
           [&] { rc = launch_lq(st, nb, X, sX, m, n, L, sL, Q, sQ, T, sT, tr, ldl, ldq); });
     return rc;
   }
   int sytrd(int nb, double *A, int64_t sA, int m, double *d, double *e, double *tau, int64_t sv) {
     int rc = 0;
-    timed(THC_K_SYTRD, 4.0 / 3.0 * m * (double)m * m * nb, [&] { rc = launch_sytrd(st, nb, A, sA, m, d, e, tau, sv); });
+    timed(THC_K_SYTRD, 4.0 / 3.0 * m * (double)m * m * nb, ShapeKey{THC_K_SYTRD, nb, m, m, 0, 0}, [&] { rc = launch_sytrd(st, nb, A, sA, m, d, e, tau, sv); });
     return rc;
   }
   int tri_eig(int nb, const double *d, const double *e, int64_t sv, int m, int kk, double *Z, int64_t sZ, double *lam,
               int64_t sl, double *scr, int64_t sscr) {
     int rc = 0;
-    timed(THC_K_TRI_EIG, 0.0, [&] { rc = launch_tri_eig(st, nb, d, e, sv, m, kk, Z, sZ, lam, sl, scr, sscr); });
+    timed(THC_K_TRI_EIG, 0.0, ShapeKey{THC_K_TRI_EIG, nb, m, kk, 0, 0}, [&] { rc = launch_tri_eig(st, nb, d, e, sv, m, kk, Z, sZ, lam, sl, scr, sscr); });
     return rc;
   }
   int ormtr(int nb, const double *A, int64_t sA, int m, const double *tau, int64_t sv, double *Z, int64_t sZ, int kk,
             double *Ut, int64_t sU, bool zout) {
     int rc = 0;
-    timed(THC_K_ORMTR, 2.0 * m * (double)m * kk * nb,
+    timed(THC_K_ORMTR, 2.0 * m * (double)m * kk * nb, ShapeKey{THC_K_ORMTR, nb, m, kk, 0, zout ? 1 : 0},
           [&] { rc = launch_ormtr(st, nb, A, sA, m, tau, sv, Z, sZ, kk, Ut, sU, zout); });
     return rc;
   }

@@ -1288,6 +1288,11 @@ __global__ __launch_bounds__(512) void k_ormtr2(const double *__restrict__ Ab, i
 // diagonal is then the contiguous row i.  One workgroup (512 threads) per
 // matrix.  Outputs: d (m), e (m-1), tau (m-1); reflector i is
 // v_i = e_{i+1} + tail with the tail stored in A[i][i+2:].
+// The trailing matrix is read and written through a buffer resource: a row
+// offset is a scalar, and only a 64-column chunk that straddles the diagonal
+// or the end m masks lanes, by an offset past the end of the buffer (reads
+// give 0, stores are dropped), so the streaming loops carry no per-element
+// branches or predicates.
 // ---------------------------------------------------------------------------
 template <int MMAX>
 __global__ __launch_bounds__(512) void k_sytrd2(double *__restrict__ Ab, int64_t sA, int m,
@@ -1299,8 +1304,8 @@ __global__ __launch_bounds__(512) void k_sytrd2(double *__restrict__ Ab, int64_t
   double *WL = VL + NB * MMAX;      // NB x MMAX
   double *x = WL + NB * MMAX;       // updated column i, then v
   double *y = x + MMAX;
-  double *prow = y + MMAX;          // row sums of the symmetric product
-  double *pp = prow + MMAX;         // NW x MMAX column partials
+  double *prow = y + MMAX;          // 4 x MMAX: row sums of the symmetric product, per 16-lane group
+  double *pp = prow + 4 * MMAX;     // NW x MMAX column partials
   double *red = pp + NW * MMAX;     // reductions: 2 NW + 2 NB
   __shared__ double s_tau, s_sc, s_alpha;
   __shared__ int s_slow;
@@ -1309,6 +1314,15 @@ __global__ __launch_bounds__(512) void k_sytrd2(double *__restrict__ Ab, int64_t
   double *e = eb + (int64_t)blockIdx.x * sv;
   double *tau = taub + (int64_t)blockIdx.x * sv;
   const int tid = threadIdx.x, lane = tid % WAVE, wid = tid / WAVE;
+  const int wvs = __builtin_amdgcn_readfirstlane(wid);  // the wave index as a scalar
+  const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(A, 0, m * m * 8, 0x00020000);
+  constexpr int OOB = 0x40000000;
+  // lane offset of chunk t in row c: masked (past the end) where r < c or r >= m
+  auto chunk_off = [&](int c, int t) -> int {
+    const int r = t * WAVE + lane;
+    if (t * WAVE < c || t * WAVE + WAVE > m) return (r >= c && r < m) ? r * 8 : OOB;
+    return r * 8;
+  };
   const int nref = m - 2;
   for (int i0 = 0; i0 < nref; i0 += NB) {
     const int nbp = (nref - i0) < NB ? (nref - i0) : NB;
@@ -1396,51 +1410,74 @@ __global__ __launch_bounds__(512) void k_sytrd2(double *__restrict__ Ab, int64_t
       }
       __syncthreads();
       // (3) y = A22 v over the trailing rows c > i (upper triangle), RU rows
-      //     per pass; dot products W_q.v and V_q.v of the earlier reflectors
+      //     per pass, the next pass's rows loaded while this one is summed;
+      //     chunks with no element r >= c are skipped (scalar branches).  Row
+      //     sums stop at 16-lane group partials (summed in step 4); the lane's
+      //     own column sums pc need no reduction until the end.  Then the dot
+      //     products W_q.v and V_q.v of the earlier reflectors.
       {
         double pc[CPL];
 #pragma unroll
         for (int t = 0; t < CPL; ++t) pc[t] = 0.0;
-        // rows c0 .. c0 + RU - 1 per pass; the next pass's rows are loaded
-        // while this one is reduced.  Chunks t with t * 64 + 63 < c hold no
-        // element of row c (upper triangle) and are skipped (wave-uniform).
-        double av[RU][CPL], an[RU][CPL];
+        double ava[RU][CPL], avb[RU][CPL];
         auto load_rows = [&](int cb, double (&dst)[RU][CPL]) {
 #pragma unroll
           for (int u = 0; u < RU; ++u) {
             const int c = cb + u;
-            const double *row = A + (int64_t)c * m;
 #pragma unroll
             for (int t = 0; t < CPL; ++t) {
-              const int r = t * WAVE + lane;
               dst[u][t] = 0.0;
-              if (t * WAVE + WAVE - 1 >= cb) dst[u][t] = (c < m && r >= c && r < m) ? row[r] : 0.0;
+              if (c < m && t * WAVE + WAVE - 1 >= cb && t * WAVE < m)
+                dst[u][t] = __builtin_bit_cast(
+                    double, __builtin_amdgcn_raw_buffer_load_b64(ra, chunk_off(c, t), c * m * 8, 0));
             }
           }
         };
-        load_rows(i + 1 + RU * wid, an);
-        for (int c0 = i + 1 + RU * wid; c0 < m; c0 += RU * NW) {
+        auto sum_rows = [&](int cb, const double (&av)[RU][CPL]) {
+          double acc[RU], vc[RU];
+#pragma unroll
+          for (int u = 0; u < RU; ++u) {
+            acc[u] = 0.0;
+            vc[u] = (cb + u < m) ? x[cb + u] : 0.0;
+          }
+#pragma unroll
+          for (int t = 0; t < CPL; ++t) {
+            if (t * WAVE + WAVE - 1 >= cb && t * WAVE < m) {
+              const double xt = x[t * WAVE + lane];
+#pragma unroll
+              for (int u = 0; u < RU; ++u) {
+                const int c = cb + u;
+                acc[u] = fma(av[u][t], xt, acc[u]);
+                // the diagonal element is counted once, in the row sum
+                double a = av[u][t];
+                if (t == (c >> 6)) a = (t * WAVE + lane > c) ? a : 0.0;
+                pc[t] = fma(a, vc[u], pc[t]);
+              }
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < RU; ++u) {
+            const int c = cb + u;
+            if (c < m) {
+              double v = acc[u];
+              v += dpp_shift<0x111>(v, 0.0);
+              v += dpp_shift<0x112>(v, 0.0);
+              v += dpp_shift<0x114>(v, 0.0);
+              v += dpp_shift<0x118>(v, 0.0);
+              if ((lane & 15) == 15) prow[(lane >> 4) * MMAX + c] = v;
+            }
+          }
+        };
+        const int step = RU * NW;
+        const int cstart = i + 1 + RU * wvs;
+        if (cstart < m) load_rows(cstart, avb);
+        for (int c0 = cstart; c0 < m; c0 += step) {
 #pragma unroll
           for (int u = 0; u < RU; ++u)
 #pragma unroll
-            for (int t = 0; t < CPL; ++t) av[u][t] = an[u][t];
-          if (c0 + RU * NW < m) load_rows(c0 + RU * NW, an);
-#pragma unroll
-          for (int u = 0; u < RU; ++u) {
-            const int c = c0 + u;
-            const double vc = (c < m) ? x[c] : 0.0;
-            double acc = 0.0;
-#pragma unroll
-            for (int t = 0; t < CPL; ++t) {
-              if (t * WAVE + WAVE - 1 >= c0) {
-                const int r = t * WAVE + lane;
-                acc += av[u][t] * x[r];
-                if (r > c) pc[t] += av[u][t] * vc;
-              }
-            }
-            acc = wave_sum(acc);
-            if (lane == 0 && c < m) prow[c] = acc;
-          }
+            for (int t = 0; t < CPL; ++t) ava[u][t] = avb[u][t];
+          if (c0 + step < m) load_rows(c0 + step, avb);
+          sum_rows(c0, ava);
         }
 #pragma unroll
         for (int t = 0; t < CPL; ++t) pp[wid * MMAX + t * WAVE + lane] = pc[t];
@@ -1458,7 +1495,7 @@ __global__ __launch_bounds__(512) void k_sytrd2(double *__restrict__ Ab, int64_t
       for (int r = tid; r < MMAX; r += NT) {
         double yr = 0.0;
         if (r >= i + 1 && r < m) {
-          yr = prow[r];
+          yr = (prow[r] + prow[MMAX + r]) + (prow[2 * MMAX + r] + prow[3 * MMAX + r]);
 #pragma unroll
           for (int w = 0; w < NW; ++w) yr += pp[w * MMAX + r];
           for (int q = 0; q < j; ++q) yr -= VL[q * MMAX + r] * red[2 * NW + q] + WL[q * MMAX + r] * red[2 * NW + j + q];
@@ -1484,16 +1521,17 @@ __global__ __launch_bounds__(512) void k_sytrd2(double *__restrict__ Ab, int64_t
     {
       constexpr int RS = 2;
       const int c1 = i0 + nbp;
-      for (int c0 = c1 + RS * wid; c0 < m; c0 += RS * NW) {
+      for (int c0 = c1 + RS * wvs; c0 < m; c0 += RS * NW) {
         double av[RS][CPL], vc[RS][NB], wc[RS][NB];
 #pragma unroll
         for (int u = 0; u < RS; ++u) {
           const int c = c0 + u;
 #pragma unroll
           for (int t = 0; t < CPL; ++t) {
-            const int r = t * WAVE + lane;
             av[u][t] = 0.0;
-            if (t * WAVE + WAVE - 1 >= c0 && c < m && r >= c && r < m) av[u][t] = A[(int64_t)c * m + r];
+            if (c < m && t * WAVE + WAVE - 1 >= c0 && t * WAVE < m)
+              av[u][t] =
+                  __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(ra, chunk_off(c, t), c * m * 8, 0));
           }
 #pragma unroll
           for (int q = 0; q < NB; ++q) {
@@ -1503,7 +1541,7 @@ __global__ __launch_bounds__(512) void k_sytrd2(double *__restrict__ Ab, int64_t
         }
 #pragma unroll
         for (int t = 0; t < CPL; ++t) {
-          if (t * WAVE + WAVE - 1 >= c0) {
+          if (t * WAVE + WAVE - 1 >= c0 && t * WAVE < m) {
             const int r = t * WAVE + lane;
             double vr[NB], wr[NB];
 #pragma unroll
@@ -1514,11 +1552,11 @@ __global__ __launch_bounds__(512) void k_sytrd2(double *__restrict__ Ab, int64_t
 #pragma unroll
             for (int u = 0; u < RS; ++u) {
               const int c = c0 + u;
-              if (c < m && r >= c && r < m) {
+              if (c < m) {
                 double a = av[u][t];
 #pragma unroll
                 for (int q = 0; q < NB; ++q) a -= vc[u][q] * wr[q] + wc[u][q] * vr[q];
-                A[(int64_t)c * m + r] = a;
+                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2_t, a), ra, chunk_off(c, t), c * m * 8, 0);
               }
             }
           }
@@ -2024,7 +2062,7 @@ void launch_scale(hipStream_t st, double *p, int64_t count, double c) {
 int launch_sytrd(hipStream_t st, int nb, double *A, int64_t sA, int m, double *d, double *e, double *tau, int64_t sv) {
   constexpr int MMAX = 512;
   if (m > MMAX) return -1;
-  const size_t lds = (2 * 8 * MMAX + 3 * MMAX + 8 * MMAX + 2 * 8 + 2 * 8 + 8) * sizeof(double);
+  const size_t lds = (2 * 8 * MMAX + 6 * MMAX + 8 * MMAX + 2 * 8 + 2 * 8 + 8) * sizeof(double);
   static bool attr = false;
   if (!attr) { set_lds(k_sytrd2<MMAX>, lds); attr = true; }
   hipLaunchKernelGGL(k_sytrd2<MMAX>, dim3(nb), dim3(512), lds, st, A, sA, m, d, e, tau, sv);
