@@ -1916,26 +1916,33 @@ static void set_lds(K kern, size_t lds) {
   (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
+// one instantiation of k_lq2: NMAX bounds n (panel rows in LDS, registers per lane)
+template <int NMAX, bool TR>
+static void lq_variant(hipStream_t st, int nb, double *X, int64_t sX, int m, int n, double *L, int64_t sL, double *Q,
+                       int64_t sQ, double *Tw, int64_t sT, int ldl, int ldq) {
+  constexpr int NWV = 8;
+  constexpr size_t lds = (16 * (NMAX + 1) + 256 + 256 + (NWV + 1) * 256 + 256 + 16 + 256) * sizeof(double);
+  static bool attr = false;
+  if (!attr) {
+    set_lds(k_lq2<NMAX, TR>, lds);
+    attr = true;
+  }
+  hipLaunchKernelGGL((k_lq2<NMAX, TR>), dim3(nb), dim3(512), lds, st, X, sX, m, n, L, sL, Q, sQ, Tw, sT, ldl, ldq);
+}
+
 int launch_lq(hipStream_t st, int nb, double *X, int64_t sX, int m, int n, double *L, int64_t sL, double *Q,
               int64_t sQ, double *Tw, int64_t sT, bool tr, int ldl, int ldq) {
   const int k = m < n ? m : n;
   if (ldl <= 0) ldl = k;
   if (ldq <= 0) ldq = tr ? k : n;
   if (n > 1024) return -1;
-  constexpr int NMAX = 1024, NWV = 8;
-  const size_t lds = (16 * (NMAX + 1) + 256 + 256 + (NWV + 1) * 256 + 256 + 16 + 256) * sizeof(double);
-  static bool attr[2] = {false, false};
-  if (!attr[tr]) {
-    if (tr) set_lds(k_lq2<NMAX, true>, lds);
-    else set_lds(k_lq2<NMAX, false>, lds);
-    attr[tr] = true;
+  if (n <= 512) {
+    if (tr) lq_variant<512, true>(st, nb, X, sX, m, n, L, sL, Q, sQ, Tw, sT, ldl, ldq);
+    else lq_variant<512, false>(st, nb, X, sX, m, n, L, sL, Q, sQ, Tw, sT, ldl, ldq);
+  } else {
+    if (tr) lq_variant<1024, true>(st, nb, X, sX, m, n, L, sL, Q, sQ, Tw, sT, ldl, ldq);
+    else lq_variant<1024, false>(st, nb, X, sX, m, n, L, sL, Q, sQ, Tw, sT, ldl, ldq);
   }
-  if (tr)
-    hipLaunchKernelGGL((k_lq2<NMAX, true>), dim3(nb), dim3(512), lds, st, X, sX, m, n, L, sL, Q, sQ, Tw, sT, ldl,
-                       ldq);
-  else
-    hipLaunchKernelGGL((k_lq2<NMAX, false>), dim3(nb), dim3(512), lds, st, X, sX, m, n, L, sL, Q, sQ, Tw, sT, ldl,
-                       ldq);
   return 0;
 }
 
