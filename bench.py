@@ -10,8 +10,11 @@ applications per second.
 
 Default workload: L = 20 spatial orbitals (40 sites), THC rank N = 80, bond
 dimension D = 256, a random normalised real MPS with bonds
-min(2^j, 2^(40-j), 256) (seed 0), FP64 contractions.  The input sits in
-device memory before the timed region starts.
+min(2^j, 2^(40-j), 256) (seed 0).  The absorb contractions run in BF16x3
+(--prec), the QR / SVD factorisations, overlaps and the Lanczos eigensolve
+in FP64; --compare-f64 also times the same step with FP64 contractions and
+reports the speedup and the Ritz-value difference.  The input sits in device
+memory before the timed region starts.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -81,6 +84,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--workload", default="L20_N80_D256")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--prec", default="bf16x3", choices=["f64", "f32", "bf16x3"],
+                    help="contraction precision of the absorb products (factorisations stay FP64)")
+    ap.add_argument("--compare-f64", action="store_true",
+                    help="also time the step with FP64 contractions (doubles the run time)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -106,25 +113,38 @@ def main():
     torch.cuda.synchronize()
     log(f"[bench] workload {args.workload}: L={L} N={N} D={D}, warmup {args.warmup}, steps {args.steps}")
 
-    K = args.warmup + args.steps
-    kr = thck.Krylov(ctx, psi, K, D=D, flags=thck.FLAG_TIME_KERNELS)
-    for s in range(args.warmup):
-        st = thck.ThcStats()
+    def run(prec):
+        K = args.warmup + args.steps
+        kr = thck.Krylov(ctx, psi, K, D=D, flags=thck.FLAG_TIME_KERNELS, prec=prec)
+        for s in range(args.warmup):
+            st = thck.ThcStats()
+            t0 = time.perf_counter()
+            kr.step(st)
+            log(f"[bench] {prec} warmup step {s}: {time.perf_counter() - t0:.1f} s")
+        torch.cuda.synchronize()
+        stats = []
+        ritz = None
         t0 = time.perf_counter()
-        kr.step(st)
-        log(f"[bench] warmup step {s}: {time.perf_counter() - t0:.1f} s")
-    torch.cuda.synchronize()
-    stats = []
-    ritz = None
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        st = thck.ThcStats()
-        ritz, _, beta = kr.step(st)
-        stats.append(st)
-        log(f"[bench] step {s}: {time.perf_counter() - t0:.1f} s elapsed, lowest Ritz value {ritz[0]:.10f}, "
-            f"beta {beta:.3e}, compressions {st.n_compressions}, max discarded weight {st.discarded_weight_max:.3e}")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+        for s in range(args.steps):
+            st = thck.ThcStats()
+            ritz, _, beta = kr.step(st)
+            stats.append(st)
+            log(f"[bench] {prec} step {s}: {time.perf_counter() - t0:.1f} s elapsed, lowest Ritz value {ritz[0]:.10f}, "
+                f"beta {beta:.3e}, compressions {st.n_compressions}, max discarded weight "
+                f"{st.discarded_weight_max:.3e}")
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        kr.close()
+        return elapsed, stats, ritz
+
+    elapsed, stats, ritz = run(args.prec)
+    f64 = None
+    if args.compare_f64 and args.prec != "f64":
+        e64, _, r64 = run("f64")
+        f64 = {"value": args.steps / e64, "ms_per_step": e64 / args.steps * 1e3, "lowest_ritz": float(r64[0]),
+               "speedup_of_mixed": e64 / elapsed,
+               "lowest_ritz_rel_diff": abs(float(ritz[0]) - float(r64[0])) / abs(float(r64[0]))}
+        log(f"[bench] f64 contractions: {e64:.1f} s per step; mixed speedup {e64 / elapsed:.3f}x")
 
     # per-kernel device time inside the timed region (HIP events on the call's stream)
     names = thck.ThcStats.KERNELS
@@ -173,7 +193,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.prec == "f64" else f"f64+{args.prec}",
         "data": "synthetic",
         "config": {
             "workload": args.workload,
@@ -182,10 +202,11 @@ def main():
             "input": f"random normalised real MPS, bonds min(2^j, 2^({2 * L}-j), {D}), seed {w['seed']}",
             "step": "one krylov_step: compressed H|v> (tree sum) + residual sum-compression + Ritz values",
             "compressions_per_step": n_comp / args.steps,
-            "contraction_precision": "f64",
+            "contraction_precision": args.prec,
         },
         "model_tflops_per_s": flops_model / elapsed / 1e12,
         "lowest_ritz": float(ritz[0]) if ritz is not None else None,
+        "fp64_contractions": f64,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -46,12 +46,19 @@ typedef enum {
   THC_ECAPACITY = -6   /* output buffer too small */
 } thc_status;
 
-/* Contraction precision for the absorb GEMMs of the compression.  The QR
- * and SVD factorisations, overlaps and Lanczos eigensolves are always FP64. */
+/* Contraction precision of the compression's absorb products: a factor
+ * absorbed into a site (B_j L_{j+1} of the canonicalisation sweep, the rest
+ * rows' source times L', (S V^T) Q_{j+1} of the truncation sweep, and the
+ * re-canonicalisation's U_j L_{j+1}).  Data stays FP64 in memory; the
+ * product rounds its operands.  The QR and SVD factorisations (with the
+ * Gram matrix and the projections of the structured sweep), overlaps and
+ * Lanczos eigensolves are always FP64.  Expected accuracy of an untruncated
+ * H|psi>: ~1e-12 relative (F64), ~1e-6 (F32), ~1e-5 (BF16X3). */
 typedef enum {
   THC_PREC_F64 = 0,
-  THC_PREC_F32 = 1,    /* FP32 operands, FP32 accumulation */
-  THC_PREC_BF16X3 = 2  /* hi/lo bf16 split, three bf16 MFMA products, FP32 accumulation */
+  THC_PREC_F32 = 1,    /* operands rounded to FP32, FP32 MFMA, FP32 accumulation */
+  THC_PREC_BF16X3 = 2  /* FP32 operands split into bf16 hi + lo, a_hi b_hi + a_hi b_lo + a_lo b_hi on BF16 MFMA,
+                          FP32 accumulation */
 } thc_prec;
 
 /* Caller-owned MPS view.  On input, bonds/offsets describe the data.  On

@@ -478,8 +478,12 @@ struct Engine {
   // pending stats readbacks are done synchronously per batch only in debug
   KernelTimer kt;
   bool timing = false;
+  // precision of the contractions that absorb a factor into a site (the
+  // factorisations, their projections, Gram matrices and overlaps are FP64)
+  int cprec = GEMM_F64;
   Engine(thc_ctx *c_, hipStream_t s_, const thc_opts &o_)
-      : c(c_), st(s_), o(o_), timing((o_.flags & THC_FLAG_TIME_KERNELS) != 0) {}
+      : c(c_), st(s_), o(o_), timing((o_.flags & THC_FLAG_TIME_KERNELS) != 0),
+        cprec(o_.prec == THC_PREC_F32 ? GEMM_F32 : (o_.prec == THC_PREC_BF16X3 ? GEMM_BF16X3 : GEMM_F64)) {}
   // launch through the timer when kernel timing is on
   template <class F>
   void timed(int cls, double flops, const ShapeKey &key, F &&launch) {
@@ -488,9 +492,10 @@ struct Engine {
   }
   // launchers of the timed kernel classes, with their algorithmic flops
   void gemm(int nb, int mode, const double *A, int64_t sA, int lda, const double *B, int64_t sB, int ldb, double *C,
-            int64_t sC, int ldc, int M, int N, int K, double alpha = 1.0, double beta = 0.0) {
-    timed(THC_K_GEMM, 2.0 * M * N * (double)K * nb, ShapeKey{THC_K_GEMM, nb, M, N, K, mode + (beta != 0.0 ? 4 : 0)},
-          [&] { launch_gemm(st, nb, mode, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta); });
+            int64_t sC, int ldc, int M, int N, int K, double alpha = 1.0, double beta = 0.0, int prec = GEMM_F64) {
+    timed(THC_K_GEMM, 2.0 * M * N * (double)K * nb,
+          ShapeKey{THC_K_GEMM, nb, M, N, K, mode + (beta != 0.0 ? 4 : 0) + 8 * prec},
+          [&] { launch_gemm(st, nb, mode, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta, prec); });
   }
   int lq(int nb, double *X, int64_t sX, int m, int n, double *L, int64_t sL, double *Q, int64_t sQ, double *T,
          int64_t sT, bool tr = false, int ldl = 0, int ldq = 0) {
@@ -575,7 +580,7 @@ struct Engine {
       launch_gather(st, nb, dj, srcw, off_src, Bb, S, (int64_t)lr * 2 * rsrc);
       for (int sg = 0; sg < 2; ++sg)
         gemm(nb, GEMM_TA | GEMM_TB, Lt[cur], S, c1, Bb + sg * rsrc, S, 2 * rsrc, Tb + (int64_t)sg * c1 * lr, S, lr,
-             c1, lr, lr1);
+             c1, lr, lr1, 1.0, 0.0, cprec);
       if (P.kind == 0) launch_rest_post(st, nb, dj, j, P.pa.off[j], lr, ra, c1, Tb, S);
       // P_j = X_rest X_canon^T (lr x lc) -> columns 0..lc-1 of L'_j
       gemm(nb, GEMM_TA, Tb, S, lr, Qt, S, cj, Lnew, S, cj, lr, lc, 2 * c1);
@@ -595,7 +600,7 @@ struct Engine {
       const int rsrc = (P.kind == 0) ? P.pa.b[1] : P.pb.b[1];
       const int64_t off_src = (P.kind == 0) ? P.pa.off[0] : P.pb.off[0];
       launch_gather(st, nb, dj, srcw, off_src, Bb, S, (int64_t)2 * rsrc);
-      gemm(nb, 0, Bb, S, rsrc, Lt[cur], S, c1, Mb, S, c1, 2, c1, lr1);
+      gemm(nb, 0, Bb, S, rsrc, Lt[cur], S, c1, Mb, S, c1, 2, c1, lr1, 1.0, 0.0, cprec);
       launch_site0(st, nb, dj, P.pa.off[0], P.pa.b[1], c1, Mb, S);
       launches += 3;
     }
@@ -618,7 +623,7 @@ struct Engine {
         launch_gather(st, nb, dj, 2, P.out.off[j], Tb, S, (int64_t)kj * 2 * kj1);
       } else {
         launch_gather(st, nb, dj, 2, P.out.off[j], Bb, S, (int64_t)kj * 2 * kj1);
-        gemm(nb, 0, Bb, S, kj1, Lb, S, kj1, Tb, S, kj1, 2 * kj, kj1, kj1);
+        gemm(nb, 0, Bb, S, kj1, Lb, S, kj1, Tb, S, kj1, 2 * kj, kj1, kj1, 1.0, 0.0, cprec);
       }
       if (lq(nb, Tb, S, kj, 2 * kj1, Lb, S, Yb, S, Tf, S) != 0)
         raise(THC_EINVAL, "site matrix too wide for the LQ kernel (2*bond > 1024)");
@@ -626,7 +631,7 @@ struct Engine {
       launches += 4;
     }
     launch_gather(st, nb, dj, 2, P.out.off[0], Bb, S, (int64_t)2 * P.k[1]);
-    gemm(nb, 0, Bb, S, P.k[1], Lb, S, P.k[1], Yb, S, P.k[1], 2, P.k[1], P.k[1]);
+    gemm(nb, 0, Bb, S, P.k[1], Lb, S, P.k[1], Yb, S, P.k[1], 2, P.k[1], P.k[1], 1.0, 0.0, cprec);
     launch_scatter(st, nb, dj, P.out.off[0], Yb, S, (int64_t)2 * P.k[1]);
     return launches + 3;
   }
@@ -667,7 +672,8 @@ struct Engine {
           // physical index with both operands read transposed
           for (int sg = 0; sg < 2; ++sg)
             gemm(nb, GEMM_TA | GEMM_TB, Lb, S, P.c[j + 1], Bb + sg * P.bo[j + 1], S, 2 * P.bo[j + 1],
-                 Tb + (int64_t)sg * P.c[j + 1] * P.bo[j], S, P.bo[j], P.c[j + 1], P.bo[j], P.bo[j + 1]);
+                 Tb + (int64_t)sg * P.c[j + 1] * P.bo[j], S, P.bo[j], P.c[j + 1], P.bo[j], P.bo[j + 1], 1.0, 0.0,
+                 cprec);
         }
         ++launches;
         if (lq(nb, Tb, S, P.bo[j], 2 * P.c[j + 1], Lb, S, Qs + P.qs_off[j], S, Tf, S, true) != 0)
@@ -680,7 +686,7 @@ struct Engine {
         launch_construct(st, dj, nb, 0, n, P.pa.off[0], P.kind ? P.pb.off[0] : 0, la, ra, lb, rb, Bb, S, P.bo[0],
                          P.bo[1]);
         if (n > 1)
-          gemm(nb, 0, Bb, S, P.bo[1], Lb, S, P.c[1], Mb, S, P.c[1], 2, P.c[1], P.bo[1]);
+          gemm(nb, 0, Bb, S, P.bo[1], Lb, S, P.c[1], Mb, S, P.c[1], 2, P.c[1], P.bo[1], 1.0, 0.0, cprec);
         else
           launch_copy(st, nb, Bb, S, Mb, S, 2);
         launches += 2;
@@ -712,8 +718,8 @@ struct Engine {
                          dw_d + (size_t)j * nb, true);
       launch_scatter(st, nb, dj, P.out.off[j], Ub, S, (int64_t)m * kk);
       // M_{j+1} = C (kk x c_{j+1}) * Q_{j+1} (Q_{j+1} stored transposed)
-      gemm(nb, GEMM_TB, Cb, S, nc, Qs + P.qs_off[j + 1], S, nc, Mb, S, 2 * P.c[j + 2], kk, 2 * P.c[j + 2],
-                  nc);
+      gemm(nb, GEMM_TB, Cb, S, nc, Qs + P.qs_off[j + 1], S, nc, Mb, S, 2 * P.c[j + 2], kk, 2 * P.c[j + 2], nc, 1.0,
+           0.0, cprec);
       launches += 10;
     }
     if (!jacobi) HIPCHK(hipMemsetAsync(sw_d, 0, (size_t)nb * n * sizeof(int), st));
@@ -733,8 +739,8 @@ struct Engine {
       launch_svd_finish(st, nb, Qz, S, m, kk, rk_d + (size_t)j * nb, Ub, S, Cb, S, nc);
       launch_scatter(st, nb, dj, P.out.off[j], Ub, S, (int64_t)m * kk);
       // M_{j+1} = C (kk x c_{j+1}) * Q_{j+1} (Q_{j+1} stored transposed)
-      gemm(nb, GEMM_TB, Cb, S, nc, Qs + P.qs_off[j + 1], S, nc, Mb, S, 2 * P.c[j + 2], kk, 2 * P.c[j + 2],
-                  nc);
+      gemm(nb, GEMM_TB, Cb, S, nc, Qs + P.qs_off[j + 1], S, nc, Mb, S, 2 * P.c[j + 2], kk, 2 * P.c[j + 2], nc, 1.0,
+           0.0, cprec);
       launches += 9;
     }
     // last site

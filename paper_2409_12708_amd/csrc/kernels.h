@@ -29,10 +29,12 @@ void launch_construct(hipStream_t st, const CJob *jobs, int nb, int site, int n_
                       int ro);
 // GEMM modes (bits): B given transposed, A given transposed.
 constexpr int GEMM_TB = 1, GEMM_TA = 2;
+// contraction precision of a GEMM (operands and result are FP64 in memory)
+constexpr int GEMM_F64 = 0, GEMM_F32 = 1, GEMM_BF16X3 = 2;
 // C = alpha op(A) op(B) + beta C (beta = 0: C is not read).
 void launch_gemm(hipStream_t st, int nb, int mode, const double *A, int64_t sA, int lda, const double *B,
                  int64_t sB, int ldb, double *C, int64_t sC, int ldc, int M, int N, int K, double alpha = 1.0,
-                 double beta = 0.0);
+                 double beta = 0.0, int prec = GEMM_F64);
 void launch_transpose(hipStream_t st, int nb, const double *src, int64_t ss, int r, int c, double *dst, int64_t sd);
 // LQ of X (m x n), k = min(m, n): L (m x k, row stride ldl), Q (k x n, row
 // stride ldq).  With tr, X is given transposed (n x m row-major) and Q is

@@ -15,6 +15,7 @@
 //   overlap     transfer-matrix chain <a|b>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -124,6 +125,8 @@ __global__ void k_construct(const CJob *__restrict__ jobs, int site, int n_sites
 //   D (16x16): lane l, register r holds D[l/16 + 4r][l%16]
 // ---------------------------------------------------------------------------
 typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef short s4_t __attribute__((ext_vector_type(4)));
 typedef unsigned int u2_t __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ d4_t mfma16(double a, double b, d4_t c) {
@@ -142,8 +145,24 @@ __device__ __forceinline__ d4_t mfma16(double a, double b, d4_t c) {
 // that each XCD (workgroups are dealt to the 8 XCDs round-robin) receives a
 // contiguous run of (job, tile) pairs: the tiles of one job share that
 // XCD's L2.
+//
+// Contraction precision (operands and result stay FP64 in memory):
+//   GEMM_F64    FP64 MFMA 16x16x4, FP64 accumulation;
+//   GEMM_F32    operands rounded to FP32, FP32 MFMA 16x16x4, FP32 accumulation;
+//   GEMM_BF16X3 operands rounded to FP32 and split x = hi + lo into two
+//               bfloat16 parts, a b ~ a_hi b_hi + a_hi b_lo + a_lo b_hi on
+//               BF16 MFMA 16x16x16 with FP32 accumulation (the dropped
+//               a_lo b_lo and the split leave ~2^-16 relative per product).
+// The FP32 / BF16 MFMAs return D[4 (l/16) + r][l % 16] in lane l, register r
+// (the FP64 one D[l/16 + 4 r][l % 16]).
 // ---------------------------------------------------------------------------
-template <int MODE, int BM, int BN>
+__device__ __forceinline__ unsigned short bf16_rne(float x) {
+  const unsigned u = __float_as_uint(x);
+  return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_to_float(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+template <int MODE, int BM, int BN, int PREC>
 __global__ __launch_bounds__(256) void k_gemm_mfma(const double *__restrict__ A, int64_t sA, int lda,
                                                    const double *__restrict__ B, int64_t sB, int ldb,
                                                    double *__restrict__ C, int64_t sC, int ldc, int M, int N,
@@ -154,8 +173,16 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(const double *__restrict__ A,
   constexpr int LA = BK + 1;                 // row stride of [rows][k] chunks
   constexpr int LB = BN + 16;                // row stride of a [k][n] chunk
   constexpr int NA = BM * BK / 256, NBL = BN * BK / 256;
-  __shared__ double As[BM * LA];
-  __shared__ double Bs[TB ? BN * LA : BK * LB];
+  // FP64: As [BM][17], Bs [BN][17] or [16][BN + 16] doubles; FP32: the same
+  // shapes in floats; BF16X3: hi and lo parts [rows][16] with k contiguous
+  // for both operands (a plain B chunk is stored transposed)
+  typedef typename std::conditional<PREC == GEMM_F64, double, float>::type lds_t;
+  constexpr int SA = (PREC == GEMM_BF16X3) ? 1 : BM * LA;
+  constexpr int SB = (PREC == GEMM_BF16X3) ? 1 : (TB ? BN * LA : BK * LB);
+  __shared__ lds_t As[SA];
+  __shared__ lds_t Bs[SB];
+  constexpr int SH = (PREC == GEMM_BF16X3) ? 1 : 0;
+  __shared__ unsigned short Ah[SH ? BM * BK : 1], Al[SH ? BM * BK : 1], Bh[SH ? BN * BK : 1], Bl[SH ? BN * BK : 1];
 
   const int T = tiles_m * tiles_n;
   const int G = gridDim.x;
@@ -202,51 +229,96 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(const double *__restrict__ A,
       }
     }
   };
+  // element (row, k) of the A chunk / (col, k) of the B chunk, for the split stores
+  auto put_split = [&](unsigned short *hi, unsigned short *lo, int idx, double v) {
+    const float f = (float)v;
+    const unsigned short h = bf16_rne(f);
+    hi[idx] = h;
+    lo[idx] = bf16_rne(f - bf16_to_float(h));
+  };
   auto store = [&]() {
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
+      int row, k;
       if (TA) {
         const int e = tid + 256 * i;
-        As[(e % BM) * LA + e / BM] = ra[i];
+        row = e % BM;
+        k = e / BM;
       } else {
-        As[(tid / 16 + 16 * i) * LA + tid % 16] = ra[i];
+        row = tid / 16 + 16 * i;
+        k = tid % 16;
       }
+      if constexpr (PREC == GEMM_BF16X3) put_split(Ah, Al, row * BK + k, ra[i]);
+      else As[row * LA + k] = (lds_t)ra[i];
     }
 #pragma unroll
     for (int i = 0; i < NBL; ++i) {
       if (TB) {
-        Bs[(tid / 16 + 16 * i) * LA + tid % 16] = rb[i];
+        const int col = tid / 16 + 16 * i, k = tid % 16;
+        if constexpr (PREC == GEMM_BF16X3) put_split(Bh, Bl, col * BK + k, rb[i]);
+        else Bs[col * LA + k] = (lds_t)rb[i];
       } else {
         const int e = tid + 256 * i;
-        Bs[(e / BN) * LB + e % BN] = rb[i];
+        const int k = e / BN, col = e % BN;
+        if constexpr (PREC == GEMM_BF16X3) put_split(Bh, Bl, col * BK + k, rb[i]);
+        else Bs[k * LB + col] = (lds_t)rb[i];
       }
     }
   };
 
-  d4_t acc[WM][WN];
+  typedef typename std::conditional<PREC == GEMM_F64, d4_t, f4_t>::type acc_t;
+  acc_t acc[WM][WN];
 #pragma unroll
   for (int i = 0; i < WM; ++i)
 #pragma unroll
-    for (int j = 0; j < WN; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < WN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
   load(0);
   for (int k0 = 0; k0 < K; k0 += BK) {
     store();
     __syncthreads();
     if (k0 + BK < K) load(k0 + BK);
+    if constexpr (PREC == GEMM_BF16X3) {
+      // one 16x16x16 step covers the chunk: lane l holds k = 4 (l/16) .. + 3
+      s4_t ah[WM], al[WM], bh[WN], bl[WN];
 #pragma unroll
-    for (int ks = 0; ks < BK / 4; ++ks) {
-      double af[WM], bf[WN];
+      for (int i = 0; i < WM; ++i) {
+        const int o = (wm * (BM / 2) + 16 * i + li) * BK + 4 * lk;
+        ah[i] = *reinterpret_cast<const s4_t *>(Ah + o);
+        al[i] = *reinterpret_cast<const s4_t *>(Al + o);
+      }
 #pragma unroll
-      for (int i = 0; i < WM; ++i) af[i] = As[(wm * (BM / 2) + 16 * i + li) * LA + 4 * ks + lk];
-#pragma unroll
-      for (int j = 0; j < WN; ++j)
-        bf[j] = TB ? Bs[(wn * (BN / 2) + 16 * j + li) * LA + 4 * ks + lk]
-                   : Bs[(4 * ks + lk) * LB + wn * (BN / 2) + 16 * j + li];
+      for (int j = 0; j < WN; ++j) {
+        const int o = (wn * (BN / 2) + 16 * j + li) * BK + 4 * lk;
+        bh[j] = *reinterpret_cast<const s4_t *>(Bh + o);
+        bl[j] = *reinterpret_cast<const s4_t *>(Bl + o);
+      }
 #pragma unroll
       for (int i = 0; i < WM; ++i)
 #pragma unroll
-        for (int j = 0; j < WN; ++j) acc[i][j] = mfma16(af[i], bf[j], acc[i][j]);
+        for (int j = 0; j < WN; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[i], bh[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bl[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bh[j], acc[i][j], 0, 0, 0);
+        }
+    } else {
+#pragma unroll
+      for (int ks = 0; ks < BK / 4; ++ks) {
+        lds_t af[WM], bf[WN];
+#pragma unroll
+        for (int i = 0; i < WM; ++i) af[i] = As[(wm * (BM / 2) + 16 * i + li) * LA + 4 * ks + lk];
+#pragma unroll
+        for (int j = 0; j < WN; ++j)
+          bf[j] = TB ? Bs[(wn * (BN / 2) + 16 * j + li) * LA + 4 * ks + lk]
+                     : Bs[(4 * ks + lk) * LB + wn * (BN / 2) + 16 * j + li];
+#pragma unroll
+        for (int i = 0; i < WM; ++i)
+#pragma unroll
+          for (int j = 0; j < WN; ++j) {
+            if constexpr (PREC == GEMM_F64) acc[i][j] = mfma16(af[i], bf[j], acc[i][j]);
+            else acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[j], acc[i][j], 0, 0, 0);
+          }
+      }
     }
     __syncthreads();
   }
@@ -257,10 +329,11 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(const double *__restrict__ A,
       const int gc = n0 + wn * (BN / 2) + 16 * j + li;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int gr = m0 + wm * (BM / 2) + 16 * i + lk + 4 * r;
+        const int gr = m0 + wm * (BM / 2) + 16 * i + (PREC == GEMM_F64 ? lk + 4 * r : 4 * lk + r);
         if (gr < M && gc < N) {
           double *cp = C + (int64_t)gr * ldc + gc;
-          *cp = (beta != 0.0) ? alpha * acc[i][j][r] + beta * *cp : alpha * acc[i][j][r];
+          const double a = (double)acc[i][j][r];
+          *cp = (beta != 0.0) ? alpha * a + beta * *cp : alpha * a;
         }
       }
     }
@@ -1877,32 +1950,45 @@ void launch_construct(hipStream_t st, const CJob *jobs, int nb, int site, int n_
                      ra, lb, rb, out, out_stride, lo, ro);
 }
 
-template <int MODE>
+template <int MODE, int PREC>
 static void gemm_mode(hipStream_t st, int nb, const double *A, int64_t sA, int lda, const double *B, int64_t sB,
                       int ldb, double *C, int64_t sC, int ldc, int M, int N, int K, double alpha, double beta) {
   if (M > 64 && N > 64) {
     const int tm = (M + 127) / 128, tn = (N + 127) / 128;
-    hipLaunchKernelGGL((k_gemm_mfma<MODE, 128, 128>), dim3(nb * tm * tn), dim3(256), 0, st, A, sA, lda, B, sB, ldb,
-                       C, sC, ldc, M, N, K, tm, tn, alpha, beta);
+    hipLaunchKernelGGL((k_gemm_mfma<MODE, 128, 128, PREC>), dim3(nb * tm * tn), dim3(256), 0, st, A, sA, lda, B, sB,
+                       ldb, C, sC, ldc, M, N, K, tm, tn, alpha, beta);
   } else {
     const int tm = (M + 63) / 64, tn = (N + 63) / 64;
-    hipLaunchKernelGGL((k_gemm_mfma<MODE, 64, 64>), dim3(nb * tm * tn), dim3(256), 0, st, A, sA, lda, B, sB, ldb,
-                       C, sC, ldc, M, N, K, tm, tn, alpha, beta);
+    hipLaunchKernelGGL((k_gemm_mfma<MODE, 64, 64, PREC>), dim3(nb * tm * tn), dim3(256), 0, st, A, sA, lda, B, sB,
+                       ldb, C, sC, ldc, M, N, K, tm, tn, alpha, beta);
+  }
+}
+
+template <int PREC>
+static void gemm_prec(hipStream_t st, int nb, int mode, const double *A, int64_t sA, int lda, const double *B,
+                      int64_t sB, int ldb, double *C, int64_t sC, int ldc, int M, int N, int K, double alpha,
+                      double beta) {
+  switch (mode) {
+    case 0: gemm_mode<0, PREC>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta); break;
+    case GEMM_TB: gemm_mode<GEMM_TB, PREC>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta); break;
+    case GEMM_TA: gemm_mode<GEMM_TA, PREC>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta); break;
+    case GEMM_TA | GEMM_TB:
+      gemm_mode<GEMM_TA | GEMM_TB, PREC>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta);
+      break;
+    default: break;
   }
 }
 
 void launch_gemm(hipStream_t st, int nb, int mode, const double *A, int64_t sA, int lda, const double *B,
                  int64_t sB, int ldb, double *C, int64_t sC, int ldc, int M, int N, int K, double alpha,
-                 double beta) {
+                 double beta, int prec) {
   if (nb <= 0 || M <= 0 || N <= 0) return;
-  switch (mode) {
-    case 0: gemm_mode<0>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta); break;
-    case GEMM_TB: gemm_mode<GEMM_TB>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta); break;
-    case GEMM_TA: gemm_mode<GEMM_TA>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta); break;
-    case GEMM_TA | GEMM_TB:
-      gemm_mode<GEMM_TA | GEMM_TB>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta);
+  switch (prec) {
+    case GEMM_F32: gemm_prec<GEMM_F32>(st, nb, mode, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta); break;
+    case GEMM_BF16X3:
+      gemm_prec<GEMM_BF16X3>(st, nb, mode, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta);
       break;
-    default: break;
+    default: gemm_prec<GEMM_F64>(st, nb, mode, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta); break;
   }
 }
 

@@ -310,3 +310,48 @@ def test_apply_H_canonical_input_matches_plain(thck):
         err = _rel(M.to_dense(out.to_sites()), ref)
         print(f"truncated H|psi> declared canonical={decl}: rel err vs oracle tree {err:.3e}")
         assert err < 1e-8
+
+
+# ---------------------------------------------------------------------------
+# Mixed-precision contractions (thc_prec): the absorb products run in FP32 or
+# BF16x3 on MFMA with FP32 accumulation; factorisations, overlaps and the
+# Lanczos eigensolve stay FP64.  Untruncated results against the dense FP64
+# reference: 1e-5 relative (FP32), 1e-3 (BF16x3).  The error must also sit
+# above FP64 rounding, or the reduced-precision path did not run.
+# ---------------------------------------------------------------------------
+MIXED = [("f32", 1e-5), ("bf16x3", 1e-3)]
+
+
+@pytest.mark.parametrize("prec,tol", MIXED)
+@pytest.mark.parametrize("workload", ["L4_N8_D16", "L8_N32_D256"])
+def test_apply_H_mixed_precision_untruncated(thck, prec, tol, workload):
+    t, chi, zeta, sites = synth.make_workload(workload)
+    psi = M.scale(sites, 1.0 / M.norm(sites))
+    ctx = thck.Context(t, chi, zeta)
+    D = synth.WORKLOADS[workload]["D"]
+    out = ctx.apply_H(thck.DeviceMPS.from_sites(psi), D=D, prec=prec)
+    got = M.to_dense(out.to_sites())
+    ref = F.apply_H_dense(M.to_dense(psi), t, TH.thc_v(chi, zeta))
+    err = _rel(got, ref)
+    print(f"{workload} prec={prec}: rel err vs dense FP64 {err:.3e}")
+    assert err < tol
+    assert err > 1e-13
+
+
+@pytest.mark.parametrize("prec,tol", MIXED)
+def test_lanczos_mixed_precision_energies(thck, prec, tol):
+    # Ritz values of a mixed-precision Krylov run against the FP64 oracle
+    L, N = 3, 4
+    t, chi, zeta = synth.thc_factors(np.random.default_rng(16), L, N)
+    occ = synth.hartree_fock_occupation(L, 2)
+    hf = synth.occupation_mps_tensors(occ)
+    K = 4
+    st = OL.KrylovState(hf, K)
+    ctx = thck.Context(t, chi, zeta)
+    kr = thck.Krylov(ctx, thck.DeviceMPS.from_sites(hf), K, D=8, prec=prec)
+    for i in range(K):
+        rg, _, _ = OL.krylov_step(st, t, chi, zeta, D=8)
+        g, _, _ = kr.step()
+        err = np.max(np.abs(g - rg)) / max(1.0, np.max(np.abs(rg)))
+        print(f"lanczos prec={prec} step {i}: max Ritz error {err:.2e}")
+        assert err < tol
