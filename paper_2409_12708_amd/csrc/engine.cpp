@@ -218,7 +218,7 @@ struct Plan {
   Profile out;
   // per-job workspace layout (elements)
   int64_t oB = 0, oT = 0, oL = 0, oQs = 0, oM = 0, oY = 0, oW = 0, oZ = 0, oC = 0, oLz = 0, oQz = 0, oTf = 0,
-          oS = 0, oU = 0, oG = 0, oDet = 0, oZm = 0, oLam = 0, oScr = 0;
+          oS = 0, oU = 0, oG = 0, oDet = 0, oZm = 0, oLam = 0, oScr = 0, oTo = 0;
   int64_t sv = 0;  // stride of the d / e / tau vectors inside oDet
   std::vector<int64_t> qs_off;  // offset of Q_j inside Qs
   int64_t per_job = 0;
@@ -275,7 +275,7 @@ Plan make_plan(int kind, const Profile &pa, const Profile *pb, int D, bool rc_in
   P.out.b = P.k;
   P.out.pack();
   int64_t mB = 0, mT = 0, mL = 0, mM = 0, mW = 0, mZ = 0, mQz = 0, mLz = 0, mS = 0, mTf = 0, mU = 0, mG = 0,
-          mZm = 0, mScr = 0;
+          mZm = 0, mScr = 0, mTo = 0;
   P.qs_off.assign(n, 0);
   int64_t qs = 0;
   double fl = 0.0;
@@ -313,6 +313,7 @@ Plan make_plan(int kind, const Profile &pa, const Profile *pb, int D, bool rc_in
       mG = std::max(mG, (int64_t)m * m);
       mZm = std::max(mZm, (int64_t)m * kk);
       mScr = std::max(mScr, tri_eig_scratch(m, kk));
+      mTo = std::max(mTo, ormtr_tf_stride(m));
       fl += svd_flops(m, nc);
       fl += 2.0 * kk * nc * 2.0 * P.c[j + 2];  // absorb S V^T into site j+1
     }
@@ -345,6 +346,7 @@ Plan make_plan(int kind, const Profile &pa, const Profile *pb, int D, bool rc_in
   P.oZm = take(std::max<int64_t>(mZm, 1));
   P.oLam = take(std::max<int64_t>(mS, 1));
   P.oScr = take(std::max<int64_t>(mScr, 1));
+  P.oTo = take(std::max<int64_t>(mTo, 1));
   if (P.mode == 1) {
     P.sLt = std::max<int64_t>(P.sLt, 1);
     P.oLt = take(2 * ((P.sLt + 31) / 32 * 32));
@@ -494,7 +496,7 @@ struct Engine {
   void gemm(int nb, int mode, const double *A, int64_t sA, int lda, const double *B, int64_t sB, int ldb, double *C,
             int64_t sC, int ldc, int M, int N, int K, double alpha = 1.0, double beta = 0.0, int prec = GEMM_F64) {
     timed(THC_K_GEMM, 2.0 * M * N * (double)K * nb,
-          ShapeKey{THC_K_GEMM, nb, M, N, K, mode + (beta != 0.0 ? 4 : 0) + 8 * prec},
+          ShapeKey{THC_K_GEMM, nb, M, N, K, mode + (beta != 0.0 ? 16 : 0) + 32 * prec},
           [&] { launch_gemm(st, nb, mode, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta, prec); });
   }
   int lq(int nb, double *X, int64_t sX, int m, int n, double *L, int64_t sL, double *Q, int64_t sQ, double *T,
@@ -516,10 +518,10 @@ struct Engine {
     return rc;
   }
   int ormtr(int nb, const double *A, int64_t sA, int m, const double *tau, int64_t sv, double *Z, int64_t sZ, int kk,
-            double *Ut, int64_t sU, bool zout) {
+            double *Ut, int64_t sU, bool zout, double *Tf, int64_t sTf) {
     int rc = 0;
     timed(THC_K_ORMTR, 2.0 * m * (double)m * kk * nb, ShapeKey{THC_K_ORMTR, nb, m, kk, 0, zout ? 1 : 0},
-          [&] { rc = launch_ormtr(st, nb, A, sA, m, tau, sv, Z, sZ, kk, Ut, sU, zout); });
+          [&] { rc = launch_ormtr(st, nb, A, sA, m, tau, sv, Z, sZ, kk, Ut, sU, zout, Tf, sTf); });
     return rc;
   }
 
@@ -702,12 +704,13 @@ struct Engine {
     for (int j = 0; j + 1 < n && !jacobi; ++j) {
       const int m = 2 * P.k[j], nc = P.c[j + 1], kk = P.k[j + 1];
       // Gram G = Y Y^T, Y = M_j (m x nc)
-      gemm(nb, GEMM_TB, Mb, S, nc, Mb, S, nc, Gb, S, m, m, m, nc);
+      // (the tridiagonalisation reads the upper triangle only)
+      gemm(nb, GEMM_TB | GEMM_UPPER, Mb, S, nc, Mb, S, nc, Gb, S, m, m, m, nc);
       if (sytrd(nb, Gb, S, m, Db, Eb, Taub, S) != 0) raise(THC_EINVAL, "site matrix too tall for sytrd");
       if (tri_eig(nb, Db, Eb, S, m, kk, Zm, S, Lam, S, Scr, S) != 0)
         raise(THC_EINVAL, "site matrix too tall for the tridiagonal eigensolver");
       // eigenvectors as the columns of Z (m x kk)
-      if (ormtr(nb, Gb, S, m, Taub, S, Zm, S, kk, Zb, S, true) != 0) raise(THC_EINVAL, "ormtr size");
+      if (ormtr(nb, Gb, S, m, Taub, S, Zm, S, kk, Zb, S, true, W + P.oTo, S) != 0) raise(THC_EINVAL, "ormtr size");
       // orthonormal rows spanning the top-kk eigenvectors: LQ of Z^T, given
       // transposed; Qz holds Q^T (m x kk)
       if (lq(nb, Zb, S, kk, m, Lz, S, Qz, S, Tf, S, true) != 0)

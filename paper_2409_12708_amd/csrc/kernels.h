@@ -27,8 +27,10 @@ int lq_t_stride(int k);
 void launch_construct(hipStream_t st, const CJob *jobs, int nb, int site, int n_sites, int64_t in_off_a,
                       int64_t in_off_b, int la, int ra, int lb, int rb, double *out, int64_t out_stride, int lo,
                       int ro);
-// GEMM modes (bits): B given transposed, A given transposed.
-constexpr int GEMM_TB = 1, GEMM_TA = 2;
+// GEMM modes (bits): B given transposed, A given transposed; with UPPER only
+// the output tiles that reach the diagonal or above it are computed (the
+// upper triangle of a symmetric product; entries below it are not written).
+constexpr int GEMM_TB = 1, GEMM_TA = 2, GEMM_UPPER = 4;
 // contraction precision of a GEMM (operands and result are FP64 in memory)
 constexpr int GEMM_F64 = 0, GEMM_F32 = 1, GEMM_BF16X3 = 2;
 // C = alpha op(A) op(B) + beta C (beta = 0: C is not read).
@@ -69,8 +71,10 @@ int launch_sytrd(hipStream_t st, int nb, double *A, int64_t sA, int m, double *d
 int launch_tri_eig(hipStream_t st, int nb, const double *d, const double *e, int64_t sv, int m, int kk, double *Z,
                    int64_t sZ, double *lam, int64_t sl, double *scr, int64_t sscr);
 // U = Q_H Z; written as rows of Ut (kk x m), or with zout as Z itself (m x kk).
+// Tf: workspace for the blocks' compact-WY factors, ormtr_tf_stride(m) per job.
+int64_t ormtr_tf_stride(int m);
 int launch_ormtr(hipStream_t st, int nb, const double *A, int64_t sA, int m, const double *tau, int64_t sv, double *Z,
-                 int64_t sZ, int kk, double *Ut, int64_t sU, bool zout = false);
+                 int64_t sZ, int kk, double *Ut, int64_t sU, bool zout, double *Tf, int64_t sTf);
 // qt: Q given as its transpose (m x kk) instead of kk x m.
 void launch_svd_finish2(hipStream_t st, int nb, const double *Q, int64_t sQ, int m, int kk, double *C, int64_t sC,
                         int n, double cutoff, const double *d, int64_t sv, double *U, int64_t sU, int *rank,

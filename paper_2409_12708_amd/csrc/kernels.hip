@@ -167,7 +167,7 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(const double *__restrict__ A,
                                                    const double *__restrict__ B, int64_t sB, int ldb,
                                                    double *__restrict__ C, int64_t sC, int ldc, int M, int N,
                                                    int K, int tiles_m, int tiles_n, double alpha, double beta) {
-  constexpr bool TB = (MODE & GEMM_TB) != 0, TA = (MODE & GEMM_TA) != 0;
+  constexpr bool TB = (MODE & GEMM_TB) != 0, TA = (MODE & GEMM_TA) != 0, UP = (MODE & GEMM_UPPER) != 0;
   constexpr int BK = 16;
   constexpr int WM = BM / 32, WN = BN / 32;  // 16x16 blocks per wave
   constexpr int LA = BK + 1;                 // row stride of [rows][k] chunks
@@ -190,6 +190,7 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(const double *__restrict__ A,
   if ((G & 7) == 0) g = (g & 7) * (G >> 3) + (g >> 3);
   const int job = g / T, t = g % T;
   const int m0 = (t / tiles_n) * BM, n0 = (t % tiles_n) * BN;
+  if (UP && m0 >= n0 + BN) return;  // tile strictly below the diagonal: not needed
   A += (int64_t)job * sA;
   B += (int64_t)job * sB;
   C += (int64_t)job * sC;
@@ -1217,21 +1218,75 @@ __global__ void k_ritz(const double *__restrict__ Mm, const double *__restrict__
 //              iteration with partial-pivoting tridiagonal LU
 //   ormtr      U^T = Z^T Q_H^T, blocked compact-WY application
 // ---------------------------------------------------------------------------
+// ormtr_tfac: the forward compact-WY factor T of each block of 16 reflectors
+// left by sytrd2 (v_i[i+1] = 1, v_i[r] = A[i][r] for r >= i+2), so that
+// H_{i0} ... H_{i0+15} = I - V^T T V.  One workgroup per (block, matrix):
+// G[q][p] = v_q . v_p (q < p), then T[0:p, p] = -tau_p T[0:p, 0:p] G[0:p, p].
+// Output Tf[job][block] (16 x 16, row-major).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_ormtr_tfac(const double *__restrict__ Ab, int64_t sA, int m,
+                                                    const double *__restrict__ taub, int64_t sv,
+                                                    double *__restrict__ Tfb, int64_t sTf) {
+  constexpr int NB = 16, VL = 516;
+  __shared__ double V[NB * VL];
+  __shared__ double G[NB * NB], T[NB * NB], tv[NB];
+  const int bi = blockIdx.x, job = blockIdx.y;
+  const double *A = Ab + (int64_t)job * sA;
+  const double *tau = taub + (int64_t)job * sv;
+  double *Tf = Tfb + (int64_t)job * sTf + (int64_t)bi * NB * NB;
+  const int tid = threadIdx.x;
+  const int nref = m - 2, i0 = bi * NB;
+  const int pb = (nref - i0) < NB ? (nref - i0) : NB;
+  for (int e = tid; e < NB * 512; e += 256) {
+    const int q = e / 512, r = e % 512;
+    const int i = i0 + q;
+    double x = 0.0;
+    if (q < pb && r < m) {
+      if (r == i + 1) x = 1.0;
+      else if (r > i + 1) x = A[(int64_t)i * m + r];
+    }
+    V[q * VL + r] = x;
+  }
+  if (tid < NB) tv[tid] = (tid < pb) ? tau[i0 + tid] : 0.0;
+  __syncthreads();
+  {
+    const int q = tid / NB, p = tid % NB;
+    double acc = 0.0;
+    if (q < p)
+      for (int r = i0 + p + 1; r < m; ++r) acc += V[q * VL + r] * V[p * VL + r];
+    G[tid] = acc;
+  }
+  __syncthreads();
+  if (tid < NB) {
+    const int q = tid;
+    for (int p = 0; p < NB; ++p) {
+      double acc = 0.0;
+      for (int r = q; r < p; ++r) acc += T[q * NB + r] * G[r * NB + p];
+      if (q < p) T[q * NB + p] = -tv[p] * acc;
+      else if (q == p) T[q * NB + p] = tv[p];
+      else T[q * NB + p] = 0.0;
+    }
+  }
+  __syncthreads();
+  Tf[tid] = T[tid];
+}
+
+// ---------------------------------------------------------------------------
 // ormtr2: U = Q_H Z = H_0 H_1 ... H_{m-3} Z for the reflectors left by
-// sytrd2 (v_i[i+1] = 1, v_i[r] = A[i][r] for r >= i+2) and m <= 512.  Z is cut
-// into slabs of 64 columns, one workgroup (8 waves) per slab; wave w keeps
-// rows [64w, 64w + 64) of its slab in registers for the whole pass, as 4 x 4
-// MFMA blocks in the accumulator layout (lane l, register r <-> row
-// R0 + l/16 + 4r, column n0 + l%16).  Register r of such a block is also the
-// B operand of the 16x16x4 step over rows R0 + 4r .. R0 + 4r + 3, so each
-// block of 16 reflectors (last block first) costs
+// sytrd2 and m <= 512, with the blocks' T factors from ormtr_tfac.  Z is
+// cut into slabs of 64 columns, one workgroup (8 waves) per slab; wave w
+// keeps rows [64w, 64w + 64) of its slab in registers for the whole pass,
+// as 4 x 4 MFMA blocks in the accumulator layout (lane l, register r <->
+// row R0 + l/16 + 4r, column n0 + l%16).  Register r of such a block is
+// also the B operand of the 16x16x4 step over rows R0 + 4r .. R0 + 4r + 3,
+// so each block of 16 reflectors (last block first) costs
 //   W  = V Z        16 x 64, each wave over its 64 rows, summed in LDS
-//   X  = T W        T the forward compact-WY factor of the block
+//   X  = T W
 //   Z -= V^T X      accumulated into the resident blocks
-// and Z is read once and written once (transposed, as rows of Ut).
+// Z is read once and written once.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(512) void k_ormtr2(const double *__restrict__ Ab, int64_t sA, int m,
-                                                const double *__restrict__ taub, int64_t sv,
+                                                const double *__restrict__ Tfb, int64_t sTf,
                                                 const double *__restrict__ Zb, int64_t sZ, int kk,
                                                 double *__restrict__ Utb, int64_t sU, int nslab, int zout) {
   constexpr int NB = 16, NWV = 8, CS = 64, VL = 516;
@@ -1241,11 +1296,9 @@ __global__ __launch_bounds__(512) void k_ormtr2(const double *__restrict__ Ab, i
   double *Ws = Wp + NWV * NB * CS;   // NB x CS
   double *Xs = Ws + NB * CS;         // NB x CS
   double *T = Xs + NB * CS;          // NB x NB
-  double *G = T + NB * NB;           // NB x NB: v_q . v_p
-  double *tv = G + NB * NB;          // NB
   const int job = blockIdx.x / nslab, slab = blockIdx.x % nslab;
   const double *A = Ab + (int64_t)job * sA;
-  const double *tau = taub + (int64_t)job * sv;
+  const double *Tf = Tfb + (int64_t)job * sTf;
   const double *Z = Zb + (int64_t)job * sZ;
   double *Ut = Utb + (int64_t)job * sU;
   const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
@@ -1268,10 +1321,11 @@ __global__ __launch_bounds__(512) void k_ormtr2(const double *__restrict__ Ab, i
   for (int bi = nblk - 1; bi >= 0; --bi) {
     const int i0 = bi * NB;
     const int pb = (nref - i0) < NB ? (nref - i0) : NB;
-    // reflectors of the block: 16 consecutive columns of A per row (coalesced)
-    for (int e = tid; e < NB * 512; e += 512) {
-      const int q = e / 512, r = e % 512;
-      const int i = i0 + q;
+    __syncthreads();  // the previous block's readers of V / T are done
+    // thread tid loads V[q][tid] (q = 0..15), coalesced along the rows of A
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int i = i0 + q, r = tid;
       double x = 0.0;
       if (q < pb && r < m) {
         if (r == i + 1) x = 1.0;
@@ -1279,15 +1333,8 @@ __global__ __launch_bounds__(512) void k_ormtr2(const double *__restrict__ Ab, i
       }
       V[q * VL + r] = x;
     }
-    if (tid < NB) tv[tid] = (tid < pb) ? tau[i0 + tid] : 0.0;
+    if (tid < NB * NB) T[tid] = Tf[(int64_t)bi * NB * NB + tid];
     __syncthreads();
-    if (tid < NB * NB) {
-      const int q = tid / NB, p = tid % NB;
-      double acc = 0.0;
-      if (q < p)
-        for (int r = i0 + p + 1; r < m; ++r) acc += V[q * VL + r] * V[p * VL + r];
-      G[tid] = acc;
-    }
     // partial W = V Z over this wave's rows
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -1300,17 +1347,6 @@ __global__ __launch_bounds__(512) void k_ormtr2(const double *__restrict__ Ab, i
       for (int r = 0; r < 4; ++r) Wp[(wv * NB + lk + 4 * r) * CS + 16 * j + li] = acc[r];
     }
     __syncthreads();
-    if (tid < NB) {
-      // T[0:p, p] = -tau_p T[0:p, 0:p] (V^T v_p)[0:p]; lane q owns row q of T
-      const int q = tid;
-      for (int p = 0; p < NB; ++p) {
-        double acc = 0.0;
-        for (int r = q; r < p; ++r) acc += T[q * NB + r] * G[r * NB + p];
-        if (q < p) T[q * NB + p] = -tv[p] * acc;
-        else if (q == p) T[q * NB + p] = tv[p];
-        else T[q * NB + p] = 0.0;
-      }
-    }
     for (int e = tid; e < NB * CS; e += 512) {
       double acc = 0.0;
 #pragma unroll
@@ -1338,7 +1374,6 @@ __global__ __launch_bounds__(512) void k_ormtr2(const double *__restrict__ Ab, i
         for (int j = 0; j < 4; ++j) z[i][j] = mfma16(a, b[j], z[i][j]);
       }
     }
-    __syncthreads();
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -1969,6 +2004,9 @@ static void gemm_prec(hipStream_t st, int nb, int mode, const double *A, int64_t
                       int64_t sB, int ldb, double *C, int64_t sC, int ldc, int M, int N, int K, double alpha,
                       double beta) {
   switch (mode) {
+    case GEMM_TB | GEMM_UPPER:
+      gemm_mode<GEMM_TB | GEMM_UPPER, PREC>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta);
+      break;
     case 0: gemm_mode<0, PREC>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta); break;
     case GEMM_TB: gemm_mode<GEMM_TB, PREC>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta); break;
     case GEMM_TA: gemm_mode<GEMM_TA, PREC>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta); break;
@@ -2169,15 +2207,23 @@ int launch_tri_eig(hipStream_t st, int nb, const double *d, const double *e, int
   return 0;
 }
 
+int64_t ormtr_tf_stride(int m) {
+  const int nref = m - 2;
+  return nref > 0 ? (int64_t)((nref + 15) / 16) * 256 : 0;
+}
+
 int launch_ormtr(hipStream_t st, int nb, const double *A, int64_t sA, int m, const double *tau, int64_t sv, double *Z,
-                 int64_t sZ, int kk, double *Ut, int64_t sU, bool zout) {
+                 int64_t sZ, int kk, double *Ut, int64_t sU, bool zout, double *Tf, int64_t sTf) {
   if (m > 512) return -1;
-  const size_t lds = (16 * 516 + 8 * 16 * 64 + 2 * 16 * 64 + 2 * 256 + 16) * sizeof(double);
+  const int nslab = (kk + 63) / 64;
+  if (nslab == 0 || nb <= 0) return 0;
+  const int nref = m - 2;
+  const int nblk = nref > 0 ? (nref + 15) / 16 : 0;
+  if (nblk > 0) hipLaunchKernelGGL(k_ormtr_tfac, dim3(nblk, nb), dim3(256), 0, st, A, sA, m, tau, sv, Tf, sTf);
+  const size_t lds = (16 * 516 + 8 * 16 * 64 + 2 * 16 * 64 + 256) * sizeof(double);
   static bool attr = false;
   if (!attr) { set_lds(k_ormtr2, lds); attr = true; }
-  const int nslab = (kk + 63) / 64;
-  if (nslab == 0) return 0;
-  hipLaunchKernelGGL(k_ormtr2, dim3(nb * nslab), dim3(512), lds, st, A, sA, m, tau, sv, Z, sZ, kk, Ut, sU, nslab,
+  hipLaunchKernelGGL(k_ormtr2, dim3(nb * nslab), dim3(512), lds, st, A, sA, m, Tf, sTf, Z, sZ, kk, Ut, sU, nslab,
                      zout ? 1 : 0);
   return 0;
 }
