@@ -40,6 +40,35 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+KERNEL_FN = {"lq": "k_lq2", "sytrd": "k_sytrd2", "tri_eig": "k_tri_eig", "ormtr": "k_ormtr2", "gemm": "k_gemm_mfma"}
+
+
+def kernel_digest(fn: str):
+    """SHA-256 of a kernel's source text (from its signature line to its closing brace)."""
+    import hashlib
+    path = os.path.join(ROOT, "paper_2409_12708_amd", "csrc", "kernels.hip")
+    src = open(path).read().splitlines()
+    try:
+        i = next(k for k, l in enumerate(src) if f"void {fn}(" in l)
+        j = next(k for k in range(i, len(src)) if src[k] == "}")
+    except StopIteration:
+        return None
+    return hashlib.sha256("\n".join(src[i:j + 1]).encode()).hexdigest()
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed counter runs (profiles/), or None
+    when there are none or the kernel's source has changed since they were taken."""
+    fn = KERNEL_FN.get(kernel)
+    path = os.path.join(ROOT, "profiles", f"traffic_{fn}_{workload}.json")
+    if not fn or not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_sha256") != kernel_digest(fn):
+        return None
+    return int(rec["bytes_per_launch"])
+
+
 def cpu_baseline(workload: str, seconds_hint: float = 20.0):
     """Time the FP64 oracle on a bounded sample of the same workload: one
     layer-compression and one add-compression at the full bond dimension,
@@ -169,7 +198,7 @@ def main():
         "peak": round(peak, 2),
         "unit": "TFLOP/s",
         "frac": round(achieved / peak, 4),
-        "traffic": None,
+        "traffic": measured_traffic(dom, args.workload),
         "avg_launch_ms": round(kms[dom] / max(kn[dom], 1), 4),
         "launches": int(kn[dom]),
     }
@@ -205,6 +234,8 @@ def main():
             "contraction_precision": args.prec,
         },
         "model_tflops_per_s": flops_model / elapsed / 1e12,
+        # model flops of the whole step over its time, against the FP64 matrix peak
+        "path_fraction_of_fp64_peak": flops_model / elapsed / 1e12 / FP64_MFMA_PEAK_TFLOPS,
         "lowest_ritz": float(ritz[0]) if ritz is not None else None,
         "fp64_contractions": f64,
         "roofline": roofline,
