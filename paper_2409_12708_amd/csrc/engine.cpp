@@ -639,7 +639,8 @@ struct Engine {
   }
 
   // Run the compression of nb jobs (same plan).  Output slots in jobs[].out.
-  void compress(const Plan &P, const std::vector<CJob> &hjobs, int D) {
+  // nrc: the first nrc jobs get right-canonical outputs (all when negative)
+  void compress(const Plan &P, const std::vector<CJob> &hjobs, int D, int nrc = -1) {
     const int nb = (int)hjobs.size();
     if (nb == 0) return;
     const int n = P.n;
@@ -750,7 +751,8 @@ struct Engine {
     launch_scatter(st, nb, dj, P.out.off[n - 1], Mb, S, (int64_t)P.k[n - 1] * 2);
     ++launches;
     // outputs in right-canonical form (inputs of later structured sweeps)
-    launches += recanon(P, dj, nb);
+    const int nr = (nrc < 0 || nrc > nb) ? nb : nrc;
+    if (nr > 0) launches += recanon(P, dj, nr);
     HIPCHK(hipGetLastError());
     // statistics: read back ranks/disc/sweeps of this batch (async into host arrays after sync at end)
     h_rank.resize((size_t)nb * n);
@@ -916,6 +918,10 @@ struct JobSpec {
   const double *y;
   int dag;
   double scale;  // for layer jobs (multiplies site 0)
+  // the output must be right-canonical (it will be the first input of a
+  // structured compression); otherwise the re-canonicalisation is skipped
+  // and the output is left in the truncation sweep's (left-canonical) form
+  bool rc_out = true;
 };
 
 // Run a list of job specs (any mix of signatures); returns output nodes in order.
@@ -948,11 +954,16 @@ std::vector<Node> run_jobs(Engine &E, const std::vector<JobSpec> &specs, int D) 
       const JobSpec &sf = sp[sg.second[0]];
       Plan P = make_plan(sf.kind, sf.a->prof, sf.kind ? &sf.b->prof : nullptr, D, sf.a->rc);
       int B = E.batch_limit(P);
+      // jobs whose output must be right-canonical first: the
+      // re-canonicalisation then runs on a leading part of each batch
+      std::stable_partition(sg.second.begin(), sg.second.end(), [&](size_t i) { return sp[i].rc_out; });
       for (size_t i0 = 0; i0 < sg.second.size(); i0 += B) {
         size_t i1 = std::min(sg.second.size(), i0 + B);
         std::vector<CJob> hj;
+        int nrc = 0;
         for (size_t t = i0; t < i1; ++t) {
           size_t i = sg.second[t];
+          if (sp[i].rc_out) ++nrc;
           const JobSpec &s = sp[i];
           CJob j{};
           j.kind = s.kind;
@@ -971,11 +982,11 @@ std::vector<Node> run_jobs(Engine &E, const std::vector<JobSpec> &specs, int D) 
           out[i].prof = P.out;
           out[i].coef = 1.0;
           out[i].owned = true;
-          out[i].rc = true;
+          out[i].rc = s.rc_out;
           j.out = out[i].data;
           hj.push_back(j);
         }
-        E.compress(P, hj, D);
+        E.compress(P, hj, D, nrc);
         const int nbt = (int)hj.size();
         for (size_t t = i0; t < i1; ++t) {
           Node &nd = out[sg.second[t]];
@@ -1003,12 +1014,22 @@ struct Reducer {
   Engine &E;
   int D;
   std::vector<std::vector<Node>> levels;
+  // nodes ever appended to each level: a node's position there decides its
+  // role, first (even) or second (odd) member of its pair
+  std::vector<size_t> pushed;
   Reducer(Engine &e, int D_) : E(e), D(D_) {}
 
-  void push(const Node &leaf) {
-    if (levels.empty()) levels.resize(1);
-    levels[0].push_back(leaf);
+  void append(size_t l, const Node &nd) {
+    if (levels.size() < l + 1) levels.resize(l + 1);
+    if (pushed.size() < l + 1) pushed.resize(l + 1, 0);
+    levels[l].push_back(nd);
+    ++pushed[l];
   }
+  void push(const Node &leaf) { append(0, leaf); }
+  // only the first member of a pair has to be right-canonical (a sum puts a
+  // canonical term first); an odd node carried up is the last, even-placed
+  // one of its level
+  static bool needs_rc(size_t position) { return position % 2 == 0; }
   size_t ready_pairs() const {
     size_t r = 0;
     for (auto &q : levels) r += q.size() / 2;
@@ -1031,18 +1052,21 @@ struct Reducer {
       taken[l].assign(levels[l].begin(), levels[l].begin() + 2 * np);
       levels[l].erase(levels[l].begin(), levels[l].begin() + 2 * np);
     }
+    std::vector<size_t> next(taken.size() + 1, 0);  // positions the results will take
+    for (size_t l = 0; l < taken.size(); ++l) next[l + 1] = (l + 1 < pushed.size()) ? pushed[l + 1] : 0;
     for (size_t l = 0; l < taken.size(); ++l)
       for (size_t p = 0; p + 1 < taken[l].size(); p += 2) {
-        specs.push_back(JobSpec{1, &taken[l][p], &taken[l][p + 1], nullptr, 0, 1.0});
+        JobSpec js{1, &taken[l][p], &taken[l][p + 1], nullptr, 0, 1.0};
+        js.rc_out = needs_rc(next[l + 1]++);
+        specs.push_back(js);
         where.push_back({l, p / 2});
       }
     if (specs.empty()) return;
     std::vector<Node> res = run_jobs(E, specs, D);
     for (auto &t : taken)
       for (auto &nd : t) release(E.c, nd);
-    if (levels.size() < taken.size() + 1) levels.resize(taken.size() + 1);
     // results go to the next level in pair order (levels before higher ones)
-    for (size_t i = 0; i < res.size(); ++i) levels[where[i].first + 1].push_back(res[i]);
+    for (size_t i = 0; i < res.size(); ++i) append(where[i].first + 1, res[i]);
   }
   void flush(size_t min_pairs) {
     const size_t b = std::max<size_t>(1, min_pairs);
@@ -1061,9 +1085,9 @@ struct Reducer {
       if (nonempty <= 1) return nonempty ? levels[top][0] : Node{};
       for (size_t l = 0; l < levels.size(); ++l)
         if (levels[l].size() == 1 && l < top) {
-          if (levels.size() < l + 2) levels.resize(l + 2);
-          levels[l + 1].push_back(levels[l][0]);
+          const Node nd = levels[l][0];
           levels[l].clear();
+          append(l + 1, nd);
           break;
         }
     }
@@ -1217,7 +1241,11 @@ Node apply_H_nodes(Engine &E, const Node &psi, int D, int D_sum) {
     for (size_t i = i0; i < i1; ++i) s1.push_back(JobSpec{0, leaves[i].src, nullptr, leaves[i].y, 0, leaves[i].scale});
     std::vector<Node> a1 = run_jobs(E, s1, D);
     std::vector<JobSpec> s2;
-    for (size_t i = i0; i < i1; ++i) s2.push_back(JobSpec{0, &a1[i - i0], nullptr, leaves[i].y, 1, 1.0});
+    for (size_t i = i0; i < i1; ++i) {
+      JobSpec js{0, &a1[i - i0], nullptr, leaves[i].y, 1, 1.0};
+      js.rc_out = Reducer::needs_rc(i);  // leaf i is node i of the tree's first level
+      s2.push_back(js);
+    }
     std::vector<Node> a2 = run_jobs(E, s2, D);
     for (auto &nd : a1) release(c, nd);
     for (auto &nd : a2) red.push(nd);

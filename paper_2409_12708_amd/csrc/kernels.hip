@@ -1689,13 +1689,28 @@ __global__ __launch_bounds__(512) void k_sytrd2(double *__restrict__ Ab, int64_t
 
 
 // Sturm count: number of eigenvalues of the symmetric tridiagonal (d, e) below x.
+// quotient through the hardware FP64 reciprocal estimate refined by one
+// Newton step (r <- r + r (1 - b r)), then one product: a few ulps instead
+// of the correctly rounded division's longer sequence.  Used where such a
+// relative perturbation only perturbs the problem by as much: Sturm counts
+// (a backward-stable recurrence), and the LU and solves of inverse
+// iteration, whose iterate converges to the same vector.
+__device__ __forceinline__ double rcp_nr(double b) {
+  // the estimate flushes denormal inputs (1/0 = inf): magnitudes below
+  // 1e-300 are raised to it, as a zero pivot is replaced by a tiny one
+  const double bb = (fabs(b) < 1e-300) ? copysign(1e-300, b) : b;
+  const double r = __builtin_amdgcn_rcp(bb);
+  return fma(r, fma(-bb, r, 1.0), r);
+}
+__device__ __forceinline__ double qdiv(double a, double b) { return a * rcp_nr(b); }
+
 __device__ __forceinline__ int sturm_count(const double *d, const double *e2, int m, double x, double pivmin) {
   int cnt = 0;
   double q = d[0] - x;
   if (fabs(q) < pivmin) q = -pivmin;
   if (q < 0.0) ++cnt;
   for (int k = 1; k < m; ++k) {
-    q = (d[k] - x) - e2[k - 1] / q;
+    q = (d[k] - x) - qdiv(e2[k - 1], q);
     if (fabs(q) < pivmin) q = -pivmin;
     if (q < 0.0) ++cnt;
   }
@@ -1724,12 +1739,12 @@ __device__ void inv_iter_one(const double *sd, const double *se, int m, int kk, 
     const int64_t o = (int64_t)k * kk + t;
     if (fabs(r0) >= fabs(l)) {
       if (r0 == 0.0) r0 = tiny;
-      const double mult = l / r0;
+      const double mult = qdiv(l, r0);
       U0[o] = r0; U1[o] = r1; U2[o] = r2; ML[o] = mult; SW[o] = 0;
       r0 = an - mult * r1;
       r1 = bn - mult * r2;
     } else {
-      const double mult = r0 / l;
+      const double mult = qdiv(r0, l);
       U0[o] = l; U1[o] = an; U2[o] = bn; ML[o] = mult; SW[o] = 1;
       const double n0 = r1 - mult * an, n1 = r2 - mult * bn;
       r0 = n0;
@@ -1768,7 +1783,8 @@ __device__ void inv_iter_one(const double *sd, const double *se, int m, int kk, 
     double x1 = 0.0, x2 = 0.0, mx = 0.0;
     for (int k = m - 1; k >= 0; --k) {
       const int64_t o = (int64_t)k * kk + t;
-      double x = (Z[o] - U1[o] * x1 - U2[o] * x2) / U0[o];
+      const double iu = rcp_nr(U0[o]);
+      double x = (Z[o] - U1[o] * x1 - U2[o] * x2) * iu;
       if (fabs(x) > 1e150) {
         const double s = 1e-150;
         for (int q = k + 1; q < m; ++q) Z[(int64_t)q * kk + t] *= s;
@@ -1776,7 +1792,7 @@ __device__ void inv_iter_one(const double *sd, const double *se, int m, int kk, 
         x1 *= s;
         x2 *= s;
         mx *= s;
-        x = (Z[o] * s - U1[o] * x1 - U2[o] * x2) / U0[o];
+        x = (Z[o] * s - U1[o] * x1 - U2[o] * x2) * iu;
       }
       Z[o] = x;
       x2 = x1;
