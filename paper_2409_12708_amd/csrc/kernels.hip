@@ -1942,8 +1942,6 @@ __global__ __launch_bounds__(256) void k_svd_finish2(const double *__restrict__ 
                                                      double *__restrict__ Ub, int64_t sU,
                                                      int *__restrict__ rank_out, double *__restrict__ disc_out, int qt) {
   __shared__ double nr[1024];
-  __shared__ int s_rank;
-  __shared__ double s_keep2, s_smax;
   const int job = blockIdx.x;
   const double *Q = Qb + (int64_t)job * sQ;
   double *Cc = Cb + (int64_t)job * sC;
@@ -1967,9 +1965,6 @@ __global__ __launch_bounds__(256) void k_svd_finish2(const double *__restrict__ 
       else nr[t] = -1.0;
     }
     if (!(smax > 0.0)) nr[0] = 0.0;  // zero matrix: keep one (zero) column
-    s_rank = last + 1;
-    s_keep2 = keep2;
-    s_smax = smax;
     double tr = 0.0;
     for (int k = 0; k < m; ++k) tr += db[(int64_t)job * sv + k];
     rank_out[job] = last + 1;
