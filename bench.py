@@ -40,7 +40,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-KERNEL_FN = {"lq": "k_lq2", "sytrd": "k_sytrd2", "tri_eig": "k_tri_eig", "ormtr": "k_ormtr2", "gemm": "k_gemm_mfma"}
+KERNEL_FN = {"lq": "k_lq2", "sytrd": "k_sytrd", "tri_eig": "k_tri_eig", "ormtr": "k_ormtr2", "gemm": "k_gemm_mfma"}
 
 
 def kernel_digest(fn: str):
@@ -191,7 +191,7 @@ def main():
     peak = FP64_VALU_PEAK_TFLOPS if alu else FP64_MFMA_PEAK_TFLOPS
     roofline = {
         "bound": "alu" if alu else "mfma",
-        "kernel": {"lq": "k_lq2 (Householder LQ with Q, FP64)", "sytrd": "k_sytrd2 (tridiagonalisation, FP64)",
+        "kernel": {"lq": "k_lq2 (Householder LQ with Q, FP64)", "sytrd": "k_sytrd (tridiagonalisation, FP64)",
                    "ormtr": "k_ormtr2 (eigenvector back-transformation, FP64)",
                    "gemm": "k_gemm_mfma (FP64)"}.get(dom, dom),
         "achieved": round(achieved, 3),

@@ -1219,7 +1219,7 @@ __global__ void k_ritz(const double *__restrict__ Mm, const double *__restrict__
 //   ormtr      U^T = Z^T Q_H^T, blocked compact-WY application
 // ---------------------------------------------------------------------------
 // ormtr_tfac: the forward compact-WY factor T of each block of 16 reflectors
-// left by sytrd2 (v_i[i+1] = 1, v_i[r] = A[i][r] for r >= i+2), so that
+// left by sytrd (v_i[i+1] = 1, v_i[r] = A[i][r] for r >= i+2), so that
 // H_{i0} ... H_{i0+15} = I - V^T T V.  One workgroup per (block, matrix):
 // G[q][p] = v_q . v_p (q < p), then T[0:p, p] = -tau_p T[0:p, 0:p] G[0:p, p].
 // Output Tf[job][block] (16 x 16, row-major).
@@ -1273,7 +1273,7 @@ __global__ __launch_bounds__(256) void k_ormtr_tfac(const double *__restrict__ A
 
 // ---------------------------------------------------------------------------
 // ormtr2: U = Q_H Z = H_0 H_1 ... H_{m-3} Z for the reflectors left by
-// sytrd2 and m <= 512, with the blocks' T factors from ormtr_tfac.  Z is
+// sytrd and m <= 512, with the blocks' T factors from ormtr_tfac.  Z is
 // cut into slabs of 64 columns, one workgroup (8 waves) per slab; wave w
 // keeps rows [64w, 64w + 64) of its slab in registers for the whole pass,
 // as 4 x 4 MFMA blocks in the accumulator layout (lane l, register r <->
@@ -1387,36 +1387,48 @@ __global__ __launch_bounds__(512) void k_ormtr2(const double *__restrict__ Ab, i
 }
 
 // ---------------------------------------------------------------------------
-// sytrd2: Householder tridiagonalisation of a symmetric A (m <= MMAX), the
-// blocked scheme of LAPACK dsytrd/dlatrd.  Panels of NB reflectors: inside
-// a panel the trailing matrix is only read, y = A22 v corrected by the
-// panel's earlier reflectors (y -= V (W^T v) + W (V^T v)); after the panel
-// it is updated once, A22 -= V W^T + W V^T.  The kernel reads and writes the
+// sytrd: Householder tridiagonalisation of a symmetric A (m <= MMAX), the
+// blocked scheme of LAPACK dsytrd/dlatrd.  Panels of NB reflectors: inside a
+// panel the trailing matrix is only read, y = A22 v corrected by the panel's
+// earlier reflectors (y -= V (W^T v) + W (V^T v)); the panel's update
+// A22 -= V W^T + W V^T is applied once.  The kernel reads and writes the
 // upper triangle (row c, columns r >= c): the part of column i below the
 // diagonal is then the contiguous row i.  One workgroup (512 threads) per
 // matrix.  Outputs: d (m), e (m-1), tau (m-1); reflector i is
 // v_i = e_{i+1} + tail with the tail stored in A[i][i+2:].
-// The trailing matrix is read and written through a buffer resource: a row
-// offset is a scalar, and only a 64-column chunk that straddles the diagonal
-// or the end m masks lanes, by an offset past the end of the buffer (reads
-// give 0, stores are dropped), so the streaming loops carry no per-element
-// branches or predicates.
+//  * The trailing matrix is streamed through a buffer resource: a row offset
+//    is a scalar, and lanes outside the triangle or past m get an offset past
+//    the end of the buffer (reads give 0, stores are dropped), so the loads
+//    carry no branches and each sum waits only for the loads it uses.
+//  * The product streams the unscaled updated row x rather than v, so it does
+//    not wait for the reflector: on the rows after i,
+//    v = e_{i+1} + sc (x - alpha e_{i+1}), hence
+//    A22 v = sc A22 x + (1 - sc alpha) A22 e_{i+1}, and A22 e_{i+1} is row
+//    i+1 of A22 (symmetry), which the stream reads anyway: the wave that owns
+//    it keeps a copy in LDS, which is also the next column's row i+1.
+//  * The diagonal element enters both the row and the column sums; the sum
+//    is corrected once from the trailing diagonal kept in LDS.
+//  * The update of a panel is applied by the next panel's first column in
+//    the pass that forms its product (row c1 first, as that column's
+//    reflector), so the trailing matrix is read once less per panel.
+//  * Every thread forms the reflector from the wave partial sums itself:
+//    four barriers per column and no dependent global load.
 // ---------------------------------------------------------------------------
 template <int MMAX>
-__global__ __launch_bounds__(512) void k_sytrd2(double *__restrict__ Ab, int64_t sA, int m,
+__global__ __launch_bounds__(512) void k_sytrd(double *__restrict__ Ab, int64_t sA, int m,
                                                  double *__restrict__ db, double *__restrict__ eb,
                                                  double *__restrict__ taub, int64_t sv) {
-  constexpr int NB = 8, NT = 512, NW = NT / WAVE, CPL = MMAX / WAVE, RU = 4;
+  constexpr int NB = 8, NT = 512, NW = NT / WAVE, CPL = MMAX / WAVE, RU = 8;
+  static_assert(MMAX == NT, "one entry of each column vector per thread");
   extern __shared__ double lds[];
   double *VL = lds;                 // NB x MMAX reflectors of the panel
   double *WL = VL + NB * MMAX;      // NB x MMAX
-  double *x = WL + NB * MMAX;       // updated column i, then v
-  double *y = x + MMAX;
-  double *prow = y + MMAX;          // 4 x MMAX: row sums of the symmetric product, per 16-lane group
+  double *x = WL + NB * MMAX;       // row i updated by the panel (unscaled)
+  double *nr = x + MMAX;            // row i+1 of the panel-start trailing matrix
+  double *prow = nr + MMAX;         // 4 x MMAX: row sums per 16-lane group
   double *pp = prow + 4 * MMAX;     // NW x MMAX column partials
-  double *red = pp + NW * MMAX;     // reductions: 2 NW + 2 NB
-  __shared__ double s_tau, s_sc, s_alpha;
-  __shared__ int s_slow;
+  double *dg = pp + NW * MMAX;      // diagonal of the panel-start trailing matrix
+  double *red = dg + MMAX;          // reductions: 2 NW + 2 NB + NW
   double *A = Ab + (int64_t)blockIdx.x * sA;
   double *d = db + (int64_t)blockIdx.x * sv;
   double *e = eb + (int64_t)blockIdx.x * sv;
@@ -1431,22 +1443,28 @@ __global__ __launch_bounds__(512) void k_sytrd2(double *__restrict__ Ab, int64_t
     if (t * WAVE < c || t * WAVE + WAVE > m) return (r >= c && r < m) ? r * 8 : OOB;
     return r * 8;
   };
+  nr[tid] = tid < m ? A[tid] : 0.0;
+  dg[tid] = tid < m ? A[(int64_t)tid * m + tid] : 0.0;
+  __syncthreads();
   const int nref = m - 2;
   for (int i0 = 0; i0 < nref; i0 += NB) {
     const int nbp = (nref - i0) < NB ? (nref - i0) : NB;
     for (int j = 0; j < nbp; ++j) {
       const int i = i0 + j;
+      // the first column of a later panel applies the previous panel's
+      // rank-2k update in the same pass as its product
+      const bool fused = (j == 0 && i0 > 0);
       // (1) row i updated by the panel's earlier reflectors
-      double am = 0.0, ss = 0.0;
-      for (int r = i + tid; r < m; r += NT) {
-        double a = A[(int64_t)i * m + r];
-        for (int q = 0; q < j; ++q) a -= VL[q * MMAX + r] * WL[q * MMAX + i] + WL[q * MMAX + r] * VL[q * MMAX + i];
-        x[r] = a;
-        if (r >= i + 2) {
-          am = fmax(am, fabs(a));
-          ss += a * a;
+      double a = 0.0, am = 0.0, ss = 0.0;
+      if (tid >= i && tid < m) {
+        a = nr[tid];
+        for (int q = 0; q < j; ++q) a -= VL[q * MMAX + tid] * WL[q * MMAX + i] + WL[q * MMAX + tid] * VL[q * MMAX + i];
+        if (tid >= i + 2) {
+          am = fabs(a);
+          ss = a * a;
         }
       }
+      x[tid] = a;
       am = wave_max(am);
       ss = wave_sum(ss);
       if (lane == 0) {
@@ -1454,118 +1472,157 @@ __global__ __launch_bounds__(512) void k_sytrd2(double *__restrict__ Ab, int64_t
         red[NW + wid] = ss;
       }
       __syncthreads();
-      if (tid == 0) {
-        double amx = 0.0, s2 = 0.0;
-        for (int q = 0; q < NW; ++q) {
-          amx = fmax(amx, red[q]);
-          s2 += red[NW + q];
-        }
-        const double alpha = x[i + 1];
-        d[i] = x[i];
-        s_alpha = alpha;
-        s_slow = 0;
-        if (!(amx > 1e-290)) {  // only denormal dust below the subdiagonal: no reflection
-          s_tau = 0.0;
-          s_sc = 0.0;
-          e[i] = alpha;
-          tau[i] = 0.0;
-        } else if (s2 > 1e-280 && s2 < 1e280 && fabs(alpha) < 1e140) {
-          const double bs = -copysign(sqrt(alpha * alpha + s2), alpha);
-          s_tau = (bs - alpha) / bs;
-          s_sc = 1.0 / (alpha - bs);
-          e[i] = bs;
-          tau[i] = s_tau;
-        } else {
-          s_slow = 1;
-          red[2 * NW] = amx;
-        }
+      // (2) the reflector, formed by every thread from the partial sums
+      double amx = 0.0, s2 = 0.0;
+      for (int q = 0; q < NW; ++q) {
+        amx = fmax(amx, red[q]);
+        s2 += red[NW + q];
       }
-      __syncthreads();
-      if (s_slow) {  // squares out of range: norm of the scaled column
-        const double scl = fmax(red[2 * NW], fabs(s_alpha)), inv = 1.0 / scl;
+      const double alpha = x[i + 1];
+      double tp, sc, ei;
+      if (!(amx > 1e-290)) {  // only denormal dust below the subdiagonal: no reflection
+        tp = 0.0;
+        sc = 0.0;
+        ei = alpha;
+      } else if (s2 > 1e-280 && s2 < 1e280 && fabs(alpha) < 1e140) {
+        const double bs = -copysign(sqrt(alpha * alpha + s2), alpha);
+        tp = (bs - alpha) / bs;
+        sc = 1.0 / (alpha - bs);
+        ei = bs;
+      } else {  // squares out of range: norm of the scaled column
+        const double scl = fmax(amx, fabs(alpha)), inv = 1.0 / scl;
+        double t3 = 0.0;
+        if (tid >= i + 2 && tid < m) {
+          const double t = a * inv;
+          t3 = t * t;
+        }
+        t3 = wave_sum(t3);
+        if (lane == 0) red[2 * NW + 2 * NB + wid] = t3;
+        __syncthreads();
         double s3 = 0.0;
-        for (int r = i + 2 + tid; r < m; r += NT) {
-          const double t = x[r] * inv;
-          s3 += t * t;
-        }
-        s3 = wave_sum(s3);
-        if (lane == 0) red[NW + wid] = s3;
-        __syncthreads();
-        if (tid == 0) {
-          double s2 = 0.0;
-          for (int q = 0; q < NW; ++q) s2 += red[NW + q];
-          const double as = s_alpha * inv;
-          const double bs = -copysign(sqrt(as * as + s2), as);
-          s_tau = (bs - as) / bs;
-          s_sc = inv / (as - bs);
-          e[i] = bs * scl;
-          tau[i] = s_tau;
-        }
-        __syncthreads();
+        for (int q = 0; q < NW; ++q) s3 += red[2 * NW + 2 * NB + q];
+        const double as = alpha * inv;
+        const double bs = -copysign(sqrt(as * as + s3), as);
+        tp = (bs - as) / bs;
+        sc = inv / (as - bs);
+        ei = bs * scl;
       }
-      const double tp = s_tau, sc = s_sc;
-      // (2) v: unit at i+1, scaled tail (stored in row i for the back-transformation)
-      for (int r = tid; r < MMAX; r += NT) {
-        double vr = 0.0;
-        if (r == i + 1) {
-          vr = 1.0;
-        } else if (r > i + 1 && r < m && tp != 0.0) {
-          vr = x[r] * sc;
-          A[(int64_t)i * m + r] = vr;
-        }
-        VL[j * MMAX + r] = vr;
-        x[r] = vr;
+      const double ce = 1.0 - sc * alpha;  // weight of A22 e_{i+1}; in [1/2, 1] when reflecting
+      if (tid == 0) {
+        d[i] = x[i];
+        e[i] = ei;
+        tau[i] = tp;
       }
-      __syncthreads();
-      // (3) y = A22 v over the trailing rows c > i (upper triangle), RU rows
-      //     per pass, the next pass's rows loaded while this one is summed;
-      //     chunks with no element r >= c are skipped (scalar branches).  Row
-      //     sums stop at 16-lane group partials (summed in step 4); the lane's
-      //     own column sums pc need no reduction until the end.  Then the dot
-      //     products W_q.v and V_q.v of the earlier reflectors.
+      // (3) A22 x over the trailing rows c > i (upper triangle), RU rows per
+      //     wave and pass; chunks with no element r >= c are not summed.
+      //     Row sums stop at 16-lane group partials; the lane's column sums
+      //     pc are written once at the end.  The wave owning row i+1 keeps
+      //     it for the next column.  Then the dot products W_q.v and V_q.v.
       {
         double pc[CPL];
 #pragma unroll
         for (int t = 0; t < CPL; ++t) pc[t] = 0.0;
-        double ava[RU][CPL], avb[RU][CPL];
-        auto load_rows = [&](int cb, double (&dst)[RU][CPL]) {
+        const int step = RU * NW;
+        if (fused) {
+          // rows c > i: a = A - V W^T - W V^T with the previous panel's V, W
+          // (all NB reflectors), stored back, then summed as below
+          constexpr int RS = 2;
+          for (int c0 = i + 1 + RS * wvs; c0 < m; c0 += RS * NW) {
+            double av[RS][CPL], vc[RS][NB], wc[RS][NB], acc[RS], xc[RS];
 #pragma unroll
-          for (int u = 0; u < RU; ++u) {
-            const int c = cb + u;
+            for (int u = 0; u < RS; ++u) {
+              const int c = c0 + u;
+#pragma unroll
+              for (int t = 0; t < CPL; ++t)
+                av[u][t] = __builtin_bit_cast(
+                    double, __builtin_amdgcn_raw_buffer_load_b64(ra, chunk_off(c, t), c * m * 8, 0));
+#pragma unroll
+              for (int q = 0; q < NB; ++q) {
+                vc[u][q] = (c < m) ? VL[q * MMAX + c] : 0.0;
+                wc[u][q] = (c < m) ? WL[q * MMAX + c] : 0.0;
+              }
+              acc[u] = 0.0;
+              xc[u] = (c < m) ? x[c] : 0.0;
+            }
 #pragma unroll
             for (int t = 0; t < CPL; ++t) {
-              dst[u][t] = 0.0;
-              if (c < m && t * WAVE + WAVE - 1 >= cb && t * WAVE < m)
-                dst[u][t] = __builtin_bit_cast(
-                    double, __builtin_amdgcn_raw_buffer_load_b64(ra, chunk_off(c, t), c * m * 8, 0));
+              if (t * WAVE + WAVE - 1 >= c0 && t * WAVE < m) {
+                const int r = t * WAVE + lane;
+                const double xt = x[r];
+                double vr[NB], wr[NB];
+#pragma unroll
+                for (int q = 0; q < NB; ++q) {
+                  vr[q] = VL[q * MMAX + r];
+                  wr[q] = WL[q * MMAX + r];
+                }
+#pragma unroll
+                for (int u = 0; u < RS; ++u) {
+                  const int c = c0 + u;
+                  if (c < m) {
+                    double a = av[u][t];
+#pragma unroll
+                    for (int q = 0; q < NB; ++q) a -= vc[u][q] * wr[q] + wc[u][q] * vr[q];
+                    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2_t, a), ra, chunk_off(c, t), c * m * 8, 0);
+                    a = (r >= c && r < m) ? a : 0.0;
+                    if (u == 0 && c0 == i + 1 && r >= c) nr[r] = a;
+                    if (t == (c >> 6) && r == c) dg[c] = a;
+                    acc[u] = fma(a, xt, acc[u]);
+                    pc[t] = fma(a, xc[u], pc[t]);
+                  }
+                }
+              }
+            }
+#pragma unroll
+            for (int u = 0; u < RS; ++u) {
+              const int c = c0 + u;
+              if (c < m) {
+                double v = acc[u];
+                v += dpp_shift<0x111>(v, 0.0);
+                v += dpp_shift<0x112>(v, 0.0);
+                v += dpp_shift<0x114>(v, 0.0);
+                v += dpp_shift<0x118>(v, 0.0);
+                if ((lane & 15) == 15) prow[(lane >> 4) * MMAX + c] = v;
+              }
             }
           }
-        };
-        auto sum_rows = [&](int cb, const double (&av)[RU][CPL]) {
+        }
+        for (int c0 = i + 1 + RU * wvs; !fused && c0 < m; c0 += step) {
+          // all RU rows at once, without branches (rows past the end and
+          // chunks before the diagonal are masked by their offsets), so the
+          // sums below wait for each load only as they reach it
+          double av[RU][CPL];
+#pragma unroll
+          for (int u = 0; u < RU; ++u)
+#pragma unroll
+            for (int t = 0; t < CPL; ++t)
+              av[u][t] = __builtin_bit_cast(
+                  double, __builtin_amdgcn_raw_buffer_load_b64(ra, chunk_off(c0 + u, t), (c0 + u) * m * 8, 0));
+          if (c0 == i + 1) {
+#pragma unroll
+            for (int t = 0; t < CPL; ++t)
+              if (t * WAVE + WAVE - 1 >= c0 && t * WAVE < m) nr[t * WAVE + lane] = av[0][t];
+          }
           double acc[RU], vc[RU];
 #pragma unroll
           for (int u = 0; u < RU; ++u) {
             acc[u] = 0.0;
-            vc[u] = (cb + u < m) ? x[cb + u] : 0.0;
+            vc[u] = (c0 + u < m) ? x[c0 + u] : 0.0;
           }
 #pragma unroll
           for (int t = 0; t < CPL; ++t) {
-            if (t * WAVE + WAVE - 1 >= cb && t * WAVE < m) {
+            if (t * WAVE + WAVE - 1 >= c0 && t * WAVE < m) {
               const double xt = x[t * WAVE + lane];
 #pragma unroll
               for (int u = 0; u < RU; ++u) {
-                const int c = cb + u;
+                // the diagonal enters both sums; step 4 removes one
                 acc[u] = fma(av[u][t], xt, acc[u]);
-                // the diagonal element is counted once, in the row sum
-                double a = av[u][t];
-                if (t == (c >> 6)) a = (t * WAVE + lane > c) ? a : 0.0;
-                pc[t] = fma(a, vc[u], pc[t]);
+                pc[t] = fma(av[u][t], vc[u], pc[t]);
               }
             }
           }
 #pragma unroll
           for (int u = 0; u < RU; ++u) {
-            const int c = cb + u;
+            const int c = c0 + u;
             if (c < m) {
               double v = acc[u];
               v += dpp_shift<0x111>(v, 0.0);
@@ -1575,60 +1632,64 @@ __global__ __launch_bounds__(512) void k_sytrd2(double *__restrict__ Ab, int64_t
               if ((lane & 15) == 15) prow[(lane >> 4) * MMAX + c] = v;
             }
           }
-        };
-        const int step = RU * NW;
-        const int cstart = i + 1 + RU * wvs;
-        if (cstart < m) load_rows(cstart, avb);
-        for (int c0 = cstart; c0 < m; c0 += step) {
-#pragma unroll
-          for (int u = 0; u < RU; ++u)
-#pragma unroll
-            for (int t = 0; t < CPL; ++t) ava[u][t] = avb[u][t];
-          if (c0 + step < m) load_rows(c0 + step, avb);
-          sum_rows(c0, ava);
         }
 #pragma unroll
         for (int t = 0; t < CPL; ++t) pp[wid * MMAX + t * WAVE + lane] = pc[t];
         for (int dq = wid; dq < 2 * j; dq += NW) {
-          const double *a = (dq < j) ? WL + dq * MMAX : VL + (dq - j) * MMAX;
+          const double *w = (dq < j) ? WL + dq * MMAX : VL + (dq - j) * MMAX;
           double sacc = 0.0;
-          for (int r = i + 1 + lane; r < m; r += WAVE) sacc += a[r] * x[r];
+          for (int r = i + 2 + lane; r < m; r += WAVE) sacc += w[r] * x[r];
           sacc = wave_sum(sacc);
-          if (lane == 0) red[2 * NW + dq] = sacc;
+          if (lane == 0) red[2 * NW + dq] = w[i + 1] + sc * sacc;
         }
       }
       __syncthreads();
-      // (4) y = tau (A22 v - V (W^T v) - W (V^T v)), then y.v
-      double yv = 0.0;
-      for (int r = tid; r < MMAX; r += NT) {
-        double yr = 0.0;
-        if (r >= i + 1 && r < m) {
-          yr = (prow[r] + prow[MMAX + r]) + (prow[2 * MMAX + r] + prow[3 * MMAX + r]);
+      // (4) y = tau (A22 v - V (W^T v) - W (V^T v)) and y.v; entry tid per thread
+      double yr = 0.0, vr = 0.0;
+      if (tid >= i + 1 && tid < m) {
+        vr = (tid == i + 1) ? 1.0 : sc * x[tid];
+        double s = (prow[tid] + prow[MMAX + tid]) + (prow[2 * MMAX + tid] + prow[3 * MMAX + tid]);
 #pragma unroll
-          for (int w = 0; w < NW; ++w) yr += pp[w * MMAX + r];
-          for (int q = 0; q < j; ++q) yr -= VL[q * MMAX + r] * red[2 * NW + q] + WL[q * MMAX + r] * red[2 * NW + j + q];
-          yr *= tp;
-          yv += yr * x[r];
-        }
-        y[r] = yr;
+        for (int w = 0; w < NW; ++w) s += pp[w * MMAX + tid];
+        s -= dg[tid] * x[tid];
+        yr = sc * s + ce * nr[tid];
+        for (int q = 0; q < j; ++q)
+          yr -= VL[q * MMAX + tid] * red[2 * NW + q] + WL[q * MMAX + tid] * red[2 * NW + j + q];
+        yr *= tp;
       }
-      yv = wave_sum(yv);
+      const double yv = wave_sum(yr * vr);
       if (lane == 0) red[wid] = yv;
       __syncthreads();
       double K = 0.0;
       for (int q = 0; q < NW; ++q) K += red[q];
       K *= -0.5 * tp;
-      // (5) w = y + K v
-      for (int r = tid; r < MMAX; r += NT) WL[j * MMAX + r] = (r >= i + 1 && r < m) ? y[r] + K * x[r] : 0.0;
+      // (5) v and w = y + K v into the panel; the tail of v into row i for the
+      //     back-transformation
+      VL[j * MMAX + tid] = vr;
+      WL[j * MMAX + tid] = yr + K * vr;
+      if (tid >= i + 2 && tid < m && tp != 0.0) A[(int64_t)i * m + tid] = vr;
       __syncthreads();
     }
-    // (6) A22 -= V W^T + W V^T on the rows / columns after the panel: each
-    //     wave takes RS rows at a time with their V, W entries in registers,
-    //     loads all their live chunks at once, and per chunk reads the
-    //     lane's V, W entries once for the RS rows
-    {
+    // (6) A22 -= V W^T + W V^T on the rows / columns after the panel.  With
+    //     a later panel, only row c1 here (kept for its first column); the
+    //     other rows are updated by that column's pass.  After the last
+    //     panel, all rows: each wave takes RS rows at a time with their V, W
+    //     entries in registers and per chunk reads the lane's V, W entries
+    //     once for the RS rows.
+    const int c1 = i0 + nbp;
+    if (i0 + NB < nref) {
+      // a later panel follows: update row c1 only (its first column's
+      // reflector), the rest goes with that column's product
+      if (tid >= c1 && tid < m) {
+        double a = A[(int64_t)c1 * m + tid];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) a -= VL[q * MMAX + c1] * WL[q * MMAX + tid] + WL[q * MMAX + c1] * VL[q * MMAX + tid];
+        A[(int64_t)c1 * m + tid] = a;
+        nr[tid] = a;
+        if (tid == c1) dg[c1] = a;
+      }
+    } else {
       constexpr int RS = 2;
-      const int c1 = i0 + nbp;
       for (int c0 = c1 + RS * wvs; c0 < m; c0 += RS * NW) {
         double av[RS][CPL], vc[RS][NB], wc[RS][NB];
 #pragma unroll
@@ -1665,6 +1726,8 @@ __global__ __launch_bounds__(512) void k_sytrd2(double *__restrict__ Ab, int64_t
 #pragma unroll
                 for (int q = 0; q < NB; ++q) a -= vc[u][q] * wr[q] + wc[u][q] * vr[q];
                 __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2_t, a), ra, chunk_off(c, t), c * m * 8, 0);
+                if (u == 0 && c0 == c1 && r >= c && r < m) nr[r] = a;
+                if (t == (c >> 6) && r == c) dg[c] = a;
               }
             }
           }
@@ -2206,12 +2269,14 @@ void launch_scale(hipStream_t st, double *p, int64_t count, double c) {
 
 
 int launch_sytrd(hipStream_t st, int nb, double *A, int64_t sA, int m, double *d, double *e, double *tau, int64_t sv) {
-  constexpr int MMAX = 512;
+  constexpr int MMAX = 512, NW = 512 / WAVE, NB = 8;
   if (m > MMAX) return -1;
-  const size_t lds = (2 * 8 * MMAX + 6 * MMAX + 8 * MMAX + 2 * 8 + 2 * 8 + 8) * sizeof(double);
+  // V, W (NB x MMAX each), x, kept row, 4 group row sums, NW column partials,
+  // trailing diagonal (MMAX each), reductions
+  const size_t lds = (2 * NB * MMAX + 2 * MMAX + 4 * MMAX + NW * MMAX + MMAX + 2 * NW + 2 * NB + NW) * sizeof(double);
   static bool attr = false;
-  if (!attr) { set_lds(k_sytrd2<MMAX>, lds); attr = true; }
-  hipLaunchKernelGGL(k_sytrd2<MMAX>, dim3(nb), dim3(512), lds, st, A, sA, m, d, e, tau, sv);
+  if (!attr) { set_lds(k_sytrd<MMAX>, lds); attr = true; }
+  hipLaunchKernelGGL(k_sytrd<MMAX>, dim3(nb), dim3(512), lds, st, A, sA, m, d, e, tau, sv);
   return 0;
 }
 
