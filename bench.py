@@ -30,6 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_MFMA_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix peak (vendor figure)
+HBM_PEAK_GBS = 8000.0         # MI355X HBM3E peak bandwidth (vendor figure)
 # FP64 vector ALU peak: 256 CUs x 4 SIMDs x 16 FP64 FMA lanes x 2 flops x 2.4 GHz
 FP64_VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # kernel classes whose arithmetic runs on the vector ALUs (the rest on MFMA)
@@ -180,25 +181,41 @@ def main():
     kms = {k: sum(st.kernel_ms[i] for st in stats) for i, k in enumerate(names)}
     kfl = {k: sum(st.kernel_flops[i] for st in stats) for i, k in enumerate(names)}
     kn = {k: sum(st.kernel_launches[i] for st in stats) for i, k in enumerate(names)}
+    kby = {k: sum(st.kernel_bytes[i] for st in stats) for i, k in enumerate(names)}
     for k in names:
         if kn[k]:
-            rate = kfl[k] / (kms[k] * 1e-3) / 1e12 if kms[k] > 0 else 0.0
-            log(f"[bench] {k:8s} launches {kn[k]:7d}  device {kms[k] / 1e3:8.2f} s  "
-                f"avg {kms[k] / kn[k]:8.3f} ms  {rate:6.2f} TFLOP/s")
+            sec = kms[k] * 1e-3
+            rate = kfl[k] / sec / 1e12 if sec > 0 else 0.0
+            bw = kby[k] / sec / 1e9 if sec > 0 else 0.0
+            log(f"[bench] {k:8s} launches {kn[k]:7d}  device {sec:8.2f} s  "
+                f"avg {kms[k] / kn[k]:8.3f} ms  {rate:6.2f} TFLOP/s  {bw:7.1f} GB/s")
+    # the dominant kernel class (largest device time) against the roof its
+    # arithmetic intensity puts it under: HBM below the ridge point, else the
+    # FP64 peak of the unit it computes on
     dom = max((k for k in names if kfl[k] > 0), key=lambda k: kms[k])
-    achieved = kfl[dom] / (kms[dom] * 1e-3) / 1e12
+    sec = kms[dom] * 1e-3
     alu = dom in VALU_KERNELS
-    peak = FP64_VALU_PEAK_TFLOPS if alu else FP64_MFMA_PEAK_TFLOPS
+    cpeak = FP64_VALU_PEAK_TFLOPS if alu else FP64_MFMA_PEAK_TFLOPS
+    intensity = kfl[dom] / kby[dom]
+    ridge = cpeak * 1e12 / (HBM_PEAK_GBS * 1e9)
+    if intensity < ridge:
+        achieved, peak, unit, bound = kby[dom] / sec / 1e9, HBM_PEAK_GBS, "GB/s", "hbm"
+    else:
+        achieved, peak, unit, bound = kfl[dom] / sec / 1e12, cpeak, "TFLOP/s", "alu" if alu else "mfma"
     roofline = {
-        "bound": "alu" if alu else "mfma",
+        "bound": bound,
         "kernel": {"lq": "k_lq2 (Householder LQ with Q, FP64)", "sytrd": "k_sytrd (tridiagonalisation, FP64)",
                    "ormtr": "k_ormtr2 (eigenvector back-transformation, FP64)",
                    "gemm": "k_gemm_mfma (FP64)"}.get(dom, dom),
         "achieved": round(achieved, 3),
         "peak": round(peak, 2),
-        "unit": "TFLOP/s",
+        "unit": unit,
         "frac": round(achieved / peak, 4),
         "traffic": measured_traffic(dom, args.workload),
+        "algorithmic_bytes_per_launch": int(kby[dom] / max(kn[dom], 1)),
+        "intensity_flop_per_byte": round(intensity, 3),
+        "ridge_flop_per_byte": round(ridge, 2),
+        "achieved_tflops": round(kfl[dom] / sec / 1e12, 3),
         "avg_launch_ms": round(kms[dom] / max(kn[dom], 1), 4),
         "launches": int(kn[dom]),
     }

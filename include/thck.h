@@ -108,7 +108,16 @@ typedef struct {
  * device time, the launch count and the algorithmic flops of those launches
  * (LAPACK operation counts: LQ with thin Q 4nk^2 - 4k^3/3 for an m x n matrix,
  * k = min(m, n), n >= m; tridiagonalisation 4m^3/3; back-transformation
- * 2m^2 k; GEMM 2MNK) in thc_stats.kernel_*.  Off by default. */
+ * 2m^2 k; GEMM 2MNK) and their algorithmic device-memory bytes in
+ * thc_stats.kernel_*.  Bytes are the doubles each kernel's algorithm must
+ * move: LQ reads X and writes L and Q; GEMM reads A and B, reads C when
+ * beta != 0 and writes C (the upper half with upper-triangle tiles);
+ * back-transformation reads the reflectors (m^2/2) and Z and writes U;
+ * bisection/inverse iteration reads d, e and writes the k vectors; the
+ * one-stage tridiagonalisation streams the trailing upper triangle once per
+ * column and writes it once per panel of 8 (sum over columns of
+ * s(s+1)/2 for trailing size s, plus that sum over the first columns of
+ * the panels after the first).  Off by default. */
 #define THC_FLAG_TIME_KERNELS 2ull
 
 enum {
@@ -132,6 +141,7 @@ typedef struct {
   double kernel_ms[THC_NK];        /* THC_FLAG_TIME_KERNELS: summed device time per kernel class */
   double kernel_flops[THC_NK];     /* algorithmic flops of those launches */
   int64_t kernel_launches[THC_NK];
+  double kernel_bytes[THC_NK];     /* algorithmic device-memory bytes of those launches */
 } thc_stats;
 
 typedef struct thc_ctx thc_ctx;

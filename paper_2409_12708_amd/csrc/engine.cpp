@@ -229,6 +229,19 @@ double lq_flops(double m, double n) {  // LQ of m x n (m rows): R + thin Q, LAPA
   double k = std::min(m, n), M = std::max(m, n);
   return 2.0 * (2.0 * M * k * k - 2.0 * k * k * k / 3.0);
 }
+// Device-memory bytes of the one-stage tridiagonalisation of an m x m matrix
+// (panels of 8): the trailing upper triangle (s(s+1)/2 entries for trailing
+// size s) is read once per column and written once more by the first column
+// of each panel after the first, which applies the previous panel's update.
+double sytrd_bytes(int m) {
+  constexpr int NB = 8;
+  double el = 0.0;
+  for (int i = 0; i < m - 2; ++i) {
+    const double s = m - i - 1;
+    el += 0.5 * s * (s + 1.0) * ((i > 0 && i % NB == 0) ? 2.0 : 1.0);
+  }
+  return 8.0 * el;
+}
 double svd_flops(double m, double n) {  // Golub-Reinsch thin SVD with U and V (model)
   double k = std::min(m, n), M = std::max(m, n);
   return 14.0 * M * k * k + 8.0 * k * k * k;
@@ -368,6 +381,7 @@ struct CallStats {
   double flops = 0.0;
   double kms[THC_NK] = {};
   double kflops[THC_NK] = {};
+  double kbytes[THC_NK] = {};
   int64_t kn[THC_NK] = {};
 };
 
@@ -422,7 +436,7 @@ struct KernelTimer {
   struct Rec {
     hipEvent_t a, b;
     int cls;
-    double flops;
+    double flops, bytes;
     ShapeKey key;
   };
   std::vector<hipEvent_t> pool;
@@ -440,8 +454,8 @@ struct KernelTimer {
     return pool[used++];
   }
   template <class F>
-  void run(hipStream_t st, int cls, double flops, const ShapeKey &key, F &&launch) {
-    Rec r{get(), get(), cls, flops, key};
+  void run(hipStream_t st, int cls, double flops, double bytes, const ShapeKey &key, F &&launch) {
+    Rec r{get(), get(), cls, flops, bytes, key};
     HIPCHK(hipEventRecord(r.a, st));
     launch();
     HIPCHK(hipEventRecord(r.b, st));
@@ -454,6 +468,7 @@ struct KernelTimer {
       HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
       cs.kms[r.cls] += ms;
       cs.kflops[r.cls] += r.flops;
+      cs.kbytes[r.cls] += r.bytes;
       cs.kn[r.cls] += 1;
       if (shape_stats_on()) {
         ShapeStat &s = shape_stats()[r.key];
@@ -488,39 +503,41 @@ struct Engine {
         cprec(o_.prec == THC_PREC_F32 ? GEMM_F32 : (o_.prec == THC_PREC_BF16X3 ? GEMM_BF16X3 : GEMM_F64)) {}
   // launch through the timer when kernel timing is on
   template <class F>
-  void timed(int cls, double flops, const ShapeKey &key, F &&launch) {
-    if (timing) kt.run(st, cls, flops, key, launch);
+  void timed(int cls, double flops, double bytes, const ShapeKey &key, F &&launch) {
+    if (timing) kt.run(st, cls, flops, bytes, key, launch);
     else launch();
   }
-  // launchers of the timed kernel classes, with their algorithmic flops
+  // launchers of the timed kernel classes, with their algorithmic flops and bytes
   void gemm(int nb, int mode, const double *A, int64_t sA, int lda, const double *B, int64_t sB, int ldb, double *C,
             int64_t sC, int ldc, int M, int N, int K, double alpha = 1.0, double beta = 0.0, int prec = GEMM_F64) {
+    const double cbytes = (mode & GEMM_UPPER) ? 0.5 * M * (double)N : (double)M * N;
     timed(THC_K_GEMM, 2.0 * M * N * (double)K * nb,
-          ShapeKey{THC_K_GEMM, nb, M, N, K, mode + (beta != 0.0 ? 16 : 0) + 32 * prec},
+          8.0 * nb * ((double)M * K + (double)K * N + cbytes * (beta != 0.0 ? 2.0 : 1.0)), ShapeKey{THC_K_GEMM, nb, M, N, K, mode + (beta != 0.0 ? 16 : 0) + 32 * prec},
           [&] { launch_gemm(st, nb, mode, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta, prec); });
   }
   int lq(int nb, double *X, int64_t sX, int m, int n, double *L, int64_t sL, double *Q, int64_t sQ, double *T,
          int64_t sT, bool tr = false, int ldl = 0, int ldq = 0) {
     int rc = 0;
-    timed(THC_K_LQ, lq_flops(m, n) * nb, ShapeKey{THC_K_LQ, nb, m, n, 0, tr ? 1 : 0},
+    const double k = std::min(m, n);
+    timed(THC_K_LQ, lq_flops(m, n) * nb, 8.0 * nb * ((double)m * n + m * k + k * n), ShapeKey{THC_K_LQ, nb, m, n, 0, tr ? 1 : 0},
           [&] { rc = launch_lq(st, nb, X, sX, m, n, L, sL, Q, sQ, T, sT, tr, ldl, ldq); });
     return rc;
   }
   int sytrd(int nb, double *A, int64_t sA, int m, double *d, double *e, double *tau, int64_t sv) {
     int rc = 0;
-    timed(THC_K_SYTRD, 4.0 / 3.0 * m * (double)m * m * nb, ShapeKey{THC_K_SYTRD, nb, m, m, 0, 0}, [&] { rc = launch_sytrd(st, nb, A, sA, m, d, e, tau, sv); });
+    timed(THC_K_SYTRD, 4.0 / 3.0 * m * (double)m * m * nb, sytrd_bytes(m) * nb, ShapeKey{THC_K_SYTRD, nb, m, m, 0, 0}, [&] { rc = launch_sytrd(st, nb, A, sA, m, d, e, tau, sv); });
     return rc;
   }
   int tri_eig(int nb, const double *d, const double *e, int64_t sv, int m, int kk, double *Z, int64_t sZ, double *lam,
               int64_t sl, double *scr, int64_t sscr) {
     int rc = 0;
-    timed(THC_K_TRI_EIG, 0.0, ShapeKey{THC_K_TRI_EIG, nb, m, kk, 0, 0}, [&] { rc = launch_tri_eig(st, nb, d, e, sv, m, kk, Z, sZ, lam, sl, scr, sscr); });
+    timed(THC_K_TRI_EIG, 0.0, 8.0 * nb * (2.0 * m + (double)m * kk + kk), ShapeKey{THC_K_TRI_EIG, nb, m, kk, 0, 0}, [&] { rc = launch_tri_eig(st, nb, d, e, sv, m, kk, Z, sZ, lam, sl, scr, sscr); });
     return rc;
   }
   int ormtr(int nb, const double *A, int64_t sA, int m, const double *tau, int64_t sv, double *Z, int64_t sZ, int kk,
             double *Ut, int64_t sU, bool zout, double *Tf, int64_t sTf) {
     int rc = 0;
-    timed(THC_K_ORMTR, 2.0 * m * (double)m * kk * nb, ShapeKey{THC_K_ORMTR, nb, m, kk, 0, zout ? 1 : 0},
+    timed(THC_K_ORMTR, 2.0 * m * (double)m * kk * nb, 8.0 * nb * (0.5 * m * (double)m + 2.0 * m * (double)kk), ShapeKey{THC_K_ORMTR, nb, m, kk, 0, zout ? 1 : 0},
           [&] { rc = launch_ormtr(st, nb, A, sA, m, tau, sv, Z, sZ, kk, Ut, sU, zout, Tf, sTf); });
     return rc;
   }
@@ -1142,6 +1159,7 @@ void fill_stats(thc_stats *st, const CallStats &cs) {
     st->kernel_ms[k] = cs.kms[k];
     st->kernel_flops[k] = cs.kflops[k];
     st->kernel_launches[k] = cs.kn[k];
+    st->kernel_bytes[k] = cs.kbytes[k];
   }
   st->reserved = 0;
 }
@@ -1723,6 +1741,7 @@ thc_status krylov_step(thc_krylov *k, double *ritz_gen, double *ritz_tri, double
         st->kernel_ms[q] = s1.kernel_ms[q] + s2.kernel_ms[q];
         st->kernel_flops[q] = s1.kernel_flops[q] + s2.kernel_flops[q];
         st->kernel_launches[q] = s1.kernel_launches[q] + s2.kernel_launches[q];
+        st->kernel_bytes[q] = s1.kernel_bytes[q] + s2.kernel_bytes[q];
       }
     }
   });

@@ -66,6 +66,7 @@ class ThcStats(C.Structure):
         ("kernel_ms", C.c_double * 5),
         ("kernel_flops", C.c_double * 5),
         ("kernel_launches", C.c_int64 * 5),
+        ("kernel_bytes", C.c_double * 5),
     ]
     KERNELS = ("lq", "sytrd", "tri_eig", "ormtr", "gemm")
 
@@ -73,8 +74,10 @@ class ThcStats(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved" and not f.startswith("kernel_")}
 
     def kernels(self):
-        """Per kernel class: (summed ms, algorithmic flops, launches); filled with THC_FLAG_TIME_KERNELS."""
-        return {k: (self.kernel_ms[i], self.kernel_flops[i], self.kernel_launches[i]) for i, k in enumerate(self.KERNELS)}
+        """Per kernel class: (summed ms, algorithmic flops, launches, algorithmic bytes);
+        filled with THC_FLAG_TIME_KERNELS."""
+        return {k: (self.kernel_ms[i], self.kernel_flops[i], self.kernel_launches[i], self.kernel_bytes[i])
+                for i, k in enumerate(self.KERNELS)}
 
 
 FLAG_SVD_JACOBI = 1      # one-sided Jacobi SVD in the truncation step
