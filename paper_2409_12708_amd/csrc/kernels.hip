@@ -1781,9 +1781,10 @@ __device__ __forceinline__ int sturm_count(const double *d, const double *e2, in
 }
 
 // tri_eig: top-kk eigenpairs of the tridiagonal (d, e), one workgroup of
-// 1024 threads per matrix, kk <= 256.  Eigenvalues: multisection on Sturm
-// counts to full precision, four lanes per eigenvalue (the t-th largest).
-// Eigenvectors: inverse iteration (three steps) with a partial-pivoting LU
+// 512 threads per matrix (two fit on a CU; a 1024-thread workgroup runs
+// alone), kk <= 256.  Eigenvalues: trisection on Sturm counts to full
+// precision, two lanes per eigenvalue (the t-th largest).
+// Eigenvectors: inverse iteration (two steps) with a partial-pivoting LU
 // of (T - lambda I), zero pivots replaced by eps*||T||, from a
 // deterministic pseudo-random start.  Consecutive eigenvalues within a
 // relative gap of 1e-6 form a cluster (at most 32 members) whose members are
@@ -1793,91 +1794,109 @@ __device__ __forceinline__ int sturm_count(const double *d, const double *e2, in
 // an orthonormal basis, which the re-orthonormalisation that follows
 // provides).
 // Output Z (m x kk, column t = eigenvector t) and lambda (kk, descending).
-// Scratch per job: 4 m kk doubles + m kk ints, laid out [r][t].
+// Scratch per job: 3 m kk doubles (the bands of U), laid out [r][t].
+// pseudo-random start component (k, t) of inverse iteration, in [-1/2, 1/2)
+__device__ __forceinline__ double inv_iter_start(int k, int t) {
+  unsigned int h = (unsigned int)k * 2654435761u ^ ((unsigned int)(t + 1) * 40503u) ^ 0x9e3779b9u;
+  h ^= h >> 16; h *= 0x85ebca6bu; h ^= h >> 13; h *= 0xc2b2ae35u; h ^= h >> 16;
+  return ((double)(h & 0xffffffu) / 16777216.0) - 0.5;
+}
+
+// Two steps of inverse iteration for eigenvalue lm, vector t (column t of Z,
+// layout [r][t]).  Each step factors T - lm I with partial pivoting (rows k
+// and k+1 swapped when |sub-diagonal| > |pivot|) and applies the row
+// operations to the right-hand side in the same pass, storing only the
+// three bands of U; the back substitution accumulates the sum of squares.
+// The first right-hand side is generated on the fly; the second is the first
+// solution, scaled as it is read.  Members of a cluster (q0 < t) are
+// normalised, orthogonalised against members q0..t-1 and normalised again
+// after each step.
 __device__ void inv_iter_one(const double *sd, const double *se, int m, int kk, int t, double lm, double tiny,
-                             double *U0, double *U1, double *U2, double *ML, int *SW, double *Z, int q0) {
-  double r0 = sd[0] - lm, r1 = (m > 1) ? se[0] : 0.0, r2 = 0.0;
-  for (int k = 0; k + 1 < m; ++k) {
-    const double l = se[k], an = sd[k + 1] - lm, bn = (k + 2 < m) ? se[k + 1] : 0.0;
-    const int64_t o = (int64_t)k * kk + t;
-    if (fabs(r0) >= fabs(l)) {
-      if (r0 == 0.0) r0 = tiny;
-      const double mult = qdiv(l, r0);
-      U0[o] = r0; U1[o] = r1; U2[o] = r2; ML[o] = mult; SW[o] = 0;
-      r0 = an - mult * r1;
-      r1 = bn - mult * r2;
-    } else {
-      const double mult = qdiv(r0, l);
-      U0[o] = l; U1[o] = an; U2[o] = bn; ML[o] = mult; SW[o] = 1;
-      const double n0 = r1 - mult * an, n1 = r2 - mult * bn;
-      r0 = n0;
-      r1 = n1;
-    }
-    r2 = 0.0;
-  }
-  if (r0 == 0.0) r0 = tiny;
-  {
-    const int64_t o = (int64_t)(m - 1) * kk + t;
-    U0[o] = r0; U1[o] = 0.0; U2[o] = 0.0;
-  }
-  for (int k = 0; k < m; ++k) {
-    unsigned int h = (unsigned int)k * 2654435761u ^ ((unsigned int)(t + 1) * 40503u) ^ 0x9e3779b9u;
-    h ^= h >> 16; h *= 0x85ebca6bu; h ^= h >> 13; h *= 0xc2b2ae35u; h ^= h >> 16;
-    Z[(int64_t)k * kk + t] = ((double)(h & 0xffffffu) / 16777216.0) - 0.5;
-  }
+                             double *U0, double *U1, double *U2, double *Z, int q0) {
   if (!(tiny > 1e-250)) {  // T = 0: every vector is an eigenvector; use e_t
     for (int k = 0; k < m; ++k) Z[(int64_t)k * kk + t] = (k == t) ? 1.0 : 0.0;
     return;
   }
+  double rs = 1.0;  // scale of the right-hand side held in Z
   for (int iter = 0; iter < 2; ++iter) {
-    double yk = Z[t];
+    double r0 = sd[0] - lm, r1 = (m > 1) ? se[0] : 0.0, r2 = 0.0;
+    double yk = (iter == 0) ? inv_iter_start(0, t) : Z[t] * rs;
     for (int k = 0; k + 1 < m; ++k) {
+      const double l = se[k], an = sd[k + 1] - lm, bn = (k + 2 < m) ? se[k + 1] : 0.0;
       const int64_t o = (int64_t)k * kk + t;
-      double yk1 = Z[o + kk];
-      if (SW[o]) { const double tmp = yk; yk = yk1; yk1 = tmp; }
-      yk1 -= ML[o] * yk;
+      double yk1 = (iter == 0) ? inv_iter_start(k + 1, t) : Z[o + kk] * rs;
+      if (fabs(r0) >= fabs(l)) {
+        if (r0 == 0.0) r0 = tiny;
+        const double mult = qdiv(l, r0);
+        U0[o] = r0; U1[o] = r1; U2[o] = r2;
+        r0 = an - mult * r1;
+        r1 = bn - mult * r2;
+        yk1 -= mult * yk;
+      } else {
+        const double mult = qdiv(r0, l);
+        U0[o] = l; U1[o] = an; U2[o] = bn;
+        const double n0 = r1 - mult * an, n1 = r2 - mult * bn;
+        r0 = n0;
+        r1 = n1;
+        const double tmp = yk;
+        yk = yk1;
+        yk1 = tmp - mult * yk1;
+      }
+      r2 = 0.0;
       Z[o] = yk;
       yk = yk1;
     }
-    Z[(int64_t)(m - 1) * kk + t] = yk;
+    if (r0 == 0.0) r0 = tiny;
+    {
+      const int64_t o = (int64_t)(m - 1) * kk + t;
+      U0[o] = r0; U1[o] = 0.0; U2[o] = 0.0;
+      Z[o] = yk;
+    }
     // back substitution with running rescaling: a solve against a nearly
     // singular (T - lambda I) grows by up to 1/eps per tiny pivot, so the
-    // partial solution is scaled down whenever it exceeds 1e150
-    double x1 = 0.0, x2 = 0.0, mx = 0.0;
+    // partial solution is scaled down whenever it exceeds 1e150 (entries stay
+    // below 1e150, so the sum of their squares cannot overflow)
+    double x1 = 0.0, x2 = 0.0, s2 = 0.0;
     for (int k = m - 1; k >= 0; --k) {
       const int64_t o = (int64_t)k * kk + t;
       const double iu = rcp_nr(U0[o]);
       double x = (Z[o] - U1[o] * x1 - U2[o] * x2) * iu;
       if (fabs(x) > 1e150) {
-        const double s = 1e-150;
-        for (int q = k + 1; q < m; ++q) Z[(int64_t)q * kk + t] *= s;
-        for (int q = 0; q < k; ++q) Z[(int64_t)q * kk + t] *= s;  // remaining right-hand side
-        x1 *= s;
-        x2 *= s;
-        mx *= s;
-        x = (Z[o] * s - U1[o] * x1 - U2[o] * x2) * iu;
+        const double sc = 1e-150;
+        for (int q = k + 1; q < m; ++q) Z[(int64_t)q * kk + t] *= sc;
+        for (int q = 0; q < k; ++q) Z[(int64_t)q * kk + t] *= sc;  // remaining right-hand side
+        x1 *= sc;
+        x2 *= sc;
+        s2 *= sc * sc;
+        x = (Z[o] * sc - U1[o] * x1 - U2[o] * x2) * iu;
       }
       Z[o] = x;
       x2 = x1;
       x1 = x;
-      mx = fmax(mx, fabs(x));
+      s2 += x * x;
     }
-    // rescale by the max first (avoids overflow of the 2-norm), then orthogonalise
-    const double im = (mx > 0.0 && isfinite(mx)) ? 1.0 / mx : 0.0;
-    for (int k = 0; k < m; ++k) Z[(int64_t)k * kk + t] *= im;
-    for (int q = q0; q < t; ++q) {
-      double dt = 0.0;
-      for (int k = 0; k < m; ++k) dt += Z[(int64_t)k * kk + q] * Z[(int64_t)k * kk + t];
-      for (int k = 0; k < m; ++k) Z[(int64_t)k * kk + t] -= dt * Z[(int64_t)k * kk + q];
+    const double inv = (s2 > 0.0 && isfinite(s2)) ? 1.0 / sqrt(s2) : 0.0;
+    if (q0 < t) {
+      for (int k = 0; k < m; ++k) Z[(int64_t)k * kk + t] *= inv;
+      for (int q = q0; q < t; ++q) {
+        double dt = 0.0;
+        for (int k = 0; k < m; ++k) dt += Z[(int64_t)k * kk + q] * Z[(int64_t)k * kk + t];
+        for (int k = 0; k < m; ++k) Z[(int64_t)k * kk + t] -= dt * Z[(int64_t)k * kk + q];
+      }
+      double s3 = 0.0;
+      for (int k = 0; k < m; ++k) { const double x = Z[(int64_t)k * kk + t]; s3 += x * x; }
+      const double inv3 = (s3 > 0.0) ? 1.0 / sqrt(s3) : 0.0;
+      for (int k = 0; k < m; ++k) Z[(int64_t)k * kk + t] *= inv3;
+      rs = 1.0;
+    } else if (iter == 1) {
+      for (int k = 0; k < m; ++k) Z[(int64_t)k * kk + t] *= inv;
+    } else {
+      rs = inv;
     }
-    double s2 = 0.0;
-    for (int k = 0; k < m; ++k) { const double x = Z[(int64_t)k * kk + t]; s2 += x * x; }
-    const double inv = (s2 > 0.0) ? 1.0 / sqrt(s2) : 0.0;
-    for (int k = 0; k < m; ++k) Z[(int64_t)k * kk + t] *= inv;
   }
 }
 
-__global__ __launch_bounds__(1024) void k_tri_eig(const double *__restrict__ db, const double *__restrict__ eb,
+__global__ __launch_bounds__(512) void k_tri_eig(const double *__restrict__ db, const double *__restrict__ eb,
                                                  int64_t sv, int m, int kk, double *__restrict__ Zb, int64_t sZ,
                                                  double *__restrict__ lamb, int64_t sl, double *__restrict__ scrb,
                                                  int64_t sscr) {
@@ -1891,8 +1910,7 @@ __global__ __launch_bounds__(1024) void k_tri_eig(const double *__restrict__ db,
   double *scr = scrb + (int64_t)blockIdx.x * sscr;
   const int tid = threadIdx.x;
   const int64_t MK = (int64_t)m * kk;
-  double *U0 = scr, *U1 = scr + MK, *U2 = scr + 2 * MK, *ML = scr + 3 * MK;
-  int *SW = (int *)(scr + 4 * MK);
+  double *U0 = scr, *U1 = scr + MK, *U2 = scr + 2 * MK;
   for (int k = tid; k < m; k += blockDim.x) {
     sd[k] = d0[k];
     const double ek = (k + 1 < m) ? e0[k] : 0.0;
@@ -1935,31 +1953,35 @@ __global__ __launch_bounds__(1024) void k_tri_eig(const double *__restrict__ db,
   if (tid == 0) s_nsig = (tn > 0.0) ? m - sturm_count(sd, se2, m, noise, pivmin) : 0;
   __syncthreads();
   const int nsig = s_nsig;
-  // multisection: four consecutive lanes share eigenvalue t and each
-  // evaluates the Sturm count at one of the points a + (b - a) (s + 1) / 5,
-  // so every step shrinks the bracket five-fold; the four lanes agree on the
-  // new bracket through the wave ballot
+  // trisection: two consecutive lanes share eigenvalue t and each evaluates
+  // the Sturm count at one of the points a + (b - a) (s + 1) / 3, so every
+  // step shrinks the bracket three-fold; the two lanes agree on the new
+  // bracket through the wave ballot
+  constexpr int NSUB = 2;
+  constexpr double THIRD = 1.0 / 3.0;
   const int lane = tid % WAVE;
-  for (int g = tid / 4; g < ((kk + 63) / 64) * 64; g += blockDim.x / 4) {
-    const int t = g, sub = tid % 4;
+  for (int g = tid / NSUB; g < ((kk + 63) / 64) * 64; g += blockDim.x / NSUB) {
+    const int t = g, sub = tid % NSUB;
     const bool act = t < kk && t < nsig;
     const int j = m - 1 - t;  // index in ascending order
     double a = fmax(lo_s - pad, noise), b = hi_s + pad;
     bool done = !act;
-    for (int it = 0; it < 40; ++it) {
+    // 3^48 > 1e22: from a bracket of width ~2 (T is scaled to norm 1) to
+    // the 1e-18 floor below
+    for (int it = 0; it < 48; ++it) {
       if (!done && !(b - a > 2.2e-16 * fmax(fabs(a), fabs(b)) + 1e-18 * tn)) done = true;
       if (__ballot(!done) == 0ull) break;
-      const double x = a + (b - a) * (double)(sub + 1) * 0.2;
+      const double x = a + (b - a) * (double)(sub + 1) * THIRD;
       const bool above = done ? false : (sturm_count(sd, se2, m, x, pivmin) > j);
       const unsigned long long bal = __ballot(above);
       if (!done) {
-        const unsigned int grp = (unsigned int)((bal >> (lane & ~3)) & 0xFull);
+        const unsigned int grp = (unsigned int)((bal >> (lane & ~(NSUB - 1))) & ((1u << NSUB) - 1u));
         if (grp == 0u) {
-          a = a + (b - a) * 0.8;
+          a = a + (b - a) * (double)NSUB * THIRD;
         } else {
           const int s0 = __builtin_ctz(grp);
-          const double lo2 = (s0 == 0) ? a : a + (b - a) * (double)s0 * 0.2;
-          const double hi2 = a + (b - a) * (double)(s0 + 1) * 0.2;
+          const double lo2 = (s0 == 0) ? a : a + (b - a) * (double)s0 * THIRD;
+          const double hi2 = a + (b - a) * (double)(s0 + 1) * THIRD;
           a = lo2;
           b = hi2;
         }
@@ -1989,7 +2011,7 @@ __global__ __launch_bounds__(1024) void k_tri_eig(const double *__restrict__ db,
     if (!leader) continue;
     int t1 = t + 1;
     while (t1 < kk && t1 < nsig && close(t1) && (t1 % 32 != 0)) ++t1;
-    for (int u = t; u < t1; ++u) inv_iter_one(sd, se, m, kk, u, slam[u], tiny, U0, U1, U2, ML, SW, Z, t);
+    for (int u = t; u < t1; ++u) inv_iter_one(sd, se, m, kk, u, slam[u], tiny, U0, U1, U2, Z, t);
   }
 }
 
@@ -2283,7 +2305,7 @@ int launch_sytrd(hipStream_t st, int nb, double *A, int64_t sA, int m, double *d
 int launch_tri_eig(hipStream_t st, int nb, const double *d, const double *e, int64_t sv, int m, int kk, double *Z,
                    int64_t sZ, double *lam, int64_t sl, double *scr, int64_t sscr) {
   if (m > 1024 || kk > 256) return -1;
-  hipLaunchKernelGGL(k_tri_eig, dim3(nb), dim3(1024), 0, st, d, e, sv, m, kk, Z, sZ, lam, sl, scr, sscr);
+  hipLaunchKernelGGL(k_tri_eig, dim3(nb), dim3(512), 0, st, d, e, sv, m, kk, Z, sZ, lam, sl, scr, sscr);
   return 0;
 }
 
@@ -2315,7 +2337,7 @@ void launch_svd_finish2(hipStream_t st, int nb, const double *Q, int64_t sQ, int
                      disc, qt ? 1 : 0);
 }
 
-int64_t tri_eig_scratch(int m, int kk) { return 4 * (int64_t)m * kk + ((int64_t)m * kk + 1) / 2 + 8; }
+int64_t tri_eig_scratch(int m, int kk) { return 3 * (int64_t)m * kk + 8; }
 
 void launch_ritz(hipStream_t st, const double *Mm, const double *S, int m, int ld, const double *alpha,
                  const double *beta, double *out_gen, double *out_tri, int *info) {
