@@ -1400,12 +1400,13 @@ __global__ __launch_bounds__(512) void k_ormtr2(const double *__restrict__ Ab, i
 //    is a scalar, and lanes outside the triangle or past m get an offset past
 //    the end of the buffer (reads give 0, stores are dropped), so the loads
 //    carry no branches and each sum waits only for the loads it uses.
-//  * The product streams the unscaled updated row x rather than v, so it does
-//    not wait for the reflector: on the rows after i,
-//    v = e_{i+1} + sc (x - alpha e_{i+1}), hence
-//    A22 v = sc A22 x + (1 - sc alpha) A22 e_{i+1}, and A22 e_{i+1} is row
-//    i+1 of A22 (symmetry), which the stream reads anyway: the wave that owns
-//    it keeps a copy in LDS, which is also the next column's row i+1.
+//  * v is never formed before the product: on the rows after i,
+//    v = e_{i+1} + sc (x - alpha e_{i+1}) for the updated row x, hence
+//    A22 v = A22 (sc x) + (1 - sc alpha) A22 e_{i+1}; the stream scales x as
+//    it reads it (so its products stay O(|A|) at any scale of A), and
+//    A22 e_{i+1} is row i+1 of A22 (symmetry), which the stream reads anyway:
+//    the wave that owns it keeps a copy in LDS, which is also the next
+//    column's row i+1.
 //  * The diagonal element enters both the row and the column sums; the sum
 //    is corrected once from the trailing diagonal kept in LDS.
 //  * The update of a panel is applied by the next panel's first column in
@@ -1542,13 +1543,13 @@ __global__ __launch_bounds__(512) void k_sytrd(double *__restrict__ Ab, int64_t 
                 wc[u][q] = (c < m) ? WL[q * MMAX + c] : 0.0;
               }
               acc[u] = 0.0;
-              xc[u] = (c < m) ? x[c] : 0.0;
+              xc[u] = (c < m) ? x[c] * sc : 0.0;
             }
 #pragma unroll
             for (int t = 0; t < CPL; ++t) {
               if (t * WAVE + WAVE - 1 >= c0 && t * WAVE < m) {
                 const int r = t * WAVE + lane;
-                const double xt = x[r];
+                const double xt = x[r] * sc;
                 double vr[NB], wr[NB];
 #pragma unroll
                 for (int q = 0; q < NB; ++q) {
@@ -1606,12 +1607,12 @@ __global__ __launch_bounds__(512) void k_sytrd(double *__restrict__ Ab, int64_t 
 #pragma unroll
           for (int u = 0; u < RU; ++u) {
             acc[u] = 0.0;
-            vc[u] = (c0 + u < m) ? x[c0 + u] : 0.0;
+            vc[u] = (c0 + u < m) ? x[c0 + u] * sc : 0.0;
           }
 #pragma unroll
           for (int t = 0; t < CPL; ++t) {
             if (t * WAVE + WAVE - 1 >= c0 && t * WAVE < m) {
-              const double xt = x[t * WAVE + lane];
+              const double xt = x[t * WAVE + lane] * sc;
 #pragma unroll
               for (int u = 0; u < RU; ++u) {
                 // the diagonal enters both sums; step 4 removes one
@@ -1638,9 +1639,9 @@ __global__ __launch_bounds__(512) void k_sytrd(double *__restrict__ Ab, int64_t 
         for (int dq = wid; dq < 2 * j; dq += NW) {
           const double *w = (dq < j) ? WL + dq * MMAX : VL + (dq - j) * MMAX;
           double sacc = 0.0;
-          for (int r = i + 2 + lane; r < m; r += WAVE) sacc += w[r] * x[r];
+          for (int r = i + 2 + lane; r < m; r += WAVE) sacc += w[r] * (x[r] * sc);
           sacc = wave_sum(sacc);
-          if (lane == 0) red[2 * NW + dq] = w[i + 1] + sc * sacc;
+          if (lane == 0) red[2 * NW + dq] = w[i + 1] + sacc;
         }
       }
       __syncthreads();
@@ -1651,8 +1652,8 @@ __global__ __launch_bounds__(512) void k_sytrd(double *__restrict__ Ab, int64_t 
         double s = (prow[tid] + prow[MMAX + tid]) + (prow[2 * MMAX + tid] + prow[3 * MMAX + tid]);
 #pragma unroll
         for (int w = 0; w < NW; ++w) s += pp[w * MMAX + tid];
-        s -= dg[tid] * x[tid];
-        yr = sc * s + ce * nr[tid];
+        s -= dg[tid] * (x[tid] * sc);
+        yr = s + ce * nr[tid];
         for (int q = 0; q < j; ++q)
           yr -= VL[q * MMAX + tid] * red[2 * NW + q] + WL[q * MMAX + tid] * red[2 * NW + j + q];
         yr *= tp;

@@ -101,3 +101,61 @@ def test_sum_tree_counts(thck, k):
     assert err < 1e-12
     assert out.canonical
     assert M.right_canonical_error(out.to_sites()) < 1e-12
+
+
+@pytest.mark.parametrize("c", [1e-100, 1e100])
+def test_compress_extreme_scale(thck, c):
+    # the Gram matrices reach 1e+-200 and their column norms square again:
+    # the tridiagonalisation's scaled-norm branch and the eigensolver's
+    # normalisation by ||T|| carry the untruncated result through exactly
+    rng = np.random.default_rng(80)
+    n = 8
+    psi = M.scale(_norm_mps(rng, n, 8), c)
+    t, chi, zeta = synth.thc_factors(np.random.default_rng(0), n // 2, 2)
+    ctx = thck.Context(t, chi, zeta)
+    out = ctx.compress(thck.DeviceMPS.from_sites(psi), D=16)
+    ref = M.to_dense(psi)
+    assert _rel(M.to_dense(out.to_sites()), ref) < 1e-12
+
+
+def _rainbow(n):
+    """Bell pairs between sites j and n-1-j: the middle bond carries 2^(n/2)
+    equal Schmidt values.  Site j < n/2 appends its bit to the bond index,
+    site j >= n/2 removes the last appended bit (the pairs nest)."""
+    h = n // 2
+    sites = []
+    for j in range(n):
+        if j < h:
+            l, r = 2 ** j, 2 ** (j + 1)
+            A = np.zeros((l, 2, r))
+            for L in range(l):
+                for s in range(2):
+                    A[L, s, 2 * L + s] = 1.0
+        else:
+            l, r = 2 ** (n - j), 2 ** (n - j - 1)
+            A = np.zeros((l, 2, r))
+            for R in range(r):
+                for s in range(2):
+                    A[2 * R + s, s, R] = 1.0
+        sites.append(A)
+    return M.scale(sites, 2.0 ** (-h / 2))
+
+
+@pytest.mark.parametrize("flags", [0, 1])
+def test_compress_degenerate_spectrum(thck, flags):
+    # 64 equal Schmidt values at the middle bond: one eigenvalue cluster
+    # larger than the eigensolver's 32-member cap
+    n = 12
+    psi = _rainbow(n)
+    sv = M.schmidt_values(psi)[n // 2 - 1]
+    assert np.allclose(sv[:64], 0.125) and len(sv) == 64
+    t, chi, zeta = synth.thc_factors(np.random.default_rng(0), n // 2, 2)
+    ctx = thck.Context(t, chi, zeta)
+    ref = M.to_dense(psi)
+    full = ctx.compress(thck.DeviceMPS.from_sites(psi), D=64, flags=flags)
+    assert _rel(M.to_dense(full.to_sites()), ref) < 1e-12
+    # truncated inside the cluster: the kept subspace is not unique, but the
+    # result is the orthogonal projection of psi onto it, with half the norm^2
+    half = M.to_dense(ctx.compress(thck.DeviceMPS.from_sites(psi), D=32, flags=flags).to_sites())
+    assert abs(np.dot(half, ref) - np.dot(half, half)) < 1e-12
+    assert abs(np.dot(half, half) - 0.5) < 1e-12
