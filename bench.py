@@ -70,6 +70,45 @@ def measured_traffic(kernel: str, workload: str):
     return int(rec["bytes_per_launch"])
 
 
+KERNEL_LABEL = {"lq": "k_lq2 (Householder LQ with Q, FP64)", "sytrd": "k_sytrd (tridiagonalisation, FP64)",
+                "tri_eig": "k_tri_eig (bisection + inverse iteration, FP64)",
+                "ormtr": "k_ormtr2 (eigenvector back-transformation, FP64)", "gemm": "k_gemm_mfma (FP64)"}
+
+
+def roofline_of(kms, kfl, kby, kn):
+    """The dominant kernel class (largest summed device time among those with
+    algorithmic flops) against the roof its arithmetic intensity puts it
+    under: HBM below the ridge point (FP64 peak / HBM peak), else the FP64
+    peak of the unit it computes on.  Inputs per class: summed ms, flops,
+    bytes, launches.  The returned dict carries the class under "_class"."""
+    dom = max((k for k in kms if kfl[k] > 0), key=lambda k: kms[k])
+    sec = kms[dom] * 1e-3
+    alu = dom in VALU_KERNELS
+    cpeak = FP64_VALU_PEAK_TFLOPS if alu else FP64_MFMA_PEAK_TFLOPS
+    intensity = kfl[dom] / kby[dom] if kby[dom] > 0 else float("inf")
+    ridge = cpeak * 1e12 / (HBM_PEAK_GBS * 1e9)
+    if intensity < ridge:
+        achieved, peak, unit, bound = kby[dom] / sec / 1e9, HBM_PEAK_GBS, "GB/s", "hbm"
+    else:
+        achieved, peak, unit, bound = kfl[dom] / sec / 1e12, cpeak, "TFLOP/s", "alu" if alu else "mfma"
+    return {
+        "bound": bound,
+        "kernel": KERNEL_LABEL.get(dom, dom),
+        "achieved": round(achieved, 3),
+        "peak": round(peak, 2),
+        "unit": unit,
+        "frac": round(achieved / peak, 4),
+        "traffic": None,
+        "algorithmic_bytes_per_launch": int(kby[dom] / max(kn[dom], 1)),
+        "intensity_flop_per_byte": round(intensity, 3),
+        "ridge_flop_per_byte": round(ridge, 2),
+        "achieved_tflops": round(kfl[dom] / sec / 1e12, 3),
+        "avg_launch_ms": round(kms[dom] / max(kn[dom], 1), 4),
+        "launches": int(kn[dom]),
+        "_class": dom,
+    }
+
+
 def cpu_baseline(workload: str, seconds_hint: float = 20.0):
     """Time the FP64 oracle on a bounded sample of the same workload: one
     layer-compression and one add-compression at the full bond dimension,
@@ -189,36 +228,8 @@ def main():
             bw = kby[k] / sec / 1e9 if sec > 0 else 0.0
             log(f"[bench] {k:8s} launches {kn[k]:7d}  device {sec:8.2f} s  "
                 f"avg {kms[k] / kn[k]:8.3f} ms  {rate:6.2f} TFLOP/s  {bw:7.1f} GB/s")
-    # the dominant kernel class (largest device time) against the roof its
-    # arithmetic intensity puts it under: HBM below the ridge point, else the
-    # FP64 peak of the unit it computes on
-    dom = max((k for k in names if kfl[k] > 0), key=lambda k: kms[k])
-    sec = kms[dom] * 1e-3
-    alu = dom in VALU_KERNELS
-    cpeak = FP64_VALU_PEAK_TFLOPS if alu else FP64_MFMA_PEAK_TFLOPS
-    intensity = kfl[dom] / kby[dom]
-    ridge = cpeak * 1e12 / (HBM_PEAK_GBS * 1e9)
-    if intensity < ridge:
-        achieved, peak, unit, bound = kby[dom] / sec / 1e9, HBM_PEAK_GBS, "GB/s", "hbm"
-    else:
-        achieved, peak, unit, bound = kfl[dom] / sec / 1e12, cpeak, "TFLOP/s", "alu" if alu else "mfma"
-    roofline = {
-        "bound": bound,
-        "kernel": {"lq": "k_lq2 (Householder LQ with Q, FP64)", "sytrd": "k_sytrd (tridiagonalisation, FP64)",
-                   "ormtr": "k_ormtr2 (eigenvector back-transformation, FP64)",
-                   "gemm": "k_gemm_mfma (FP64)"}.get(dom, dom),
-        "achieved": round(achieved, 3),
-        "peak": round(peak, 2),
-        "unit": unit,
-        "frac": round(achieved / peak, 4),
-        "traffic": measured_traffic(dom, args.workload),
-        "algorithmic_bytes_per_launch": int(kby[dom] / max(kn[dom], 1)),
-        "intensity_flop_per_byte": round(intensity, 3),
-        "ridge_flop_per_byte": round(ridge, 2),
-        "achieved_tflops": round(kfl[dom] / sec / 1e12, 3),
-        "avg_launch_ms": round(kms[dom] / max(kn[dom], 1), 4),
-        "launches": int(kn[dom]),
-    }
+    roofline = roofline_of(kms, kfl, kby, kn)
+    roofline["traffic"] = measured_traffic(roofline.pop("_class"), args.workload)
     flops_model = sum(st.flops_model for st in stats)
     n_comp = sum(st.n_compressions for st in stats)
 
