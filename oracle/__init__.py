@@ -23,7 +23,7 @@ hamiltonian  Algorithm 1 (sequential sum) and the pairwise reduction tree
 lanczos      Global Krylov (Lanczos) step with Gram-Schmidt (Sec. 2.2).
 hf           Closed-form Hartree-Fock energy of eq. 1 for a determinant.
 
-Parity status (see the design doc for the full list): every function is pinned by
+Parity status: every function is pinned by
 a ``-m "not gpu"`` test against a dense definition, a closed form or an
 invariant, except the *truncated* H|psi> at bond dimensions where the exact
 state cannot be formed densely: "parity unpinned" beyond the untruncated
