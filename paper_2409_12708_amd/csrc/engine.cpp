@@ -488,7 +488,7 @@ struct Engine {
   const thc_opts &o;
   CallStats cs;
   // device arrays for rank / disc / sweeps of the current batch (per job x site)
-  DevBuf rk, dw, sw;
+  DevBuf rk, dw, sw, nl;
   std::vector<int> h_rank;
   std::vector<double> h_disc;
   std::vector<int> h_sw;
@@ -516,11 +516,11 @@ struct Engine {
           [&] { launch_gemm(st, nb, mode, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta, prec); });
   }
   int lq(int nb, double *X, int64_t sX, int m, int n, double *L, int64_t sL, double *Q, int64_t sQ, double *T,
-         int64_t sT, bool tr = false, int ldl = 0, int ldq = 0) {
+         int64_t sT, bool tr = false, int ldl = 0, int ldq = 0, const int *only = nullptr) {
     int rc = 0;
     const double k = std::min(m, n);
     timed(THC_K_LQ, lq_flops(m, n) * nb, 8.0 * nb * ((double)m * n + m * k + k * n), ShapeKey{THC_K_LQ, nb, m, n, 0, tr ? 1 : 0},
-          [&] { rc = launch_lq(st, nb, X, sX, m, n, L, sL, Q, sQ, T, sT, tr, ldl, ldq); });
+          [&] { rc = launch_lq(st, nb, X, sX, m, n, L, sL, Q, sQ, T, sT, tr, ldl, ldq, only); });
     return rc;
   }
   int sytrd(int nb, double *A, int64_t sA, int m, double *d, double *e, double *tau, int64_t sv) {
@@ -529,9 +529,9 @@ struct Engine {
     return rc;
   }
   int tri_eig(int nb, const double *d, const double *e, int64_t sv, int m, int kk, double *Z, int64_t sZ, double *lam,
-              int64_t sl, double *scr, int64_t sscr) {
+              int64_t sl, double *scr, int64_t sscr, int *needs_lq = nullptr) {
     int rc = 0;
-    timed(THC_K_TRI_EIG, 0.0, 8.0 * nb * (2.0 * m + (double)m * kk + kk), ShapeKey{THC_K_TRI_EIG, nb, m, kk, 0, 0}, [&] { rc = launch_tri_eig(st, nb, d, e, sv, m, kk, Z, sZ, lam, sl, scr, sscr); });
+    timed(THC_K_TRI_EIG, 0.0, 8.0 * nb * (2.0 * m + (double)m * kk + kk), ShapeKey{THC_K_TRI_EIG, nb, m, kk, 0, 0}, [&] { rc = launch_tri_eig(st, nb, d, e, sv, m, kk, Z, sZ, lam, sl, scr, sscr, needs_lq); });
     return rc;
   }
   int ormtr(int nb, const double *A, int64_t sA, int m, const double *tau, int64_t sv, double *Z, int64_t sZ, int kk,
@@ -665,7 +665,8 @@ struct Engine {
     c->ws.ensure((size_t)P.per_job * nb * sizeof(double));
     rk.ensure((size_t)nb * n * sizeof(int));
     dw.ensure((size_t)nb * n * sizeof(double));
-    sw.ensure((size_t)nb * n * sizeof(int));
+    sw.ensure((size_t)nb * n * sizeof(int) + sizeof(double));  // cleared as whole doubles
+    nl.ensure((size_t)nb * sizeof(int));
     double *W = c->ws.as<double>();
     const int64_t S = P.per_job;
     CJob *dj = upload_jobs(hjobs);
@@ -725,13 +726,21 @@ struct Engine {
       // (the tridiagonalisation reads the upper triangle only)
       gemm(nb, GEMM_TB | GEMM_UPPER, Mb, S, nc, Mb, S, nc, Gb, S, m, m, m, nc);
       if (sytrd(nb, Gb, S, m, Db, Eb, Taub, S) != 0) raise(THC_EINVAL, "site matrix too tall for sytrd");
-      if (tri_eig(nb, Db, Eb, S, m, kk, Zm, S, Lam, S, Scr, S) != 0)
+      int *nl_d = nl.as<int>();
+      if (tri_eig(nb, Db, Eb, S, m, kk, Zm, S, Lam, S, Scr, S, nl_d) != 0)
         raise(THC_EINVAL, "site matrix too tall for the tridiagonal eigensolver");
       // eigenvectors as the columns of Z (m x kk)
       if (ormtr(nb, Gb, S, m, Taub, S, Zm, S, kk, Zb, S, true, W + P.oTo, S) != 0) raise(THC_EINVAL, "ormtr size");
-      // orthonormal rows spanning the top-kk eigenvectors: LQ of Z^T, given
-      // transposed; Qz holds Q^T (m x kk)
-      if (lq(nb, Zb, S, kk, m, Lz, S, Qz, S, Tf, S, true) != 0)
+      // orthonormal columns spanning the top-kk eigenvectors, Qz (m x kk).
+      // Inverse iteration returns them orthonormal to rounding except where
+      // the eigensolver flags the job (completions below its noise floor, a
+      // cluster split at its member cap): every job takes one Newton-Schulz
+      // step Qz = Z (3I - Z^T Z) / 2 (G in Lz), and the flagged jobs the
+      // Householder LQ of Z^T (given transposed; Qz holds Q^T)
+      launch_copy(st, nb, Zb, S, Qz, S, (int64_t)m * kk);
+      gemm(nb, GEMM_TA, Zb, S, kk, Zb, S, kk, Lz, S, kk, kk, kk, m);
+      gemm(nb, 0, Zb, S, kk, Lz, S, kk, Qz, S, kk, m, kk, kk, -0.5, 1.5);
+      if (lq(nb, Zb, S, kk, m, Lz, S, Qz, S, Tf, S, true, 0, 0, nl_d) != 0)
         raise(THC_EINVAL, "site matrix too wide for the LQ kernel");
       // C = Q (kk x m) * M (m x nc)
       gemm(nb, GEMM_TA, Qz, S, kk, Mb, S, nc, Cb, S, nc, kk, nc, m);
@@ -741,9 +750,11 @@ struct Engine {
       // M_{j+1} = C (kk x c_{j+1}) * Q_{j+1} (Q_{j+1} stored transposed)
       gemm(nb, GEMM_TB, Cb, S, nc, Qs + P.qs_off[j + 1], S, nc, Mb, S, 2 * P.c[j + 2], kk, 2 * P.c[j + 2], nc, 1.0,
            0.0, cprec);
-      launches += 10;
+      launches += 13;
     }
-    if (!jacobi) HIPCHK(hipMemsetAsync(sw_d, 0, (size_t)nb * n * sizeof(int), st));
+    // no sweeps without Jacobi: clear the counts with a fill kernel (not a
+    // memset node, should the caller capture the stream into a graph)
+    if (!jacobi) launch_fill(st, 1, reinterpret_cast<double *>(sw_d), 0, ((int64_t)nb * n + 1) / 2, 0.0);
     for (int j = 0; j + 1 < n && jacobi; ++j) {
       const int m = 2 * P.k[j], nc = P.c[j + 1], kk = P.k[j + 1];
       launch_copy(st, nb, Mb, S, Yb, S, (int64_t)m * nc);

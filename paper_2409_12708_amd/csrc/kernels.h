@@ -41,9 +41,11 @@ void launch_transpose(hipStream_t st, int nb, const double *src, int64_t ss, int
 // LQ of X (m x n), k = min(m, n): L (m x k, row stride ldl), Q (k x n, row
 // stride ldq).  With tr, X is given transposed (n x m row-major) and Q is
 // returned transposed (n x k, row stride ldq); L keeps its layout.  ldl /
-// ldq <= 0 select the dense strides.
+// ldq <= 0 select the dense strides.  With only (one int per job), a job
+// whose entry is 0 is skipped and its L, Q are left as they are.
 int launch_lq(hipStream_t st, int nb, double *X, int64_t sX, int m, int n, double *L, int64_t sL, double *Q,
-              int64_t sQ, double *Tw, int64_t sT, bool tr = false, int ldl = 0, int ldq = 0);
+              int64_t sQ, double *Tw, int64_t sT, bool tr = false, int ldl = 0, int ldq = 0,
+              const int *only = nullptr);
 int launch_jacobi(hipStream_t st, int nb, double *Y, int64_t sY, int m, int n, double *s, int64_t ss, int *sweeps,
                   int max_sweeps);
 void launch_svd_select(hipStream_t st, int nb, const double *Y, int64_t sY, int m, int n, const double *s,
@@ -68,8 +70,12 @@ void launch_scale(hipStream_t st, double *p, int64_t count, double c);
 void launch_repack(hipStream_t st, int gx, const double *src, int64_t soff, int ks_l, int ks_r, double *dst,
                    int64_t doff, int rl, int rr);
 int launch_sytrd(hipStream_t st, int nb, double *A, int64_t sA, int m, double *d, double *e, double *tau, int64_t sv);
+// Top-kk eigenpairs of tridiagonals.  With needs_lq (one int per job): 1
+// where the returned vectors need not be orthonormal (completions of
+// eigenvalues below the noise floor, a cluster split at the member cap),
+// else 0.
 int launch_tri_eig(hipStream_t st, int nb, const double *d, const double *e, int64_t sv, int m, int kk, double *Z,
-                   int64_t sZ, double *lam, int64_t sl, double *scr, int64_t sscr);
+                   int64_t sZ, double *lam, int64_t sl, double *scr, int64_t sscr, int *needs_lq = nullptr);
 // U = Q_H Z; written as rows of Ut (kk x m), or with zout as Z itself (m x kk).
 // Tf: workspace for the blocks' compact-WY factors, ormtr_tf_stride(m) per job.
 int64_t ormtr_tf_stride(int m);

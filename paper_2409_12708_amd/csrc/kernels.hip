@@ -459,7 +459,9 @@ __device__ __forceinline__ void block_reflect_rows(double *__restrict__ X, int l
 template <int NMAX, bool TR>
 __global__ __launch_bounds__(512) void k_lq2(double *__restrict__ Xb, int64_t sX, int m, int n,
                                              double *__restrict__ Lb, int64_t sL, double *__restrict__ Qb,
-                                             int64_t sQ, double *__restrict__ Tb, int64_t sT, int ldl, int ldq) {
+                                             int64_t sQ, double *__restrict__ Tb, int64_t sT, int ldl, int ldq,
+                                             const int *__restrict__ only) {
+  if (only != nullptr && only[blockIdx.x] == 0) return;  // the whole workgroup: job not selected
   constexpr int NB = 16, NWV = 8;
   constexpr int VLD = NMAX + 1;     // padded row stride: rows of V fall in different LDS banks
   extern __shared__ double lds[];
@@ -1900,8 +1902,9 @@ __device__ void inv_iter_one(const double *sd, const double *se, int m, int kk, 
 __global__ __launch_bounds__(512) void k_tri_eig(const double *__restrict__ db, const double *__restrict__ eb,
                                                  int64_t sv, int m, int kk, double *__restrict__ Zb, int64_t sZ,
                                                  double *__restrict__ lamb, int64_t sl, double *__restrict__ scrb,
-                                                 int64_t sscr) {
+                                                 int64_t sscr, int *__restrict__ flagb) {
   __shared__ double sd[1024], se[1024], se2[1024];
+  __shared__ int s_need;
   __shared__ double slam[1024];
   __shared__ double s_lo, s_hi, s_tn;
   const double *d0 = db + (int64_t)blockIdx.x * sv;
@@ -1954,6 +1957,7 @@ __global__ __launch_bounds__(512) void k_tri_eig(const double *__restrict__ db, 
   if (tid == 0) s_nsig = (tn > 0.0) ? m - sturm_count(sd, se2, m, noise, pivmin) : 0;
   __syncthreads();
   const int nsig = s_nsig;
+  if (tid == 0) s_need = nsig < kk;  // pseudo-random completions among the returned vectors
   // trisection: two consecutive lanes share eigenvalue t and each evaluates
   // the Sturm count at one of the points a + (b - a) (s + 1) / 3, so every
   // step shrinks the bracket three-fold; the two lanes agree on the new
@@ -2009,11 +2013,14 @@ __global__ __launch_bounds__(512) void k_tri_eig(const double *__restrict__ db, 
     // pseudo-random starts keep the iterates independent
     auto close = [&](int u) { return slam[u - 1] - slam[u] <= gap * slam[u - 1] + 1e-15 * tn; };
     const bool leader = t == 0 || !close(t) || (t % 32 == 0);
+    if (t > 0 && t % 32 == 0 && close(t)) s_need = 1;  // a cluster split at the member cap
     if (!leader) continue;
     int t1 = t + 1;
     while (t1 < kk && t1 < nsig && close(t1) && (t1 % 32 != 0)) ++t1;
     for (int u = t; u < t1; ++u) inv_iter_one(sd, se, m, kk, u, slam[u], tiny, U0, U1, U2, Z, t);
   }
+  __syncthreads();
+  if (flagb != nullptr && tid == 0) flagb[blockIdx.x] = s_need;
 }
 
 
@@ -2144,7 +2151,7 @@ static void set_lds(K kern, size_t lds) {
 // one instantiation of k_lq2: NMAX bounds n (panel rows in LDS, registers per lane)
 template <int NMAX, bool TR>
 static void lq_variant(hipStream_t st, int nb, double *X, int64_t sX, int m, int n, double *L, int64_t sL, double *Q,
-                       int64_t sQ, double *Tw, int64_t sT, int ldl, int ldq) {
+                       int64_t sQ, double *Tw, int64_t sT, int ldl, int ldq, const int *only) {
   constexpr int NWV = 8;
   constexpr size_t lds = (16 * (NMAX + 1) + 256 + 256 + (NWV + 1) * 256 + 256 + 16 + 256) * sizeof(double);
   static bool attr = false;
@@ -2152,21 +2159,22 @@ static void lq_variant(hipStream_t st, int nb, double *X, int64_t sX, int m, int
     set_lds(k_lq2<NMAX, TR>, lds);
     attr = true;
   }
-  hipLaunchKernelGGL((k_lq2<NMAX, TR>), dim3(nb), dim3(512), lds, st, X, sX, m, n, L, sL, Q, sQ, Tw, sT, ldl, ldq);
+  hipLaunchKernelGGL((k_lq2<NMAX, TR>), dim3(nb), dim3(512), lds, st, X, sX, m, n, L, sL, Q, sQ, Tw, sT, ldl, ldq,
+                     only);
 }
 
 int launch_lq(hipStream_t st, int nb, double *X, int64_t sX, int m, int n, double *L, int64_t sL, double *Q,
-              int64_t sQ, double *Tw, int64_t sT, bool tr, int ldl, int ldq) {
+              int64_t sQ, double *Tw, int64_t sT, bool tr, int ldl, int ldq, const int *only) {
   const int k = m < n ? m : n;
   if (ldl <= 0) ldl = k;
   if (ldq <= 0) ldq = tr ? k : n;
   if (n > 1024) return -1;
   if (n <= 512) {
-    if (tr) lq_variant<512, true>(st, nb, X, sX, m, n, L, sL, Q, sQ, Tw, sT, ldl, ldq);
-    else lq_variant<512, false>(st, nb, X, sX, m, n, L, sL, Q, sQ, Tw, sT, ldl, ldq);
+    if (tr) lq_variant<512, true>(st, nb, X, sX, m, n, L, sL, Q, sQ, Tw, sT, ldl, ldq, only);
+    else lq_variant<512, false>(st, nb, X, sX, m, n, L, sL, Q, sQ, Tw, sT, ldl, ldq, only);
   } else {
-    if (tr) lq_variant<1024, true>(st, nb, X, sX, m, n, L, sL, Q, sQ, Tw, sT, ldl, ldq);
-    else lq_variant<1024, false>(st, nb, X, sX, m, n, L, sL, Q, sQ, Tw, sT, ldl, ldq);
+    if (tr) lq_variant<1024, true>(st, nb, X, sX, m, n, L, sL, Q, sQ, Tw, sT, ldl, ldq, only);
+    else lq_variant<1024, false>(st, nb, X, sX, m, n, L, sL, Q, sQ, Tw, sT, ldl, ldq, only);
   }
   return 0;
 }
@@ -2304,9 +2312,9 @@ int launch_sytrd(hipStream_t st, int nb, double *A, int64_t sA, int m, double *d
 }
 
 int launch_tri_eig(hipStream_t st, int nb, const double *d, const double *e, int64_t sv, int m, int kk, double *Z,
-                   int64_t sZ, double *lam, int64_t sl, double *scr, int64_t sscr) {
+                   int64_t sZ, double *lam, int64_t sl, double *scr, int64_t sscr, int *needs_lq) {
   if (m > 1024 || kk > 256) return -1;
-  hipLaunchKernelGGL(k_tri_eig, dim3(nb), dim3(512), 0, st, d, e, sv, m, kk, Z, sZ, lam, sl, scr, sscr);
+  hipLaunchKernelGGL(k_tri_eig, dim3(nb), dim3(512), 0, st, d, e, sv, m, kk, Z, sZ, lam, sl, scr, sscr, needs_lq);
   return 0;
 }
 
