@@ -117,7 +117,10 @@ typedef struct {
  * one-stage tridiagonalisation streams the trailing upper triangle once per
  * column and writes it once per panel of 8 (sum over columns of
  * s(s+1)/2 for trailing size s, plus that sum over the first columns of
- * the panels after the first).  Off by default. */
+ * the panels after the first).  A launch that skips some of its jobs (the
+ * LQ re-orthonormalisation of the truncation step, run only where the
+ * eigensolver's vectors need it) is counted as if every job ran.  Off by
+ * default. */
 #define THC_FLAG_TIME_KERNELS 2ull
 
 enum {
