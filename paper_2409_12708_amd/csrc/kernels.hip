@@ -1796,7 +1796,9 @@ __device__ __forceinline__ int sturm_count(const double *d, const double *e2, in
 // floor 1e-14*||T|| get pseudo-random vectors (they only need to complete
 // an orthonormal basis, which the re-orthonormalisation that follows
 // provides).
-// Output Z (m x kk, column t = eigenvector t) and lambda (kk, descending).
+// Output Z (m x kk, column t = eigenvector t) and lambda (kk, descending);
+// with flagb, per job 1 where Z need not be orthonormal (noise-floor
+// completions among the kk vectors, a cluster split at the member cap), else 0.
 // Scratch per job: 3 m kk doubles (the bands of U), laid out [r][t].
 // pseudo-random start component (k, t) of inverse iteration, in [-1/2, 1/2)
 __device__ __forceinline__ double inv_iter_start(int k, int t) {
