@@ -107,3 +107,100 @@ def sum_compress(coeffs, terms, D, eps=M.CUTOFF):
     if len(scaled) == 1:
         return M.compress(scaled[0], D, eps)
     return sum_tree(scaled, D, eps)
+
+
+# ---------------------------------------------------------------------------
+# The same tree, fed one node at a time, and H|psi> with its independent
+# compressions handed to a caller-supplied map (large cases only).
+# ---------------------------------------------------------------------------
+
+class StreamTree:
+    """The pairwise tree of ``sum_tree`` built as the nodes arrive.
+
+    Nodes reaching a level in order pair as (2k, 2k+1): the first two nodes
+    waiting at a level are compressed together and the result moves up one
+    level.  ``finish`` carries a lone node up, lowest level first, as the odd
+    last element of a level carries up in ``sum_tree`` (Sec. 4.5, Fig. 11).
+    The pairs and their operands are those of ``sum_tree``; only the time at
+    which each pair is formed differs.  ``push(node, level)`` with level > 0
+    enters the root of a complete subtree of 2**level consecutive leaves.
+    """
+
+    def __init__(self, D, eps=M.CUTOFF):
+        self.D, self.eps = D, eps
+        self.levels = []
+
+    def push(self, node, level=0):
+        while len(self.levels) <= level:
+            self.levels.append([])
+        self.levels[level].append(node)
+        if len(self.levels[level]) == 2:
+            a, b = self.levels[level]
+            self.levels[level] = []
+            self.push(add_compress(a, b, self.D, self.eps), level + 1)
+
+    def finish(self):
+        while True:
+            filled = [l for l, q in enumerate(self.levels) if q]
+            if not filled:
+                raise ValueError("empty sum")
+            if len(filled) == 1:
+                return self.levels[filled[0]][0]
+            low = filled[0]
+            node = self.levels[low].pop()
+            self.push(node, low + 1)
+
+
+def _leaf_job(args):
+    start, x, s, D, eps = args
+    return one_body_pair(start, x, s, D, eps)
+
+
+def _pair_job(args):
+    a, b, D, eps = args
+    return add_compress(a, b, D, eps)
+
+
+def apply_H_mapped(psi, t, chi, zeta, D, eps=M.CUTOFF, mapper=map, window=256):
+    """``apply_H(mode="tree")`` with the independent compressions handed to
+    ``mapper`` (the builtin ``map``, or a process pool's ordered ``map``).
+
+    The prefix states, the leaves and the pairs of the tree are the ones of
+    ``apply_H``: leaves are produced in summation order in windows of
+    ``window`` (a power of two) consecutive leaves; a full window starts at
+    a multiple of ``window``, so its leaves form a complete subtree of the
+    tree, reduced level by level (each level's pairs through ``mapper``) and
+    entered at its level; the leaves of a last, partial window are entered
+    one by one.  Only the schedule differs from ``apply_H``.
+    """
+    if window < 1 or window & (window - 1):
+        raise ValueError("window must be a power of two")
+    depth = window.bit_length() - 1
+    N = chi.shape[1]
+    pre_specs = [(psi, chi[:, nu], sp_, D, eps) for nu in range(N) for sp_ in (0, 1)]
+    pre_states = list(mapper(_leaf_job, pre_specs))
+    pre = {(nu, sp_): pre_states[2 * nu + sp_] for nu in range(N) for sp_ in (0, 1)}
+    specs = []
+    for nu, sp_, mu, s in v_terms(N):
+        c = 0.5 * zeta[mu, nu]
+        if c != 0.0:
+            specs.append(((nu, sp_), c, chi[:, mu], s))
+    lam, u = kinetic_split(t)
+    for i in range(lam.shape[0]):
+        if lam[i] != 0.0:
+            for s in (0, 1):
+                specs.append((None, lam[i], u[:, i], s))
+    tree = StreamTree(D, eps)
+    for w0 in range(0, len(specs), window):
+        chunk = specs[w0:w0 + window]
+        jobs = [(M.scale(psi if key is None else pre[key], c), x, s, D, eps) for key, c, x, s in chunk]
+        level = list(mapper(_leaf_job, jobs))
+        if len(chunk) == window:
+            for _ in range(depth):
+                level = list(mapper(_pair_job, [(level[2 * k], level[2 * k + 1], D, eps)
+                                                for k in range(len(level) // 2)]))
+            tree.push(level[0], depth)
+        else:
+            for node in level:
+                tree.push(node, 0)
+    return tree.finish()

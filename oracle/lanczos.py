@@ -23,6 +23,8 @@ S_EIG_FLOOR = 1e-10
 
 
 def ritz_tridiagonal(alpha, beta):
+    """Eigenvalues of the Lanczos tridiagonal: alpha_i on the diagonal,
+    beta_i between basis vectors i and i+1 (Sec. 2.2)."""
     m = len(alpha)
     T = np.diag(np.asarray(alpha, float))
     for k in range(m - 1):
@@ -31,16 +33,23 @@ def ritz_tridiagonal(alpha, beta):
 
 
 def ritz_generalized(Hm: np.ndarray, S: np.ndarray):
+    """Eigenvalues of H_sym = (M + M^T)/2 in the re-orthogonalised basis
+    psi_a = sum_i C_ai v_i with C S C^T = I (eq. reortho, eq. eff_H).
+
+    When every eigenvalue of S exceeds S_EIG_FLOOR, C = L^{-1} with S = L L^T
+    (Cholesky) and all m values are returned.  Otherwise S is numerically
+    singular and the basis is canonically orthogonalised: C = s^{-1/2} U^T
+    over the eigenpairs (s, U) of S with s > S_EIG_FLOOR, giving fewer
+    values (reading A12).
+    """
     Hs = 0.5 * (Hm + Hm.T)
-    try:
-        Lc = np.linalg.cholesky(S)
-        Cm = np.linalg.inv(Lc)
+    s, U = np.linalg.eigh(S)
+    if s.size and s[0] > S_EIG_FLOOR:
+        Cm = np.linalg.inv(np.linalg.cholesky(S))
         return np.linalg.eigvalsh(Cm @ Hs @ Cm.T)
-    except np.linalg.LinAlgError:
-        s, U = np.linalg.eigh(S)
-        keep = s > S_EIG_FLOOR
-        X = U[:, keep] / np.sqrt(s[keep])
-        return np.linalg.eigvalsh(X.T @ Hs @ X)
+    keep = s > S_EIG_FLOOR
+    X = U[:, keep] / np.sqrt(s[keep])
+    return np.linalg.eigvalsh(X.T @ Hs @ X)
 
 
 class KrylovState:

@@ -117,6 +117,17 @@ def right_canonicalize(psi):
     return out
 
 
+def thin_svd(a: np.ndarray):
+    """Thin SVD a = u diag(s) vt, s descending.  LAPACK's divide-and-conquer
+    driver (numpy) first; when it reports non-convergence, which it can on
+    strongly rank-deficient matrices, the QR-iteration driver (gesvd)."""
+    try:
+        return np.linalg.svd(a, full_matrices=False)
+    except np.linalg.LinAlgError:
+        import scipy.linalg
+        return scipy.linalg.svd(a, full_matrices=False, lapack_driver="gesvd")
+
+
 def truncation_rank(s: np.ndarray, D: int, eps: float = CUTOFF) -> int:
     """k = max(1, min(D, #{s_i > eps * s_1})) (reading A5)."""
     if s.size == 0 or s[0] <= 0.0:
@@ -130,7 +141,7 @@ def svd_sweep(psi, D: int, eps: float = CUTOFF, record=None):
     for j in range(len(out) - 1):
         a = out[j]
         l, d, r = a.shape
-        u, s, vt = np.linalg.svd(a.reshape(l * d, r), full_matrices=False)
+        u, s, vt = thin_svd(a.reshape(l * d, r))
         k = truncation_rank(s, D, eps)
         if record is not None:
             record.append(s.copy())
