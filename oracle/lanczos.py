@@ -52,6 +52,23 @@ def ritz_generalized(Hm: np.ndarray, S: np.ndarray):
     return np.linalg.eigvalsh(X.T @ Hs @ X)
 
 
+def ritz_pairs(Hm: np.ndarray, S: np.ndarray):
+    """Ritz values w_a and coefficient vectors X[:, a] of the generalised
+    problem of ``ritz_generalized``: psi_a = sum_i X[i, a] v_i is the Ritz
+    vector of w_a, normalised in the metric S (X^T S X = I).  With C the
+    re-orthogonalising transform (rows c_b) and y_a the eigenvectors of
+    C H_sym C^T, X = C^T Y (eq. reortho, eq. eff_H)."""
+    Hs = 0.5 * (Hm + Hm.T)
+    s, U = np.linalg.eigh(S)
+    if s.size and s[0] > S_EIG_FLOOR:
+        Cm = np.linalg.inv(np.linalg.cholesky(S))
+    else:
+        keep = s > S_EIG_FLOOR
+        Cm = (U[:, keep] / np.sqrt(s[keep])).T
+    w, Y = np.linalg.eigh(Cm @ Hs @ Cm.T)
+    return w, Cm.T @ Y
+
+
 class KrylovState:
     def __init__(self, v0, K: int):
         nv = M.norm(v0)
@@ -116,3 +133,45 @@ def dense_lanczos(Hmat_apply, v0: np.ndarray, K: int):
             break
         v.append(r / b)
     return ritz
+
+
+def ritz_vector(st: KrylovState, a: int, D: int, eps=M.CUTOFF):
+    """MPS of the a-th Ritz vector (ascending Ritz values) over the basis
+    v_0..v_{m-1} of the steps taken: sum_i X[i, a] v_i, summed by
+    ``sum_compress`` (Sec. 2.2, eq. reortho)."""
+    m = st.i
+    _, X = ritz_pairs(st.Mm[:m, :m], st.S[:m, :m])
+    return sum_compress(list(X[:, a]), st.v[:m], D, eps)
+
+
+def restart(st: KrylovState, a: int, D: int, K: int = None, eps=M.CUTOFF) -> KrylovState:
+    """A new Krylov state started from the a-th Ritz vector of st (the
+    restart the paper uses to recover convergence lost to truncation,
+    Sec. 2.2); the new start vector is normalised by KrylovState."""
+    return KrylovState(ritz_vector(st, a, D, eps), st.K if K is None else K)
+
+
+def dense_lanczos_restarted(Hmat_apply, v0: np.ndarray, K: int, restarts: int, a: int = 0):
+    """Textbook dense Lanczos (full Gram-Schmidt) restarted ``restarts`` times
+    from its a-th Ritz vector after every K steps (pin reference).  Returns
+    the Ritz values after every step."""
+    out = []
+    v0 = v0 / np.linalg.norm(v0)
+    for _ in range(restarts + 1):
+        V = [v0]
+        for i in range(K):
+            w = Hmat_apply(V[i])
+            Vm = np.stack(V)
+            Hp = Vm @ np.stack([Hmat_apply(x) for x in V]).T
+            vals, vecs = np.linalg.eigh(0.5 * (Hp + Hp.T))
+            out.append(vals)
+            r = w - sum((x @ w) * x for x in V)
+            r = r - sum((x @ r) * x for x in V)
+            b = np.linalg.norm(r)
+            if i + 1 < K and b > 1e-12:
+                V.append(r / b)
+            else:
+                break
+        v0 = np.stack(V).T @ vecs[:, a]
+        v0 = v0 / np.linalg.norm(v0)
+    return out

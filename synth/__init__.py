@@ -85,6 +85,19 @@ def hartree_fock_occupation(L: int, n_elec: int) -> list[int]:
     return occ
 
 
+def single_excitation_occupation(L: int, n_elec: int, spin: int = 0) -> list[int]:
+    """The closed-shell occupation with one electron of the given spin moved
+    from the highest occupied spatial orbital to the lowest empty one (an
+    excited start vector orthogonal to the Hartree-Fock determinant)."""
+    occ = hartree_fock_occupation(L, n_elec)
+    homo, lumo = n_elec // 2 - 1, n_elec // 2
+    if homo < 0 or lumo >= L:
+        raise ValueError("no occupied or no empty orbital to excite")
+    occ[2 * homo + spin] = 0
+    occ[2 * lumo + spin] = 1
+    return occ
+
+
 def random_dense_vector(rng: np.random.Generator, n_sites: int) -> np.ndarray:
     """Random dense real vector of length 2^n_sites (un-normalised)."""
     return rng.standard_normal(2 ** n_sites)
