@@ -98,9 +98,13 @@ typedef struct {
 
 /* opts.flags: SVD method of the truncation step.  Default: eigenpairs of the
  * Gram matrix Y Y^T (Householder tridiagonalisation, bisection, inverse
- * iteration) - about 5x fewer flops; singular values below ~1e-8 s_1 are
- * resolved only to ~eps s_1^2 / s.  THC_FLAG_SVD_JACOBI: one-sided block
- * Jacobi on Y itself (high relative accuracy, slower). */
+ * iteration), about 5x fewer flops than a bidiagonal SVD.  An eigenvalue
+ * of the m x m Gram matrix is only resolved to ~m eps lambda_1, so every
+ * job whose kept eigenvalues reach 32 m eps lambda_1 (rank-deficient sums,
+ * exact zeros in the Schmidt spectrum) gets a second Gram level: the
+ * eigenvectors of (Y - Q1 Q1^T Y)(...)^T, with Q1 the resolved ones, fill
+ * the rest of the kept basis; the count is thc_stats.svd_fallbacks.  THC_FLAG_SVD_JACOBI: one-sided block Jacobi on
+ * Y for every job (high relative accuracy, slower). */
 #define THC_FLAG_SVD_JACOBI 1ull
 
 /* opts.flags: record a pair of HIP events (on the call's stream) around each
@@ -113,15 +117,23 @@ typedef struct {
  * move: LQ reads X and writes L and Q; GEMM reads A and B, reads C when
  * beta != 0 and writes C (the upper half with upper-triangle tiles);
  * back-transformation reads the reflectors (m^2/2) and Z and writes U;
- * bisection/inverse iteration reads d, e and writes the k vectors; the
- * one-stage tridiagonalisation streams the trailing upper triangle once per
- * column and writes it once per panel of 8 (sum over columns of
- * s(s+1)/2 for trailing size s, plus that sum over the first columns of
- * the panels after the first).  A launch that skips some of its jobs (the
+ * bisection/inverse iteration reads d, e and writes the k vectors;
+ * tridiagonalisation reads the upper triangle once and writes the
+ * reflectors over it and d, e, tau (m^2 + 3m doubles; the one-stage kernel
+ * of this library re-reads the trailing triangle once per column, which
+ * only the measured traffic shows).  A launch that skips some of its jobs (the
  * LQ re-orthonormalisation of the truncation step, run only where the
- * eigensolver's vectors need it) is counted as if every job ran.  Off by
- * default. */
+ * eigensolver's vectors need it) is counted as if every job ran; the
+ * second Gram level's launches are timed in their own class with no flops or
+ * bytes.  Off by default. */
 #define THC_FLAG_TIME_KERNELS 2ull
+
+/* opts.flags: capture the launch sequence of a compression batch into a HIP
+ * graph the second time a batch of the same signature (plan, batch size,
+ * options) runs, and launch the graph from then on (graphs are kept by the
+ * context, dropped when its workspace is reallocated).  Ignored with
+ * THC_FLAG_TIME_KERNELS.  Results are the same as without it. */
+#define THC_FLAG_GRAPHS 4ull
 
 enum {
   THC_K_LQ = 0,      /* Householder LQ with Q formation (canonical sweep and re-orthonormalisation) */
@@ -129,22 +141,29 @@ enum {
   THC_K_TRI_EIG = 2, /* bisection + inverse iteration */
   THC_K_ORMTR = 3,   /* back-transformation of the eigenvectors */
   THC_K_GEMM = 4,    /* batched GEMMs of the compression */
-  THC_NK = 5
+  THC_K_SVD_FALLBACK = 5, /* second Gram level of the jobs at the noise floor (time only; flops not counted) */
+  THC_NK = 6
 };
 
 typedef struct {
   double discarded_weight_max; /* max over compressions and bonds of sum_{i>k} s_i^2 */
-  double flops_model;          /* algorithmic flops (LAPACK-formula model) of the call */
+  double flops_model;          /* flops of the operations the call runs: LAPACK counts of its factorisations
+                                  (LQ 4nk^2 - 4k^3/3, tridiagonalisation 4m^3/3, back-transformation 2m^2 k)
+                                  and 2MNK per product, for the Gram SVD route (Gram matrix, Newton-Schulz
+                                  step, C = Q^T Y); second Gram levels and flagged re-orthonormalisations are
+                                  not counted */
   int64_t n_compressions;      /* number of MPS compressions performed */
   int64_t n_launches;          /* kernel launches issued */
   int32_t max_bond;            /* largest bond kept (after the cutoff) */
   int32_t jacobi_sweeps_max;   /* most Jacobi sweeps any SVD needed */
   int32_t nonconverged;        /* SVDs that hit the sweep limit */
-  int32_t reserved;
+  int32_t svd_fallbacks;       /* SVDs redone by the second Gram level (kept eigenvalues at the noise floor) */
   double kernel_ms[THC_NK];        /* THC_FLAG_TIME_KERNELS: summed device time per kernel class */
   double kernel_flops[THC_NK];     /* algorithmic flops of those launches */
   int64_t kernel_launches[THC_NK];
   double kernel_bytes[THC_NK];     /* algorithmic device-memory bytes of those launches */
+  int64_t graph_captures;          /* THC_FLAG_GRAPHS: compression batches captured into a HIP graph */
+  int64_t graph_replays;           /* THC_FLAG_GRAPHS: compression batches launched from a captured graph */
 } thc_stats;
 
 typedef struct thc_ctx thc_ctx;
@@ -177,8 +196,9 @@ thc_status thc_destroy(thc_ctx *ctx);
 /* out <- compressed H|psi> (Algorithm 1 terms with the reuse of
  * G_{nu sigma'}|psi>, Sec. 3.2; kinetic part by App. D; summed by the
  * pairwise tree of Sec. 4.5).  psi->n_sites must equal 2L.  psi and out
- * must not alias.  st may be NULL.  Synchronises the stream once at the end
- * (to read back the kept bond dimensions). */
+ * must not alias.  st may be NULL.  Synchronises the stream after each
+ * batch of compressions (the kept bond dimensions decide how later jobs
+ * are grouped and how the output is packed) and at the end. */
 thc_status mps_apply_thc_H(thc_ctx *ctx, const thc_mps *psi, thc_mps *out, const thc_opts *o,
                            thc_stats *st, void *hip_stream);
 
@@ -186,7 +206,8 @@ thc_status mps_apply_thc_H(thc_ctx *ctx, const thc_mps *psi, thc_mps *out, const
  * Algorithm 1).  k >= 1; for k > 1 the terms are summed by the pairwise
  * tree (pair 2i with 2i+1, an odd last term carries up), every node
  * compressed to D_sum (0 = D_max) and the root to D_max.  coeffs is host.
- * All terms must have the same n_sites.  Synchronises once at the end. */
+ * All terms must have the same n_sites.  Synchronises after each batch of
+ * compressions and at the end. */
 thc_status mps_sum_compress(thc_ctx *ctx, int32_t k, const double *coeffs, const thc_mps *const *terms,
                             thc_mps *out, const thc_opts *o, thc_stats *st, void *hip_stream);
 
@@ -213,10 +234,32 @@ thc_status krylov_destroy(thc_krylov *state);
  *                   canonical orthogonalisation if S is singular);
  *   ritz_tri[0..i]  eigenvalues of the tridiagonal (alpha_i = h_ii, beta).
  * ritz_gen, ritz_tri (nullable) and beta are host arrays / scalars written
- * before return: this call synchronises once.  Returns THC_EINVAL once K
- * steps have been taken. */
+ * before return.  The call synchronises the stream: once per compression
+ * batch inside its H application and sum-compression (to read back the
+ * kept bond dimensions), after every overlap, and at the end.  When S has
+ * an eigenvalue at or below 1e-10, ritz_gen holds the values of the
+ * canonically orthogonalised basis first and NaN in the remaining entries.
+ * Returns THC_EINVAL once K steps have been taken. */
 thc_status krylov_step(thc_krylov *state, double *ritz_gen, double *ritz_tri, double *beta,
                        thc_stats *st, void *hip_stream);
+
+/* out <- the a-th Ritz vector (a = 0: lowest Ritz value) of the steps taken:
+ * psi = sum_i x_i v_i over v_0..v_{m-1}, m = steps taken, with x = C^T y_a
+ * from the generalised problem of krylov_step (eq. reortho, eq. eff_H;
+ * y_a the a-th eigenvector of C H_sym C^T), summed and compressed by
+ * mps_sum_compress with the state's options.  out follows mps_sum_compress's
+ * rules (capacity, no aliasing).  THC_EINVAL when no step has been taken or
+ * a is not below the number of kept basis directions.  Synchronises. */
+thc_status krylov_ritz_vector(thc_krylov *state, int32_t a, thc_mps *out, void *hip_stream);
+
+/* Restart (Sec. 2.2: restarting recovers convergence lost to truncation):
+ * v_0 <- the a-th Ritz vector, normalised; the basis, M, S, alpha and beta
+ * are cleared, so the next krylov_step starts a new Krylov space of up to K
+ * vectors from it.  For an excited state, start krylov_create from a vector
+ * orthogonal to the lower eigenstates (Sec. 2.2; the paper uses a
+ * Hartree-Fock single excitation) and restart from a = 0 of that run.
+ * Synchronises. */
+thc_status krylov_restart(thc_krylov *state, int32_t a, void *hip_stream);
 
 /* Copy Krylov vector v_i (i <= steps taken) into a caller MPS. */
 thc_status krylov_get_vector(thc_krylov *state, int32_t i, thc_mps *out, void *hip_stream);
@@ -233,6 +276,27 @@ thc_status mps_compress(thc_ctx *ctx, const thc_mps *in, thc_mps *out, const thc
  * y is a host array of n_sites spin-orbital coefficients. */
 thc_status mps_apply_layer(thc_ctx *ctx, const thc_mps *psi, const double *y, int32_t dag,
                            thc_mps *out, const thc_opts *o, thc_stats *st, void *hip_stream);
+
+/* Energy E = <psi|H|psi> of a real MPS and its gradient with respect to the
+ * context's THC factors, for THC-factor fitting (Sec. 2.3) and orbital
+ * gradients.  With N_nu = sum_s a+(chi^nu)_s a(chi^nu)_s (the G terms of
+ * eq. G_mu_nu_def summed over the spins, Sec. 3.1), V = 1/2 sum zeta_{mu nu}
+ * N_mu N_nu and, for fixed psi,
+ *   dzeta[mu * N + nu] = dE/dzeta_{mu nu} = 1/2 <psi|N_mu N_nu|psi>
+ *     (every entry independent, zeta not symmetrised),
+ *   dchi[p * N + k]    = dE/dchi_p^k
+ *     = 1/2 sum_nu (zeta_{k nu} + zeta_{nu k}) <psi|dN_k/dchi_p^k N_nu|psi>.
+ * H|psi> is applied without truncation: each n_{nu s}|psi> is formed
+ * exactly by two layer MPOs (bond 4 b_j) and the transition one-body
+ * matrices <psi|a+_i a_j n_{nu s}|psi> are contracted by transfer-matrix
+ * chains on the device.  prec: THC_PREC_F64 or THC_PREC_F32 (the
+ * contraction precision of those chains; FP32 operands, FP32 accumulation).
+ * energy, dchi (L x N), dzeta (N x N) are host outputs; any may be NULL, not
+ * all.  psi->n_sites must equal 2L.  Device memory grows with the bonds
+ * (~(2N + 2L) kets of bond 4 b_j, processed in chunks within ~48 GiB).
+ * Synchronises. */
+thc_status thc_energy_gradient(thc_ctx *ctx, const thc_mps *psi, int32_t prec, double *energy, double *dchi,
+                               double *dzeta, void *hip_stream);
 
 /* Thread-local description of the last non-OK status. */
 const char *thc_last_error(void);

@@ -163,8 +163,43 @@ struct thc_ctx {
   DevBuf stat_dev;
   std::vector<int> stat_rank_host;
   int batch_default = 0;
+  // per-batch device arrays (rank, discarded weight, sweep count per job and
+  // bond; the re-orthonormalisation and Jacobi flags per job), sized once for
+  // the largest batch so that captured graphs can keep their addresses
+  DevBuf rk, dw, sw, nl, jf, r1, gjobs;
+  int batch_cap = 0;
+  // captured compression batches (THC_FLAG_GRAPHS)
+  struct GraphRec {
+    hipGraphExec_t exec;
+    int64_t launches;
+  };
+  std::map<std::string, GraphRec> graphs;
+  std::map<std::string, int> graph_seen;
+  int64_t graph_captures = 0, graph_replays = 0;
 
   double *coef_ptr(int row) const { return coef.as<double>() + (size_t)row * n; }
+  void drop_graphs() {
+    for (auto &g : graphs) (void)hipGraphExecDestroy(g.second.exec);
+    graphs.clear();
+    graph_seen.clear();
+  }
+  void ensure_batch_arrays(int nb) {
+    if (nb <= batch_cap) return;
+    drop_graphs();
+    rk.ensure((size_t)nb * n * sizeof(int));
+    dw.ensure((size_t)nb * n * sizeof(double));
+    sw.ensure((size_t)nb * n * sizeof(int) + sizeof(double));  // cleared as whole doubles
+    nl.ensure((size_t)nb * sizeof(int));
+    jf.ensure((size_t)nb * sizeof(int));
+    r1.ensure((size_t)nb * sizeof(int));
+    gjobs.ensure((size_t)nb * sizeof(CJob));
+    batch_cap = nb;
+  }
+  hipStream_t cap_stream = nullptr;  // stream the graphs are captured on
+  ~thc_ctx() {
+    drop_graphs();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  }
 };
 
 namespace {
@@ -200,6 +235,16 @@ void slot_free(thc_ctx *c, double *p) {
     }
 }
 
+// Noise floor of the Gram route, per row of the m x m Gram matrix G = Y Y^T:
+// Householder tridiagonalisation perturbs G by ~m eps ||G||, so a kept
+// eigenvalue below GRAM_NOISE_PER_ROW * m * eps * lambda_1 cannot be told
+// from an exact zero (a singular value near sqrt(m eps) s_1) and its vector
+// mixes with the noise directions.  Jobs whose kept set reaches that floor
+// (rank-deficient sums, states with exact zeros in their Schmidt spectra)
+// get a second Gram level on the deflated matrix (gram_level2).
+constexpr double GRAM_NOISE_PER_ROW = 32.0;
+inline double gram_floor(int m) { return GRAM_NOISE_PER_ROW * m * 2.220446049250313e-16; }
+
 // ---------------------------------------------------------------------------
 // compression plan
 // ---------------------------------------------------------------------------
@@ -218,7 +263,7 @@ struct Plan {
   Profile out;
   // per-job workspace layout (elements)
   int64_t oB = 0, oT = 0, oL = 0, oQs = 0, oM = 0, oY = 0, oW = 0, oZ = 0, oC = 0, oLz = 0, oQz = 0, oTf = 0,
-          oS = 0, oU = 0, oG = 0, oDet = 0, oZm = 0, oLam = 0, oScr = 0, oTo = 0;
+          oS = 0, oU = 0, oG = 0, oDet = 0, oDet2 = 0, oZm = 0, oLam = 0, oScr = 0, oTo = 0;
   int64_t sv = 0;  // stride of the d / e / tau vectors inside oDet
   std::vector<int64_t> qs_off;  // offset of Q_j inside Qs
   int64_t per_job = 0;
@@ -229,23 +274,11 @@ double lq_flops(double m, double n) {  // LQ of m x n (m rows): R + thin Q, LAPA
   double k = std::min(m, n), M = std::max(m, n);
   return 2.0 * (2.0 * M * k * k - 2.0 * k * k * k / 3.0);
 }
-// Device-memory bytes of the one-stage tridiagonalisation of an m x m matrix
-// (panels of 8): the trailing upper triangle (s(s+1)/2 entries for trailing
-// size s) is read once per column and written once more by the first column
-// of each panel after the first, which applies the previous panel's update.
-double sytrd_bytes(int m) {
-  constexpr int NB = 8;
-  double el = 0.0;
-  for (int i = 0; i < m - 2; ++i) {
-    const double s = m - i - 1;
-    el += 0.5 * s * (s + 1.0) * ((i > 0 && i % NB == 0) ? 2.0 : 1.0);
-  }
-  return 8.0 * el;
-}
-double svd_flops(double m, double n) {  // Golub-Reinsch thin SVD with U and V (model)
-  double k = std::min(m, n), M = std::max(m, n);
-  return 14.0 * M * k * k + 8.0 * k * k * k;
-}
+// Device-memory bytes the tridiagonalisation of an m x m symmetric matrix
+// must move: its upper triangle read once, the reflectors written over it,
+// d, e and tau written.  (The one-stage kernel re-reads the trailing
+// triangle once per column; that excess shows in the measured traffic.)
+double sytrd_bytes(int m) { return 8.0 * ((double)m * m + 3.0 * m); }
 
 Plan make_plan(int kind, const Profile &pa, const Profile *pb, int D, bool rc_in = false) {
   Plan P;
@@ -316,7 +349,7 @@ Plan make_plan(int kind, const Profile &pa, const Profile *pb, int D, bool rc_in
     if (j + 1 < n) {
       const int m = 2 * P.k[j], nc = P.c[j + 1], kk = P.k[j + 1];
       mM = std::max(mM, (int64_t)m * nc);
-      mW = std::max(mW, (int64_t)kk * nc);
+      mW = std::max(mW, std::max((int64_t)kk * nc, (int64_t)m * kk));
       mZ = std::max(mZ, (int64_t)kk * m);
       mQz = std::max(mQz, (int64_t)kk * m);
       mLz = std::max(mLz, (int64_t)kk * kk);
@@ -327,7 +360,11 @@ Plan make_plan(int kind, const Profile &pa, const Profile *pb, int D, bool rc_in
       mZm = std::max(mZm, (int64_t)m * kk);
       mScr = std::max(mScr, tri_eig_scratch(m, kk));
       mTo = std::max(mTo, ormtr_tf_stride(m));
-      fl += svd_flops(m, nc);
+      // the Gram route of the SVD as it runs: G = Y Y^T (upper half),
+      // tridiagonalisation, back-transformation of kk vectors, one
+      // Newton-Schulz step (Z^T Z and Z (Z^T Z)), C = Q^T Y
+      fl += (double)m * m * nc + 4.0 / 3.0 * m * (double)m * m + 2.0 * m * (double)m * kk +
+            4.0 * m * (double)kk * kk + 2.0 * kk * (double)m * nc;
       fl += 2.0 * kk * nc * 2.0 * P.c[j + 2];  // absorb S V^T into site j+1
     }
     mTf = std::max(mTf, (int64_t)lq_t_stride(std::max(P.c[j], 1)));
@@ -356,6 +393,7 @@ Plan make_plan(int kind, const Profile &pa, const Profile *pb, int D, bool rc_in
   P.oG = take(std::max<int64_t>(mG, 1));
   P.sv = (std::max<int64_t>(mS, 1) + 31) / 32 * 32;
   P.oDet = take(3 * P.sv);
+  P.oDet2 = take(3 * P.sv);
   P.oZm = take(std::max<int64_t>(mZm, 1));
   P.oLam = take(std::max<int64_t>(mS, 1));
   P.oScr = take(std::max<int64_t>(mScr, 1));
@@ -376,6 +414,8 @@ struct CallStats {
   int max_bond = 0;
   int sweeps_max = 0;
   int nonconv = 0;
+  int fallbacks = 0;
+  int64_t graph_captures = 0, graph_replays = 0;
   int64_t compressions = 0;
   int64_t launches = 0;
   double flops = 0.0;
@@ -403,7 +443,8 @@ std::map<ShapeKey, ShapeStat> &shape_stats() {
   return *m;
 }
 void print_shape_stats() {
-  static const char *names[THC_NK] = {"lq", "sytrd", "tri_eig", "ormtr", "gemm"};
+  static const char *names[THC_NK] = {"lq", "sytrd", "tri_eig", "ormtr", "gemm", "svd_fallback"};
+  gemm_tuning_report(stderr);
   std::vector<std::pair<ShapeKey, ShapeStat>> v(shape_stats().begin(), shape_stats().end());
   std::sort(v.begin(), v.end(), [](const auto &a, const auto &b) { return a.second.ms > b.second.ms; });
   double tot = 0.0;
@@ -488,7 +529,6 @@ struct Engine {
   const thc_opts &o;
   CallStats cs;
   // device arrays for rank / disc / sweeps of the current batch (per job x site)
-  DevBuf rk, dw, sw, nl;
   std::vector<int> h_rank;
   std::vector<double> h_disc;
   std::vector<int> h_sw;
@@ -510,8 +550,18 @@ struct Engine {
   // launchers of the timed kernel classes, with their algorithmic flops and bytes
   void gemm(int nb, int mode, const double *A, int64_t sA, int lda, const double *B, int64_t sB, int ldb, double *C,
             int64_t sC, int ldc, int M, int N, int K, double alpha = 1.0, double beta = 0.0, int prec = GEMM_F64) {
+    // flops of the upper-triangle mode: the tiles on or above the diagonal
+    // (64 x 64 tiles for FP64, the only precision that mode runs in)
+    double fl = 2.0 * M * N * (double)K * nb;
+    if (mode & GEMM_UPPER) {
+      const double tm = std::ceil(M / 64.0), tn = std::ceil(N / 64.0);
+      double run = 0.0;
+      for (int a = 0; a < (int)tm; ++a)
+        for (int b = 0; b < (int)tn; ++b) run += (a * 64 < b * 64 + 64) ? 1.0 : 0.0;
+      fl *= run / (tm * tn);
+    }
     const double cbytes = (mode & GEMM_UPPER) ? 0.5 * M * (double)N : (double)M * N;
-    timed(THC_K_GEMM, 2.0 * M * N * (double)K * nb,
+    timed(THC_K_GEMM, fl,
           8.0 * nb * ((double)M * K + (double)K * N + cbytes * (beta != 0.0 ? 2.0 : 1.0)), ShapeKey{THC_K_GEMM, nb, M, N, K, mode + (beta != 0.0 ? 16 : 0) + 32 * prec},
           [&] { launch_gemm(st, nb, mode, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta, prec); });
   }
@@ -657,19 +707,64 @@ struct Engine {
 
   // Run the compression of nb jobs (same plan).  Output slots in jobs[].out.
   // nrc: the first nrc jobs get right-canonical outputs (all when negative)
-  void compress(const Plan &P, const std::vector<CJob> &hjobs, int D, int nrc = -1) {
-    const int nb = (int)hjobs.size();
-    if (nb == 0) return;
-    const int n = P.n;
-    static const char *trace_path = getenv("THCK_TRACE");
-    c->ws.ensure((size_t)P.per_job * nb * sizeof(double));
-    rk.ensure((size_t)nb * n * sizeof(int));
-    dw.ensure((size_t)nb * n * sizeof(double));
-    sw.ensure((size_t)nb * n * sizeof(int) + sizeof(double));  // cleared as whole doubles
-    nl.ensure((size_t)nb * sizeof(int));
+  // Second level of the Gram route for the jobs selected by jac, whose kept
+  // eigenvalues reached the noise floor gram_floor(m) * lambda_1 (exact or
+  // near-zero singular values that the first level cannot tell apart).
+  // Q1 = the r1 resolved eigenvectors (before re-orthonormalisation), then
+  // Y2 = Y - Q1 Q1^T Y carries the unresolved part at its own scale: the
+  // eigenvectors of G2 = Y2 Y2^T resolve singular values down to
+  // ~sqrt(m eps) ||Y2|| (about (m eps) s_1 in all), and the kept basis is
+  // [Q1 | leading kk - r1 eigenvectors of G2], orthonormalised by the
+  // Householder LQ; C = Q^T Y and the cutoff as on the first level.  The
+  // job's flag is recorded in flag[job] (the sweep-count array).
+  void gram_level2(const Plan &P, int j, int m, int nc, int kk, const int *jac, int *flag, int nb) {
     double *W = c->ws.as<double>();
     const int64_t S = P.per_job;
-    CJob *dj = upload_jobs(hjobs);
+    double *Mb = W + P.oM, *Yb = W + P.oY, *Wb = W + P.oW, *Zb = W + P.oZ, *Cb = W + P.oC, *Lz = W + P.oLz,
+           *Qz = W + P.oQz, *Tf = W + P.oTf, *Ub = W + P.oU, *Gb = W + P.oG, *Db = W + P.oDet, *Zm = W + P.oZm,
+           *Lam = W + P.oLam, *Scr = W + P.oScr, *To = W + P.oTo;
+    double *D2 = W + P.oDet2, *E2 = D2 + P.sv, *T2 = D2 + 2 * P.sv;
+    int *r1 = c->r1.as<int>();
+    int *rk_d = c->rk.as<int>();
+    double *dw_d = c->dw.as<double>();
+    const ShapeKey key{THC_K_SVD_FALLBACK, nb, m, nc, kk, 1};
+    auto step = [&](auto &&f) { timed(THC_K_SVD_FALLBACK, 0.0, 0.0, key, f); };
+    int rc = 0;
+    step([&] { launch_deflate_prep(st, nb, Lam, S, kk, gram_floor(m), Zb, S, m, Wb, S, r1, jac, flag); });
+    // Tm = Q1^T Y (kk x nc); Y2 = Y - Q1 Tm
+    step([&] { launch_gemm(st, nb, GEMM_TA, Wb, S, kk, Mb, S, nc, Cb, S, nc, kk, nc, m, 1.0, 0.0, GEMM_F64, jac); });
+    step([&] { launch_copy(st, nb, Mb, S, Yb, S, (int64_t)m * nc, jac); });
+    step([&] { launch_gemm(st, nb, 0, Wb, S, kk, Cb, S, nc, Yb, S, nc, m, nc, kk, -1.0, 1.0, GEMM_F64, jac); });
+    // eigenpairs of G2 = Y2 Y2^T
+    step([&] { launch_gemm(st, nb, GEMM_TB | GEMM_UPPER, Yb, S, nc, Yb, S, nc, Gb, S, m, m, m, nc, 1.0, 0.0, GEMM_F64, jac); });
+    step([&] { rc = launch_sytrd(st, nb, Gb, S, m, D2, E2, T2, S, jac); });
+    if (rc != 0) raise(THC_EINVAL, "site matrix too tall for sytrd");
+    step([&] { rc = launch_tri_eig(st, nb, D2, E2, S, m, kk, Zm, S, Lam, S, Scr, S, nullptr, jac); });
+    if (rc != 0) raise(THC_EINVAL, "site matrix too tall for the tridiagonal eigensolver");
+    step([&] { rc = launch_ormtr(st, nb, Gb, S, m, T2, S, Zm, S, kk, Zb, S, true, To, S, jac); });
+    if (rc != 0) raise(THC_EINVAL, "ormtr size");
+    // basis [Q1 | Z2], orthonormalised; C = Q^T Y; cutoff, U
+    step([&] { launch_merge_basis(st, nb, Wb, S, Zb, S, m, kk, r1, jac, Zm, S); });
+    step([&] { rc = launch_lq(st, nb, Zm, S, kk, m, Lz, S, Qz, S, Tf, S, true, 0, 0, jac); });
+    if (rc != 0) raise(THC_EINVAL, "site matrix too wide for the LQ kernel");
+    step([&] { launch_gemm(st, nb, GEMM_TA, Qz, S, kk, Mb, S, nc, Cb, S, nc, kk, nc, m, 1.0, 0.0, GEMM_F64, jac); });
+    step([&] {
+      launch_svd_finish2(st, nb, Qz, S, m, kk, Cb, S, nc, cutoff(), Db, S, Ub, S, rk_d + (size_t)j * nb,
+                         dw_d + (size_t)j * nb, true, jac);
+    });
+  }
+
+  // Enqueue every launch of one compression batch (nb jobs of plan P, the
+  // first nr of which get right-canonical outputs); returns the launch count.
+  int64_t enqueue_batch(const Plan &P, CJob *dj, int nb, int nr) {
+    const int n = P.n;
+    double *W = c->ws.as<double>();
+    const int64_t S = P.per_job;
+    int *rk_d = c->rk.as<int>();
+    double *dw_d = c->dw.as<double>();
+    int *sw_d = c->sw.as<int>();
+    int *jf_d = c->jf.as<int>();
+    int *nl_d = c->nl.as<int>();
     double *Bb = W + P.oB, *Tb = W + P.oT, *Lb = W + P.oL, *Qs = W + P.oQs, *Mb = W + P.oM, *Yb = W + P.oY,
            *Wb = W + P.oW, *Zb = W + P.oZ, *Cb = W + P.oC, *Lz = W + P.oLz, *Qz = W + P.oQz, *Tf = W + P.oTf,
            *Sb = W + P.oS, *Ub = W + P.oU;
@@ -713,74 +808,184 @@ struct Engine {
         launches += 2;
       }
     }
-    int *rk_d = rk.as<int>();
-    double *dw_d = dw.as<double>();
-    int *sw_d = sw.as<int>();
     // ---- left -> right SVD sweep ----
     double *Gb = W + P.oG, *Db = W + P.oDet, *Eb = Db + P.sv, *Taub = Db + 2 * P.sv, *Zm = W + P.oZm,
            *Lam = W + P.oLam, *Scr = W + P.oScr;
     const bool jacobi = (o.flags & THC_FLAG_SVD_JACOBI) != 0;
-    for (int j = 0; j + 1 < n && !jacobi; ++j) {
-      const int m = 2 * P.k[j], nc = P.c[j + 1], kk = P.k[j + 1];
-      // Gram G = Y Y^T, Y = M_j (m x nc)
-      // (the tridiagonalisation reads the upper triangle only)
-      gemm(nb, GEMM_TB | GEMM_UPPER, Mb, S, nc, Mb, S, nc, Gb, S, m, m, m, nc);
-      if (sytrd(nb, Gb, S, m, Db, Eb, Taub, S) != 0) raise(THC_EINVAL, "site matrix too tall for sytrd");
-      int *nl_d = nl.as<int>();
-      if (tri_eig(nb, Db, Eb, S, m, kk, Zm, S, Lam, S, Scr, S, nl_d) != 0)
-        raise(THC_EINVAL, "site matrix too tall for the tridiagonal eigensolver");
-      // eigenvectors as the columns of Z (m x kk)
-      if (ormtr(nb, Gb, S, m, Taub, S, Zm, S, kk, Zb, S, true, W + P.oTo, S) != 0) raise(THC_EINVAL, "ormtr size");
-      // orthonormal columns spanning the top-kk eigenvectors, Qz (m x kk).
-      // Inverse iteration returns them orthonormal to rounding except where
-      // the eigensolver flags the job (completions below its noise floor, a
-      // cluster split at its member cap): every job takes one Newton-Schulz
-      // step Qz = Z (3I - Z^T Z) / 2 (G in Lz), and the flagged jobs the
-      // Householder LQ of Z^T (given transposed; Qz holds Q^T)
-      launch_copy(st, nb, Zb, S, Qz, S, (int64_t)m * kk);
-      gemm(nb, GEMM_TA, Zb, S, kk, Zb, S, kk, Lz, S, kk, kk, kk, m);
-      gemm(nb, 0, Zb, S, kk, Lz, S, kk, Qz, S, kk, m, kk, kk, -0.5, 1.5);
-      if (lq(nb, Zb, S, kk, m, Lz, S, Qz, S, Tf, S, true, 0, 0, nl_d) != 0)
-        raise(THC_EINVAL, "site matrix too wide for the LQ kernel");
-      // C = Q (kk x m) * M (m x nc)
-      gemm(nb, GEMM_TA, Qz, S, kk, Mb, S, nc, Cb, S, nc, kk, nc, m);
-      launch_svd_finish2(st, nb, Qz, S, m, kk, Cb, S, nc, cutoff(), Db, S, Ub, S, rk_d + (size_t)j * nb,
-                         dw_d + (size_t)j * nb, true);
-      launch_scatter(st, nb, dj, P.out.off[j], Ub, S, (int64_t)m * kk);
-      // M_{j+1} = C (kk x c_{j+1}) * Q_{j+1} (Q_{j+1} stored transposed)
-      gemm(nb, GEMM_TB, Cb, S, nc, Qs + P.qs_off[j + 1], S, nc, Mb, S, 2 * P.c[j + 2], kk, 2 * P.c[j + 2], nc, 1.0,
-           0.0, cprec);
-      launches += 13;
-    }
-    // no sweeps without Jacobi: clear the counts with a fill kernel (not a
-    // memset node, should the caller capture the stream into a graph)
-    if (!jacobi) launch_fill(st, 1, reinterpret_cast<double *>(sw_d), 0, ((int64_t)nb * n + 1) / 2, 0.0);
-    for (int j = 0; j + 1 < n && jacobi; ++j) {
-      const int m = 2 * P.k[j], nc = P.c[j + 1], kk = P.k[j + 1];
-      launch_copy(st, nb, Mb, S, Yb, S, (int64_t)m * nc);
-      if (launch_jacobi(st, nb, Yb, S, m, nc, Sb, S, sw_d + (size_t)j * nb, max_sweeps()) != 0)
-        raise(THC_EINVAL, "site matrix too wide for the Jacobi kernel (bond > 1024)");
-      launch_svd_select(st, nb, Yb, S, m, nc, Sb, S, kk, cutoff(), Wb, S, rk_d + (size_t)j * nb,
-                        dw_d + (size_t)j * nb, nullptr, 0);
+    // sweep counts start at zero: the Gram route leaves them there except
+    // for the jobs it hands to Jacobi (a fill kernel, not a memset node,
+    // should the caller capture the stream into a graph)
+    launch_fill(st, 1, reinterpret_cast<double *>(sw_d), 0, ((int64_t)nb * n + 1) / 2, 0.0);
+    // One-sided Jacobi SVD of Y = M_j (m x nc) for the jobs selected by only
+    // (all when NULL): rows of Y rotated until orthogonal, the kk largest row
+    // norms kept (cutoff applied), right factor W (kk x nc), Q from the LQ
+    // of Z = W M^T, C = Q M.  Writes U (m x kk), C, rank, discarded weight.
+    auto jacobi_svd = [&](int j, int m, int nc, int kk, const int *only) {
+      const int cls = only ? THC_K_SVD_FALLBACK : -1;
+      auto step = [&](int c, double fl, double by, const ShapeKey &key, auto &&f) {
+        if (c >= 0) timed(c, fl, by, key, f);
+        else f();
+      };
+      const ShapeKey key{THC_K_SVD_FALLBACK, nb, m, nc, kk, 0};
+      step(cls, 0.0, 0.0, key, [&] { launch_copy(st, nb, Mb, S, Yb, S, (int64_t)m * nc, only); });
+      int rc = 0;
+      step(cls, 0.0, 0.0, key, [&] { rc = launch_jacobi(st, nb, Yb, S, m, nc, Sb, S, sw_d + (size_t)j * nb, max_sweeps(), only); });
+      if (rc != 0) raise(THC_EINVAL, "site matrix too wide for the Jacobi kernel (bond > 1024)");
+      step(cls, 0.0, 0.0, key, [&] {
+        launch_svd_select(st, nb, Yb, S, m, nc, Sb, S, kk, cutoff(), Wb, S, rk_d + (size_t)j * nb, dw_d + (size_t)j * nb,
+                          nullptr, 0, only);
+      });
       // Z = W (kk x nc) * M^T (nc x m)
-      gemm(nb, GEMM_TB, Wb, S, nc, Mb, S, nc, Zb, S, m, kk, m, nc);
-      if (lq(nb, Zb, S, kk, m, Lz, S, Qz, S, Tf, S) != 0)
-        raise(THC_EINVAL, "site matrix too wide for the LQ kernel");
+      if (only) step(cls, 0.0, 0.0, key, [&] { launch_gemm(st, nb, GEMM_TB, Wb, S, nc, Mb, S, nc, Zb, S, m, kk, m, nc, 1.0, 0.0, GEMM_F64, only); });
+      else gemm(nb, GEMM_TB, Wb, S, nc, Mb, S, nc, Zb, S, m, kk, m, nc);
+      if (only) {
+        step(cls, 0.0, 0.0, key, [&] { rc = launch_lq(st, nb, Zb, S, kk, m, Lz, S, Qz, S, Tf, S, false, 0, 0, only); });
+      } else {
+        rc = lq(nb, Zb, S, kk, m, Lz, S, Qz, S, Tf, S);
+      }
+      if (rc != 0) raise(THC_EINVAL, "site matrix too wide for the LQ kernel");
       // C = Qz (kk x m) * M (m x nc)
-      gemm(nb, 0, Qz, S, m, Mb, S, nc, Cb, S, nc, kk, nc, m);
-      launch_svd_finish(st, nb, Qz, S, m, kk, rk_d + (size_t)j * nb, Ub, S, Cb, S, nc);
+      if (only) step(cls, 0.0, 0.0, key, [&] { launch_gemm(st, nb, 0, Qz, S, m, Mb, S, nc, Cb, S, nc, kk, nc, m, 1.0, 0.0, GEMM_F64, only); });
+      else gemm(nb, 0, Qz, S, m, Mb, S, nc, Cb, S, nc, kk, nc, m);
+      step(cls, 0.0, 0.0, key, [&] { launch_svd_finish(st, nb, Qz, S, m, kk, rk_d + (size_t)j * nb, Ub, S, Cb, S, nc, only); });
+    };
+    for (int j = 0; j + 1 < n; ++j) {
+      const int m = 2 * P.k[j], nc = P.c[j + 1], kk = P.k[j + 1];
+      if (jacobi) {
+        jacobi_svd(j, m, nc, kk, nullptr);
+        launches += 7;
+      } else {
+        // Gram G = Y Y^T, Y = M_j (m x nc)
+        // (the tridiagonalisation reads the upper triangle only)
+        gemm(nb, GEMM_TB | GEMM_UPPER, Mb, S, nc, Mb, S, nc, Gb, S, m, m, m, nc);
+        if (sytrd(nb, Gb, S, m, Db, Eb, Taub, S) != 0) raise(THC_EINVAL, "site matrix too tall for sytrd");
+        if (tri_eig(nb, Db, Eb, S, m, kk, Zm, S, Lam, S, Scr, S, nl_d) != 0)
+          raise(THC_EINVAL, "site matrix too tall for the tridiagonal eigensolver");
+        // eigenvectors as the columns of Z (m x kk)
+        if (ormtr(nb, Gb, S, m, Taub, S, Zm, S, kk, Zb, S, true, W + P.oTo, S) != 0) raise(THC_EINVAL, "ormtr size");
+        // orthonormal columns spanning the top-kk eigenvectors, Qz (m x kk).
+        // Inverse iteration returns them orthonormal to rounding except where
+        // the eigensolver flags the job (completions below its noise floor, a
+        // cluster split at its member cap) or Z^T Z is off the identity by
+        // more than one Newton-Schulz step repairs: every job takes one step
+        // Qz = Z (3I - Z^T Z) / 2 (Z^T Z in Lz), the flagged jobs the
+        // Householder LQ of Z^T (given transposed; Qz holds Q^T).  Jobs whose
+        // kept eigenvalues reach the noise floor gram_floor(m) * lambda_1 are
+        // redone by the second Gram level below.
+        launch_copy(st, nb, Zb, S, Qz, S, (int64_t)m * kk);
+        gemm(nb, GEMM_TA, Zb, S, kk, Zb, S, kk, Lz, S, kk, kk, kk, m);
+        launch_svd_flags(st, nb, Lam, S, kk, gram_floor(m), Lz, S, nl_d, jf_d);
+        gemm(nb, 0, Zb, S, kk, Lz, S, kk, Qz, S, kk, m, kk, kk, -0.5, 1.5);
+        if (lq(nb, Zb, S, kk, m, Lz, S, Qz, S, Tf, S, true, 0, 0, nl_d) != 0)
+          raise(THC_EINVAL, "site matrix too wide for the LQ kernel");
+        // C = Q (kk x m) * M (m x nc)
+        gemm(nb, GEMM_TA, Qz, S, kk, Mb, S, nc, Cb, S, nc, kk, nc, m);
+        launch_svd_finish2(st, nb, Qz, S, m, kk, Cb, S, nc, cutoff(), Db, S, Ub, S, rk_d + (size_t)j * nb,
+                           dw_d + (size_t)j * nb, true);
+        // the flagged jobs: a second Gram level on the deflated matrix
+        // (overwrites their U, C, rank, weight)
+        gram_level2(P, j, m, nc, kk, jf_d, sw_d + (size_t)j * nb, nb);
+        launches += 30;
+      }
       launch_scatter(st, nb, dj, P.out.off[j], Ub, S, (int64_t)m * kk);
       // M_{j+1} = C (kk x c_{j+1}) * Q_{j+1} (Q_{j+1} stored transposed)
       gemm(nb, GEMM_TB, Cb, S, nc, Qs + P.qs_off[j + 1], S, nc, Mb, S, 2 * P.c[j + 2], kk, 2 * P.c[j + 2], nc, 1.0,
            0.0, cprec);
-      launches += 9;
+      launches += 2;
     }
     // last site
     launch_scatter(st, nb, dj, P.out.off[n - 1], Mb, S, (int64_t)P.k[n - 1] * 2);
     ++launches;
     // outputs in right-canonical form (inputs of later structured sweeps)
-    const int nr = (nrc < 0 || nrc > nb) ? nb : nrc;
     if (nr > 0) launches += recanon(P, dj, nr);
+    return launches;
+  }
+
+  // Graph of a batch: plan signature, batch size, canonical-output count and
+  // the options that change the launch sequence.
+  std::string graph_key(const Plan &P, int nb, int nr) const {
+    std::string k;
+    auto put = [&](int64_t v) { k += std::to_string(v); k += ','; };
+    put(P.kind); put(P.mode); put(nb); put(nr); put(cprec); put((int64_t)(o.flags & THC_FLAG_SVD_JACOBI));
+    put(o.max_sweeps);
+    k += std::to_string(cutoff());
+    k += '|';
+    for (int v : P.pa.b) put(v);
+    for (int64_t v : P.pa.off) put(v);
+    k += '|';
+    for (int v : P.pb.b) put(v);
+    for (int64_t v : P.pb.off) put(v);
+    k += '|';
+    for (int v : P.k) put(v);
+    return k;
+  }
+
+  // Run the compression of nb jobs (same plan).  Output slots in jobs[].out.
+  // nrc: the first nrc jobs get right-canonical outputs (all when negative).
+  // With THC_FLAG_GRAPHS (and kernel timing off) the launch sequence of a
+  // batch is captured into a HIP graph the second time its signature
+  // occurs and replayed from then on; the jobs then travel through a
+  // fixed device buffer, copied before each launch.
+  void compress(const Plan &P, const std::vector<CJob> &hjobs, int D, int nrc = -1) {
+    const int nb = (int)hjobs.size();
+    if (nb == 0) return;
+    const int n = P.n;
+    static const char *trace_path = getenv("THCK_TRACE");
+    const void *ws_before = c->ws.p;
+    c->ws.ensure((size_t)P.per_job * nb * sizeof(double));
+    if (c->ws.p != ws_before) c->drop_graphs();  // captured graphs point into the old workspace
+    c->ensure_batch_arrays(std::max(nb, 512));
+    const int nr = (nrc < 0 || nrc > nb) ? nb : nrc;
+    const bool graphs = (o.flags & THC_FLAG_GRAPHS) != 0 && !timing && nb <= 512;
+    int64_t launches = 0;
+    if (!graphs) {
+      CJob *dj = upload_jobs(hjobs);
+      launches = enqueue_batch(P, dj, nb, nr);
+    } else {
+      CJob *dj = c->gjobs.as<CJob>();
+      HIPCHK(hipMemcpyAsync(dj, hjobs.data(), nb * sizeof(CJob), hipMemcpyHostToDevice, st));
+      const std::string key = graph_key(P, nb, nr);
+      auto it = c->graphs.find(key);
+      if (it != c->graphs.end()) {
+        HIPCHK(hipGraphLaunch(it->second.exec, st));
+        launches = it->second.launches;
+        ++c->graph_replays;
+        ++cs.graph_replays;
+      } else if (c->graph_seen[key]++ == 0) {
+        launches = enqueue_batch(P, dj, nb, nr);  // first time: eager (tunes tiles, sets kernel attributes)
+      } else {
+        // capture on the context's own non-blocking stream (the caller's
+        // may be the null stream, which cannot be captured); the graph then
+        // runs on the caller's stream, in order with its other work
+        if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        const hipStream_t caller = st;
+        st = c->cap_stream;
+        HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        hipGraph_t g = nullptr;
+        try {
+          launches = enqueue_batch(P, dj, nb, nr);
+        } catch (...) {
+          (void)hipStreamEndCapture(st, &g);
+          if (g) (void)hipGraphDestroy(g);
+          st = caller;
+          throw;
+        }
+        const hipError_t ec = hipStreamEndCapture(st, &g);
+        st = caller;
+        if (ec != hipSuccess) throw HipError{ec, "hipStreamEndCapture"};
+        hipGraphExec_t ex = nullptr;
+        hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) throw HipError{e, "hipGraphInstantiate"};
+        c->graphs[key] = thc_ctx::GraphRec{ex, launches};
+        HIPCHK(hipGraphLaunch(ex, st));
+        ++c->graph_captures;
+        ++cs.graph_captures;
+      }
+    }
+    int *rk_d = c->rk.as<int>();
+    double *dw_d = c->dw.as<double>();
+    int *sw_d = c->sw.as<int>();
     HIPCHK(hipGetLastError());
     // statistics: read back ranks/disc/sweeps of this batch (async into host arrays after sync at end)
     h_rank.resize((size_t)nb * n);
@@ -792,11 +997,13 @@ struct Engine {
     HIPCHK(hipStreamSynchronize(st));
     if (timing) kt.resolve(cs);
     report_progress(nb);
+    const bool jac_all = (o.flags & THC_FLAG_SVD_JACOBI) != 0;
     for (size_t i = 0; i < (size_t)nb * (n - 1); ++i) {
       cs.disc_max = std::max(cs.disc_max, h_disc[i]);
       cs.max_bond = std::max(cs.max_bond, h_rank[i]);
       cs.sweeps_max = std::max(cs.sweeps_max, h_sw[i]);
       if (h_sw[i] > max_sweeps()) cs.nonconv++;
+      if (!jac_all && h_sw[i] > 0) cs.fallbacks++;  // SVD redone by the second Gram level
     }
     if (trace_path) trace_batch(trace_path, P, hjobs);
     last_ranks.assign(h_rank.begin(), h_rank.begin() + (size_t)nb * (n - 1));
@@ -1166,13 +1373,15 @@ void fill_stats(thc_stats *st, const CallStats &cs) {
   st->max_bond = cs.max_bond;
   st->jacobi_sweeps_max = cs.sweeps_max;
   st->nonconverged = cs.nonconv;
+  st->svd_fallbacks = cs.fallbacks;
+  st->graph_captures = cs.graph_captures;
+  st->graph_replays = cs.graph_replays;
   for (int k = 0; k < THC_NK; ++k) {
     st->kernel_ms[k] = cs.kms[k];
     st->kernel_flops[k] = cs.kflops[k];
     st->kernel_launches[k] = cs.kn[k];
     st->kernel_bytes[k] = cs.kbytes[k];
   }
-  st->reserved = 0;
 }
 
 thc_opts norm_opts(const thc_opts *o, int *D) {
@@ -1566,7 +1775,7 @@ struct thc_krylov {
   std::vector<std::vector<int64_t>> vo, wo;      // offsets
   std::vector<int> vc, wc;                       // right-canonical flags
   std::vector<double> Mm, S, alpha, beta;        // host mirrors, (K+1)^2
-  DevBuf dM, dS, dA, dB, dOutG, dOutT, dInfo;
+  DevBuf dM, dS, dA, dB, dOutG, dOutT, dInfo, dX;
 };
 
 namespace {
@@ -1748,6 +1957,9 @@ thc_status krylov_step(thc_krylov *k, double *ritz_gen, double *ritz_tri, double
       st->max_bond = std::max(s1.max_bond, s2.max_bond);
       st->jacobi_sweeps_max = std::max(s1.jacobi_sweeps_max, s2.jacobi_sweeps_max);
       st->nonconverged = s1.nonconverged + s2.nonconverged;
+      st->svd_fallbacks = s1.svd_fallbacks + s2.svd_fallbacks;
+      st->graph_captures = s1.graph_captures + s2.graph_captures;
+      st->graph_replays = s1.graph_replays + s2.graph_replays;
       for (int q = 0; q < THC_NK; ++q) {
         st->kernel_ms[q] = s1.kernel_ms[q] + s2.kernel_ms[q];
         st->kernel_flops[q] = s1.kernel_flops[q] + s2.kernel_flops[q];
@@ -1755,6 +1967,93 @@ thc_status krylov_step(thc_krylov *k, double *ritz_gen, double *ritz_tri, double
         st->kernel_bytes[q] = s1.kernel_bytes[q] + s2.kernel_bytes[q];
       }
     }
+  });
+}
+
+}  // extern "C"
+
+// Coefficients x (host, m = steps taken) of the a-th Ritz vector over
+// v_0..v_{m-1}, computed on the device from the M and S mirrors.
+namespace {
+std::vector<double> ritz_coefficients(thc_krylov *k, int a, hipStream_t st) {
+  const int m = k->i, R = k->K + 1;
+  if (m < 1) raise(THC_EINVAL, "no Krylov step taken yet");
+  if (a < 0 || a >= m) raise(THC_EINVAL, "Ritz index out of range");
+  k->dX.ensure(R * sizeof(double));
+  HIPCHK(hipMemcpyAsync(k->dM.p, k->Mm.data(), R * R * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(k->dS.p, k->S.data(), R * R * sizeof(double), hipMemcpyHostToDevice, st));
+  launch_ritz_vector(st, k->dM.as<double>(), k->dS.as<double>(), m, R, a, k->dX.as<double>(), k->dInfo.as<int>());
+  HIPCHK(hipGetLastError());
+  std::vector<double> x(m);
+  int info = 0;
+  HIPCHK(hipMemcpyAsync(x.data(), k->dX.p, m * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&info, k->dInfo.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (info != 0) raise(THC_EINVAL, "Ritz index beyond the basis directions kept by the canonical orthogonalisation");
+  for (double v : x)
+    if (!std::isfinite(v)) raise(THC_ENONFINITE, "non-finite Ritz vector coefficient");
+  return x;
+}
+}  // namespace
+
+extern "C" {
+
+thc_status krylov_ritz_vector(thc_krylov *k, int32_t a, thc_mps *out, void *hip_stream) {
+  if (!k || !out) return fail(THC_EINVAL, "NULL argument");
+  return run_guarded([&] {
+    hipStream_t st = (hipStream_t)hip_stream;
+    std::vector<double> x = ritz_coefficients(k, a, st);
+    std::vector<thc_mps> views;
+    for (int i = 0; i < k->i; ++i) views.push_back(view(k, false, i));
+    std::vector<const thc_mps *> ptrs;
+    for (auto &v : views) ptrs.push_back(&v);
+    thc_status r = mps_sum_compress(k->ctx, (int)x.size(), x.data(), ptrs.data(), out, &k->o, nullptr, hip_stream);
+    if (r != THC_OK) raise(r, thc_last_error());
+  });
+}
+
+thc_status krylov_restart(thc_krylov *k, int32_t a, void *hip_stream) {
+  if (!k) return fail(THC_EINVAL, "state is NULL");
+  return run_guarded([&] {
+    hipStream_t st = (hipStream_t)hip_stream;
+    std::vector<double> x = ritz_coefficients(k, a, st);
+    // the Ritz vector goes to slot K, which is never one of the terms (m <= K)
+    const int m = k->i, K = k->K;
+    std::vector<thc_mps> views;
+    for (int i = 0; i < m; ++i) views.push_back(view(k, false, i));
+    std::vector<const thc_mps *> ptrs;
+    for (auto &v : views) ptrs.push_back(&v);
+    thc_mps tmp = view(k, false, K);
+    thc_status r = mps_sum_compress(k->ctx, m, x.data(), ptrs.data(), &tmp, &k->o, nullptr, hip_stream);
+    if (r != THC_OK) raise(r, thc_last_error());
+    k->vc[K] = tmp.canonical;
+    int64_t used = 0;
+    for (int j = 0; j < k->n; ++j) used = std::max(used, k->vo[K][j] + (int64_t)k->vb[K][j] * 2 * k->vb[K][j + 1]);
+    HIPCHK(hipMemcpyAsync(k->vbuf[0]->p, k->vbuf[K]->p, (size_t)used * sizeof(double), hipMemcpyDeviceToDevice, st));
+    k->vb[0] = k->vb[K];
+    k->vo[0] = k->vo[K];
+    k->vc[0] = k->vc[K];
+    // normalise (site 0 carries the norm) and reset the basis and matrices
+    thc_mps v0 = view(k, false, 0);
+    double nn = 0.0;
+    r = mps_overlap(k->ctx, &v0, &v0, &nn, hip_stream);
+    if (r != THC_OK) raise(r, thc_last_error());
+    if (!(nn > 0.0) || !std::isfinite(nn)) raise(THC_EINVAL, "Ritz vector has zero or non-finite norm");
+    launch_scale(st, k->vbuf[0]->as<double>() + k->vo[0][0], (int64_t)k->vb[0][0] * 2 * k->vb[0][1],
+                 1.0 / std::sqrt(nn));
+    HIPCHK(hipGetLastError());
+    const int R = K + 1;
+    std::fill(k->Mm.begin(), k->Mm.end(), 0.0);
+    std::fill(k->S.begin(), k->S.end(), 0.0);
+    k->alpha.clear();
+    k->beta.clear();
+    k->i = 0;
+    double s00 = 0.0;
+    v0 = view(k, false, 0);
+    r = mps_overlap(k->ctx, &v0, &v0, &s00, hip_stream);
+    if (r != THC_OK) raise(r, thc_last_error());
+    k->S[0] = s00;
+    (void)R;
   });
 }
 
@@ -1785,6 +2084,207 @@ thc_status krylov_get_matrices(thc_krylov *k, double *Mm, double *S, int32_t *m)
       if (S) S[a * mm + b] = k->S[a * R + b];
     }
   return THC_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Energy and gradient w.r.t. the THC factors (THC-factor fitting, Sec. 2.3;
+// the G-term structure of Sec. 3.1).  With E_pq = sum_s a+_{ps} a_{qs} and
+// N_nu = sum_s a+(chi^nu)_s a(chi^nu)_s, everything follows from the
+// transition one-body matrices G^nu_pq = <psi|E_pq N_nu|psi>:
+//   <psi|N_mu N_nu|psi> = chi^mu^T G^nu chi^mu,  dE/dzeta = that / 2,
+//   dE/dchi_p^k = ((M_k + M_k^T) chi^k)_p,  M_k = sum_nu sym(zeta)_{k nu} G^nu.
+// Kets: n_{nu s'}|psi> = a+(chi^nu)_s' a(chi^nu)_s' |psi> for the 2N pairs
+// (nu, s'), formed exactly by two layer constructions (bond 4 b_j, no
+// compression), and n_{u_i s}|psi> for the 2L kinetic pairs (App. D), of
+// which only the overlap <psi|n|psi> is needed.  g_ij = <psi|a+_i a_j|ket>
+// comes from transfer-matrix chains with the Jordan-Wigner string of
+// a+_i a_j (c+_i Z...Z c_j for i < j, c_j Z...Z c+_i for i > j): a stack
+// of environments opened at every site i is carried to the right through Z
+// and closed at every later site, all kets of a chunk batched per GEMM.
+// ===========================================================================
+namespace {
+
+struct GradPlan {
+  int n = 0;
+  std::vector<int> b, B1, B4;         // bra, first-layer and ket bonds
+  std::vector<int64_t> o1, o4, oR;    // site offsets (per ket) of the layer states and right environments
+  int64_t S1 = 0, S4 = 0, SR = 0;     // per-ket strides
+  int64_t blkO = 0, blkF = 0;         // largest environment block (b x B) and F block (b x 2B)
+};
+
+GradPlan make_grad_plan(const thc_mps *psi) {
+  GradPlan G;
+  const int n = psi->n_sites;
+  G.n = n;
+  G.b.assign(psi->bonds, psi->bonds + n + 1);
+  G.B1.assign(n + 1, 1);
+  G.B4.assign(n + 1, 1);
+  for (int j = 1; j < n; ++j) {
+    G.B1[j] = 2 * G.b[j];
+    G.B4[j] = 4 * G.b[j];
+  }
+  G.o1.assign(n, 0);
+  G.o4.assign(n, 0);
+  G.oR.assign(n + 1, 0);
+  for (int j = 0; j < n; ++j) {
+    G.o1[j] = G.S1;
+    G.S1 += (int64_t)G.B1[j] * 2 * G.B1[j + 1];
+    G.o4[j] = G.S4;
+    G.S4 += (int64_t)G.B4[j] * 2 * G.B4[j + 1];
+  }
+  for (int j = 0; j <= n; ++j) {
+    G.oR[j] = G.SR;
+    G.SR += (int64_t)G.b[j] * G.B4[j];
+    G.blkO = std::max(G.blkO, (int64_t)G.b[j] * G.B4[j]);
+    if (j < n) G.blkF = std::max(G.blkF, (int64_t)G.b[j] * 2 * G.B4[j + 1]);
+  }
+  return G;
+}
+
+}  // namespace
+
+extern "C" {
+
+thc_status thc_energy_gradient(thc_ctx *ctx, const thc_mps *psi, int32_t prec, double *energy, double *dchi,
+                               double *dzeta, void *hip_stream) {
+  if (!ctx) return fail(THC_EINVAL, "ctx is NULL");
+  return run_guarded([&] {
+    check_mps(psi, ctx->n);
+    if (prec != THC_PREC_F64 && prec != THC_PREC_F32) raise(THC_EINVAL, "gradient precision must be F64 or F32");
+    if (!energy && !dchi && !dzeta) raise(THC_EINVAL, "no output requested");
+    const int gp = (prec == THC_PREC_F32) ? GEMM_F32 : GEMM_F64;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int L = ctx->L, N = ctx->N, n = ctx->n;
+    const GradPlan P = make_grad_plan(psi);
+    const int nkx = 2 * N, nkt = 2 * L, nk = nkx + nkt;
+    // per-ket device memory: layer states, right environments, E and F_E,
+    // W, two stacks of open environments and the stack product
+    const int64_t per_ket = P.S1 + P.S4 + P.SR + 2 * P.blkO + 2 * P.blkF + 2 * (2 * n) * P.blkO + (2 * n) * P.blkF;
+    const double budget = 48.0 * (1ull << 30);
+    int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(nk, (int64_t)(budget / (8.0 * per_ket))));
+    DevBuf ws, jobs_d, gbuf, ovl, fin, lamd, chid, zetad;
+    ws.ensure((size_t)per_ket * chunk * sizeof(double));
+    gbuf.ensure((size_t)std::max(nkx, 1) * n * n * sizeof(double));
+    ovl.ensure((size_t)nk * sizeof(double));
+    launch_fill(st, 1, gbuf.as<double>(), 0, (int64_t)std::max(nkx, 1) * n * n, 0.0);
+    double *W0 = ws.as<double>();
+    double *Phi1 = W0, *Phi4 = Phi1 + P.S1 * chunk, *Renv = Phi4 + P.S4 * chunk, *Eb = Renv + P.SR * chunk,
+           *E2 = Eb + P.blkO * chunk, *FE = E2 + P.blkO * chunk, *Wb = FE + P.blkF * chunk,
+           *Ost = Wb + P.blkF * chunk, *Ost2 = Ost + (2 * n) * P.blkO * chunk, *Fst = Ost2 + (2 * n) * P.blkO * chunk;
+    const int64_t sO = (2 * n) * P.blkO, sF = (2 * n) * P.blkF;
+    DevBuf AZ;
+    int64_t maxA = 1;
+    for (int j = 0; j < n; ++j) maxA = std::max(maxA, (int64_t)P.b[j] * 2 * P.b[j + 1]);
+    AZ.ensure((size_t)maxA * sizeof(double));
+    jobs_d.ensure((size_t)chunk * sizeof(CJob));
+    std::vector<CJob> hj(chunk);
+    for (int k0 = 0; k0 < nk; k0 += chunk) {
+      const int nc = std::min(chunk, nk - k0);
+      // ---- kets: two layer constructions per ket ----
+      for (int layer = 0; layer < 2; ++layer) {
+        for (int q = 0; q < nc; ++q) {
+          const int k = k0 + q;
+          const int row = (k < nkx) ? k : 2 * N + (k - nkx);  // coefficient rows: 2 nu + s', then 2N + 2i + s
+          CJob jb{};
+          jb.kind = 0;
+          jb.in_a = (layer == 0) ? psi->data : Phi1 + (int64_t)q * P.S1;
+          jb.y = ctx->coef_ptr(row);
+          jb.dag = layer;
+          jb.ca = 1.0;
+          hj[q] = jb;
+        }
+        HIPCHK(hipMemcpyAsync(jobs_d.p, hj.data(), nc * sizeof(CJob), hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));  // the host job array is reused by the next layer
+        for (int j = 0; j < n; ++j) {
+          if (layer == 0)
+            launch_construct(st, jobs_d.as<CJob>(), nc, j, n, psi->offsets[j], 0, P.b[j], P.b[j + 1], 0, 0,
+                             Phi1 + P.o1[j], P.S1, P.B1[j], P.B1[j + 1]);
+          else
+            launch_construct(st, jobs_d.as<CJob>(), nc, j, n, P.o1[j], 0, P.B1[j], P.B1[j + 1], 0, 0,
+                             Phi4 + P.o4[j], P.S4, P.B4[j], P.B4[j + 1]);
+        }
+      }
+      // ---- right environments R_j (b_j x B_j), R_n = [1] ----
+      launch_fill(st, nc, Renv + P.oR[n], P.SR, 1, 1.0);
+      for (int j = n - 1; j >= 1; --j) {
+        const double *Aj = psi->data + psi->offsets[j];
+        // W = A_j (2 b_j x b_{j+1}) R_{j+1} (b_{j+1} x B_{j+1})
+        launch_gemm(st, nc, 0, Aj, 0, P.b[j + 1], Renv + P.oR[j + 1], P.SR, P.B4[j + 1], Wb, P.blkF, P.B4[j + 1],
+                    2 * P.b[j], P.B4[j + 1], P.b[j + 1], 1.0, 0.0, gp);
+        // R_j = W (b_j x 2 B_{j+1}) B_j^T (ket site j viewed B_j x 2 B_{j+1})
+        launch_gemm(st, nc, GEMM_TB, Wb, P.blkF, 2 * P.B4[j + 1], Phi4 + P.o4[j], P.S4, 2 * P.B4[j + 1],
+                    Renv + P.oR[j], P.SR, P.B4[j], P.b[j], P.B4[j], 2 * P.B4[j + 1], 1.0, 0.0, gp);
+      }
+      // ---- left sweep: plain environment, open stack, closings ----
+      const int nx = std::max(0, std::min(nc, nkx - k0));  // kets of this chunk that need g
+      launch_fill(st, nc, Eb, P.blkO, 1, 1.0);
+      double *Ocur = Ost, *Onext = Ost2;
+      for (int j = 0; j < n; ++j) {
+        const int bl = P.b[j], br = P.b[j + 1], Bl = P.B4[j], Br = P.B4[j + 1];
+        const double *Aj = psi->data + psi->offsets[j];
+        const double *Kj = Phi4 + P.o4[j];
+        // F_E = E_j (bl x Bl) B_j (Bl x 2 Br)
+        launch_gemm(st, nc, 0, Eb, P.blkO, Bl, Kj, P.S4, 2 * Br, FE, P.blkF, 2 * Br, bl, 2 * Br, Bl, 1.0, 0.0, gp);
+        if (nx > 0) {
+          // W = A_j (2 bl x br) R_{j+1} (br x Br)
+          launch_gemm(st, nx, 0, Aj, 0, br, Renv + P.oR[j + 1], P.SR, Br, Wb, P.blkF, Br, 2 * bl, Br, br, 1.0, 0.0,
+                      gp);
+          launch_rdm_close(st, 1, nx, FE, P.blkF, 0, Wb, P.blkF, bl, Br, gbuf.as<double>() + (int64_t)k0 * n * n, n, j,
+                           1);
+          if (j > 0) {
+            // stack of 2j open environments (bl x Bl each) times the ket site
+            launch_gemm(st, nx, 0, Ocur, sO, Bl, Kj, P.S4, 2 * Br, Fst, sF, 2 * Br, 2 * j * bl, 2 * Br, Bl, 1.0, 0.0,
+                        gp);
+            launch_rdm_close(st, 2 * j, nx, Fst, sF, (int64_t)bl * 2 * Br, Wb, P.blkF, bl, Br,
+                             gbuf.as<double>() + (int64_t)k0 * n * n, n, j, 0);
+          }
+          if (j + 1 < n) {
+            // carry the open environments through Z: O' = A^Z^T F_r
+            launch_negate_odd(st, Aj, AZ.as<double>(), bl, br);
+            for (int r = 0; r < 2 * j; ++r)
+              launch_gemm(st, nx, GEMM_TA, AZ.as<double>(), 0, br, Fst + (int64_t)r * bl * 2 * Br, sF, Br,
+                          Onext + (int64_t)r * br * Br, sO, Br, br, Br, 2 * bl, 1.0, 0.0, gp);
+            // open two more at site j: c+ (bra 1, ket 0) and c (bra 0, ket 1)
+            launch_gemm(st, nx, GEMM_TA, Aj + br, 0, 2 * br, FE, P.blkF, 2 * Br, Onext + (int64_t)(2 * j) * br * Br,
+                        sO, Br, br, Br, bl, 1.0, 0.0, gp);
+            launch_gemm(st, nx, GEMM_TA, Aj, 0, 2 * br, FE + Br, P.blkF, 2 * Br, Onext + (int64_t)(2 * j + 1) * br * Br,
+                        sO, Br, br, Br, bl, 1.0, 0.0, gp);
+            std::swap(Ocur, Onext);
+          }
+        }
+        // E_{j+1} = A_j^T (br x 2 bl) F_E (2 bl x Br)
+        launch_gemm(st, nc, GEMM_TA, Aj, 0, br, FE, P.blkF, Br, E2, P.blkO, Br, br, Br, 2 * bl, 1.0, 0.0, gp);
+        launch_copy(st, nc, E2, P.blkO, Eb, P.blkO, (int64_t)br * Br);
+      }
+      // E_n is 1 x 1: the overlap <psi|ket>
+      launch_copy(st, nc, Eb, P.blkO, ovl.as<double>() + k0, 1, 1);
+      HIPCHK(hipGetLastError());
+    }
+    // ---- final contraction on the device ----
+    std::vector<double> lam(ctx->lam);
+    lamd.ensure((size_t)L * sizeof(double));
+    chid.ensure((size_t)std::max(1, L * N) * sizeof(double));
+    zetad.ensure((size_t)std::max(1, N * N) * sizeof(double));
+    fin.ensure((size_t)(1 + L * N + N * N + N * L * L + L * L + 1) * sizeof(double));
+    HIPCHK(hipMemcpyAsync(lamd.p, lam.data(), L * sizeof(double), hipMemcpyHostToDevice, st));
+    if (N > 0) {
+      HIPCHK(hipMemcpyAsync(chid.p, ctx->chi.data(), (size_t)L * N * sizeof(double), hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(zetad.p, ctx->zeta.data(), (size_t)N * N * sizeof(double), hipMemcpyHostToDevice, st));
+    }
+    double *out_d = fin.as<double>();
+    double *Gw = out_d + 1 + L * N + N * N;
+    launch_grad_final(st, gbuf.as<double>(), n, L, N, chid.as<double>(), zetad.as<double>(), lamd.as<double>(),
+                      ovl.as<double>(), Gw, out_d);
+    HIPCHK(hipGetLastError());
+    std::vector<double> host(1 + L * N + N * N);
+    HIPCHK(hipMemcpyAsync(host.data(), out_d, host.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (energy) *energy = host[0];
+    if (dchi) memcpy(dchi, host.data() + 1, (size_t)L * N * sizeof(double));
+    if (dzeta) memcpy(dzeta, host.data() + 1 + L * N, (size_t)N * N * sizeof(double));
+  });
 }
 
 }  // extern "C"

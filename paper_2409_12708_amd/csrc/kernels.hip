@@ -14,6 +14,11 @@
 //   svd_*       the top-k rows selected, U recovered by a second LQ
 //   overlap     transfer-matrix chain <a|b>
 #include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <tuple>
 #include <stdint.h>
 #include <type_traits>
 
@@ -166,7 +171,8 @@ template <int MODE, int BM, int BN, int PREC>
 __global__ __launch_bounds__(256) void k_gemm_mfma(const double *__restrict__ A, int64_t sA, int lda,
                                                    const double *__restrict__ B, int64_t sB, int ldb,
                                                    double *__restrict__ C, int64_t sC, int ldc, int M, int N,
-                                                   int K, int tiles_m, int tiles_n, double alpha, double beta) {
+                                                   int K, int tiles_m, int tiles_n, double alpha, double beta,
+                                                   const int *__restrict__ only) {
   constexpr bool TB = (MODE & GEMM_TB) != 0, TA = (MODE & GEMM_TA) != 0, UP = (MODE & GEMM_UPPER) != 0;
   constexpr int BK = 16;
   constexpr int WM = BM / 32, WN = BN / 32;  // 16x16 blocks per wave
@@ -191,6 +197,7 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(const double *__restrict__ A,
   const int job = g / T, t = g % T;
   const int m0 = (t / tiles_n) * BM, n0 = (t % tiles_n) * BN;
   if (UP && m0 >= n0 + BN) return;  // tile strictly below the diagonal: not needed
+  if (only != nullptr && only[job] == 0) return;  // job not selected
   A += (int64_t)job * sA;
   B += (int64_t)job * sB;
   C += (int64_t)job * sC;
@@ -646,7 +653,9 @@ static constexpr double JAC_TOL_ABS = 1e-15;
 template <int BS, int NMAX>
 __global__ __launch_bounds__(256) void k_jacobi_rows(double *__restrict__ Yb, int64_t sY, int m, int n,
                                                      double *__restrict__ sb, int64_t ss,
-                                                     int *__restrict__ sweeps_out, int max_sweeps) {
+                                                     int *__restrict__ sweeps_out, int max_sweeps,
+                                                     const int *__restrict__ only) {
+  if (only != nullptr && only[blockIdx.x] == 0) return;  // job not selected
   constexpr int P2 = 2 * BS;
   extern __shared__ double lds[];
   double *R = lds;                 // P2 x P2 rotation
@@ -835,7 +844,9 @@ __global__ __launch_bounds__(256) void k_svd_select(const double *__restrict__ Y
                                                     const double *__restrict__ sb, int64_t ss, int kk,
                                                     double cutoff, double *__restrict__ Wb, int64_t sW,
                                                     int *__restrict__ rank_out, double *__restrict__ disc_out,
-                                                    double *__restrict__ sv_out, int64_t ssv) {
+                                                    double *__restrict__ sv_out, int64_t ssv,
+                                                    const int *__restrict__ only) {
+  if (only != nullptr && only[blockIdx.x] == 0) return;  // job not selected
   __shared__ double sv[2048];
   __shared__ int id[2048];
   __shared__ int s_rank;
@@ -902,8 +913,9 @@ __global__ __launch_bounds__(256) void k_svd_select(const double *__restrict__ Y
 // ---------------------------------------------------------------------------
 __global__ void k_svd_finish(const double *__restrict__ Qb, int64_t sQ, int m, int kk,
                              const int *__restrict__ rank, double *__restrict__ Ub, int64_t sU,
-                             double *__restrict__ Cb, int64_t sC, int n) {
+                             double *__restrict__ Cb, int64_t sC, int n, const int *__restrict__ only) {
   const int job = blockIdx.y;
+  if (only != nullptr && only[job] == 0) return;  // job not selected
   const double *Q = Qb + (int64_t)job * sQ;
   double *U = Ub + (int64_t)job * sU;
   double *Cc = Cb + (int64_t)job * sC;
@@ -922,7 +934,8 @@ __global__ void k_svd_finish(const double *__restrict__ Qb, int64_t sQ, int m, i
 
 // plain batched copy with strides
 __global__ void k_copy(const double *__restrict__ src, int64_t ssrc, double *__restrict__ dst, int64_t sdst,
-                       int64_t count) {
+                       int64_t count, const int *__restrict__ only) {
+  if (only != nullptr && only[blockIdx.y] == 0) return;  // job not selected
   const double *s = src + (int64_t)blockIdx.y * ssrc;
   double *d = dst + (int64_t)blockIdx.y * sdst;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x)
@@ -1066,8 +1079,9 @@ __global__ void k_scale_range(double *__restrict__ p, int64_t count, double c) {
 // Computes the Ritz values of the Lanczos step:
 //   mode 0: eigenvalues of the tridiagonal (alpha, beta);
 //   mode 1: eigenvalues of C H_sym C^T with C S C^T = I (Cholesky of S), or
-//           of X^T H_sym X with X = U_k s_k^{-1/2} when S is not positive
-//           definite enough (canonical orthogonalisation, s > 1e-10).
+//           of X^T H_sym X with X = U_k s_k^{-1/2} when an eigenvalue of S
+//           is at or below 1e-10 (canonical orthogonalisation keeping the
+//           s_k > 1e-10); the entries past the kept count are NaN.
 // ---------------------------------------------------------------------------
 __device__ void jacobi_eig_small(double *A, int m, int lda, double *w) {
   // serial cyclic Jacobi (m tiny), run by one thread
@@ -1108,42 +1122,71 @@ __device__ void jacobi_eig_small(double *A, int m, int lda, double *w) {
   }
 }
 
-__global__ void k_ritz(const double *__restrict__ Mm, const double *__restrict__ S, int m, int ld,
-                       const double *__restrict__ alpha, const double *__restrict__ beta,
-                       double *__restrict__ out_gen, double *__restrict__ out_tri, int *__restrict__ info) {
+// Cyclic Jacobi with eigenvectors on the m x m symmetric A (row stride LD):
+// on return the eigenvalues are on the diagonal of A and V (m x m, columns)
+// holds the eigenvectors.  One thread; m <= RITZ_MAX.
+__device__ void jacobi_eig_vectors(double *A, double *V, int m) {
   constexpr int LD = RITZ_MAX;
-  __shared__ double H[LD * LD], Sc[LD * LD], C[LD * LD], T1[LD * LD], wv[LD];
-  if (threadIdx.x != 0) return;
-  // tridiagonal
   for (int i = 0; i < m; ++i)
-    for (int j = 0; j < m; ++j) T1[i * LD + j] = 0.0;
-  for (int i = 0; i < m; ++i) T1[i * LD + i] = alpha[i];
-  for (int i = 0; i + 1 < m; ++i) { T1[i * LD + i + 1] = beta[i]; T1[(i + 1) * LD + i] = beta[i]; }
-  jacobi_eig_small(T1, m, LD, wv);
-  for (int i = 0; i < m; ++i) out_tri[i] = wv[i];
-  // generalised
-  for (int i = 0; i < m; ++i)
-    for (int j = 0; j < m; ++j) {
-      H[i * LD + j] = 0.5 * (Mm[i * ld + j] + Mm[j * ld + i]);
-      Sc[i * LD + j] = S[i * ld + j];
-    }
-  // Cholesky S = L L^T (in Sc, lower)
-  bool ok = true;
-  for (int j = 0; j < m && ok; ++j) {
-    double d = Sc[j * LD + j];
-    for (int k = 0; k < j; ++k) d -= Sc[j * LD + k] * Sc[j * LD + k];
-    if (!(d > 1e-10)) { ok = false; break; }
-    d = sqrt(d);
-    Sc[j * LD + j] = d;
-    for (int i = j + 1; i < m; ++i) {
-      double v = Sc[i * LD + j];
-      for (int k = 0; k < j; ++k) v -= Sc[i * LD + k] * Sc[j * LD + k];
-      Sc[i * LD + j] = v / d;
-    }
+    for (int j = 0; j < m; ++j) V[i * LD + j] = (i == j) ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) { tot += A[i * LD + j] * A[i * LD + j]; if (i != j) off += A[i * LD + j] * A[i * LD + j]; }
+    if (off <= 1e-30 * tot || off == 0.0) break;
+    for (int p = 0; p < m; ++p)
+      for (int q = p + 1; q < m; ++q) {
+        const double apq = A[p * LD + q];
+        if (apq == 0.0) continue;
+        const double th = (A[q * LD + q] - A[p * LD + p]) / (2.0 * apq);
+        const double t = copysign(1.0, th) / (fabs(th) + sqrt(1.0 + th * th));
+        const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+        for (int k = 0; k < m; ++k) {
+          const double ap = A[p * LD + k], aq = A[q * LD + k];
+          A[p * LD + k] = c * ap - s * aq; A[q * LD + k] = s * ap + c * aq;
+        }
+        for (int k = 0; k < m; ++k) {
+          const double ap = A[k * LD + p], aq = A[k * LD + q];
+          A[k * LD + p] = c * ap - s * aq; A[k * LD + q] = s * ap + c * aq;
+        }
+        for (int k = 0; k < m; ++k) {
+          const double ap = V[k * LD + p], aq = V[k * LD + q];
+          V[k * LD + p] = c * ap - s * aq; V[k * LD + q] = s * ap + c * aq;
+        }
+      }
   }
+}
+
+// The re-orthogonalising transform of the Lanczos basis (eq. reortho):
+// rows c_a of C (mk x m) with C S C^T = I.  S = U diag(s) U^T; when every
+// s exceeds 1e-10, C = L^{-1} with S = L L^T (Cholesky, mk = m); otherwise
+// canonical orthogonalisation keeps the eigenvectors with s > 1e-10:
+// c_k = u_k^T / sqrt(s_k).  Returns mk; ok = Cholesky branch.  Work arrays
+// T1, Sc, U of RITZ_MAX^2.  One thread.
+__device__ int ritz_transform(const double *S, int ld, int m, double *C, double *T1, double *Sc, double *U, bool &ok) {
+  constexpr int LD = RITZ_MAX;
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) T1[i * LD + j] = S[i * ld + j];
+  jacobi_eig_vectors(T1, U, m);
+  ok = true;
+  for (int k = 0; k < m; ++k) ok = ok && (T1[k * LD + k] > 1e-10);
   int mk = m;
   if (ok) {
-    // C = L^{-1} (lower), by forward substitution on the identity
+    // Cholesky S = L L^T (in Sc, lower), then C = L^{-1} by forward
+    // substitution on the identity
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) Sc[i * LD + j] = S[i * ld + j];
+    for (int j = 0; j < m; ++j) {
+      double d = Sc[j * LD + j];
+      for (int k = 0; k < j; ++k) d -= Sc[j * LD + k] * Sc[j * LD + k];
+      d = sqrt(d > 0.0 ? d : 0.0);
+      Sc[j * LD + j] = d;
+      for (int i = j + 1; i < m; ++i) {
+        double v = Sc[i * LD + j];
+        for (int k = 0; k < j; ++k) v -= Sc[i * LD + k] * Sc[j * LD + k];
+        Sc[i * LD + j] = v / d;
+      }
+    }
     for (int col = 0; col < m; ++col)
       for (int i = 0; i < m; ++i) {
         double v = (i == col) ? 1.0 : 0.0;
@@ -1151,50 +1194,24 @@ __global__ void k_ritz(const double *__restrict__ Mm, const double *__restrict__
         C[i * LD + col] = (i < col) ? 0.0 : v / Sc[i * LD + i];
       }
   } else {
-    // canonical orthogonalisation: S = U diag(s) U^T, keep s > 1e-10,
-    // C = diag(s_k^{-1/2}) U_k^T  (rows)
-    for (int i = 0; i < m; ++i)
-      for (int j = 0; j < m; ++j) { T1[i * LD + j] = S[i * ld + j]; C[i * LD + j] = (i == j) ? 1.0 : 0.0; }
-    // Jacobi with eigenvectors
-    for (int sweep = 0; sweep < 100; ++sweep) {
-      double off = 0.0, tot = 0.0;
-      for (int i = 0; i < m; ++i)
-        for (int j = 0; j < m; ++j) { tot += T1[i * LD + j] * T1[i * LD + j]; if (i != j) off += T1[i * LD + j] * T1[i * LD + j]; }
-      if (off <= 1e-30 * tot || off == 0.0) break;
-      for (int p = 0; p < m; ++p)
-        for (int q = p + 1; q < m; ++q) {
-          const double apq = T1[p * LD + q];
-          if (apq == 0.0) continue;
-          const double th = (T1[q * LD + q] - T1[p * LD + p]) / (2.0 * apq);
-          const double t = copysign(1.0, th) / (fabs(th) + sqrt(1.0 + th * th));
-          const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
-          for (int k = 0; k < m; ++k) {
-            const double ap = T1[p * LD + k], aq = T1[q * LD + k];
-            T1[p * LD + k] = c * ap - s * aq; T1[q * LD + k] = s * ap + c * aq;
-          }
-          for (int k = 0; k < m; ++k) {
-            const double ap = T1[k * LD + p], aq = T1[k * LD + q];
-            T1[k * LD + p] = c * ap - s * aq; T1[k * LD + q] = s * ap + c * aq;
-          }
-          for (int k = 0; k < m; ++k) {  // eigenvector columns in C (C <- C J)
-            const double ap = C[k * LD + p], aq = C[k * LD + q];
-            C[k * LD + p] = c * ap - s * aq; C[k * LD + q] = s * ap + c * aq;
-          }
-        }
-    }
-    // rows of the transform: X^T rows = u_k^T / sqrt(s_k) for s_k > 1e-10
     mk = 0;
     for (int k = 0; k < m; ++k) {
       const double sk = T1[k * LD + k];
       if (sk > 1e-10) {
-        for (int i = 0; i < m; ++i) Sc[mk * LD + i] = C[i * LD + k] / sqrt(sk);
+        for (int i = 0; i < m; ++i) C[mk * LD + i] = U[i * LD + k] / sqrt(sk);
         ++mk;
       }
     }
-    for (int r = 0; r < mk; ++r)
-      for (int i = 0; i < m; ++i) C[r * LD + i] = Sc[r * LD + i];
   }
-  // T1 = C H C^T (mk x mk)
+  return mk;
+}
+
+// T1 = C H_sym C^T (mk x mk) with H_sym = (M + M^T)/2; Sc is work.
+__device__ void ritz_projected(const double *Mm, int ld, int m, int mk, const double *C, double *T1, double *H,
+                               double *Sc) {
+  constexpr int LD = RITZ_MAX;
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) H[i * LD + j] = 0.5 * (Mm[i * ld + j] + Mm[j * ld + i]);
   for (int i = 0; i < mk; ++i)
     for (int j = 0; j < m; ++j) {
       double v = 0.0;
@@ -1207,10 +1224,65 @@ __global__ void k_ritz(const double *__restrict__ Mm, const double *__restrict__
       for (int k = 0; k < m; ++k) v += Sc[i * LD + k] * C[j * LD + k];
       T1[i * LD + j] = v;
     }
+}
+
+__global__ void k_ritz(const double *__restrict__ Mm, const double *__restrict__ S, int m, int ld,
+                       const double *__restrict__ alpha, const double *__restrict__ beta,
+                       double *__restrict__ out_gen, double *__restrict__ out_tri, int *__restrict__ info) {
+  constexpr int LD = RITZ_MAX;
+  __shared__ double H[LD * LD], Sc[LD * LD], C[LD * LD], T1[LD * LD], U[LD * LD], wv[LD];
+  if (threadIdx.x != 0) return;
+  // tridiagonal
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) T1[i * LD + j] = 0.0;
+  for (int i = 0; i < m; ++i) T1[i * LD + i] = alpha[i];
+  for (int i = 0; i + 1 < m; ++i) { T1[i * LD + i + 1] = beta[i]; T1[(i + 1) * LD + i] = beta[i]; }
+  jacobi_eig_small(T1, m, LD, wv);
+  for (int i = 0; i < m; ++i) out_tri[i] = wv[i];
+  // generalised
+  bool ok = true;
+  const int mk = ritz_transform(S, ld, m, C, T1, Sc, U, ok);
+  ritz_projected(Mm, ld, m, mk, C, T1, H, Sc);
   jacobi_eig_small(T1, mk, LD, wv);
-  for (int i = 0; i < m; ++i) out_gen[i] = (i < mk) ? wv[i] : 0.0;
+  // values of dropped basis directions are reported as NaN
+  for (int i = 0; i < m; ++i) out_gen[i] = (i < mk) ? wv[i] : __longlong_as_double(0x7ff8000000000000LL);
   info[0] = ok ? 0 : 1;
   info[1] = mk;
+}
+
+// Coefficients x (m) of the a-th Ritz vector (ascending Ritz values) over
+// the basis v_0..v_{m-1}: x = C^T y_a with y_a the eigenvector of C H_sym C^T
+// (eq. reortho, eq. eff_H); the Ritz vector sum_i x_i v_i has unit norm in
+// the metric S.  info[0] = 0 on success, 1 when a >= the kept count.
+__global__ void k_ritz_vector(const double *__restrict__ Mm, const double *__restrict__ S, int m, int ld, int a,
+                              double *__restrict__ x, int *__restrict__ info) {
+  constexpr int LD = RITZ_MAX;
+  __shared__ double H[LD * LD], Sc[LD * LD], C[LD * LD], T1[LD * LD], U[LD * LD];
+  if (threadIdx.x != 0) return;
+  bool ok = true;
+  const int mk = ritz_transform(S, ld, m, C, T1, Sc, U, ok);
+  if (a < 0 || a >= mk) {
+    info[0] = 1;
+    return;
+  }
+  ritz_projected(Mm, ld, m, mk, C, T1, H, Sc);
+  jacobi_eig_vectors(T1, U, mk);
+  // the a-th smallest eigenvalue's column
+  int order[LD];
+  for (int i = 0; i < mk; ++i) order[i] = i;
+  for (int i = 1; i < mk; ++i) {
+    const int v = order[i];
+    int j = i - 1;
+    while (j >= 0 && T1[order[j] * LD + order[j]] > T1[v * LD + v]) { order[j + 1] = order[j]; --j; }
+    order[j + 1] = v;
+  }
+  const int col = order[a];
+  for (int i = 0; i < m; ++i) {
+    double v = 0.0;
+    for (int k = 0; k < mk; ++k) v += C[k * LD + i] * U[k * LD + col];
+    x[i] = v;
+  }
+  info[0] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1228,11 +1300,13 @@ __global__ void k_ritz(const double *__restrict__ Mm, const double *__restrict__
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_ormtr_tfac(const double *__restrict__ Ab, int64_t sA, int m,
                                                     const double *__restrict__ taub, int64_t sv,
-                                                    double *__restrict__ Tfb, int64_t sTf) {
+                                                    double *__restrict__ Tfb, int64_t sTf,
+                                                    const int *__restrict__ only) {
   constexpr int NB = 16, VL = 516;
   __shared__ double V[NB * VL];
   __shared__ double G[NB * NB], T[NB * NB], tv[NB];
   const int bi = blockIdx.x, job = blockIdx.y;
+  if (only != nullptr && only[job] == 0) return;  // job not selected
   const double *A = Ab + (int64_t)job * sA;
   const double *tau = taub + (int64_t)job * sv;
   double *Tf = Tfb + (int64_t)job * sTf + (int64_t)bi * NB * NB;
@@ -1290,7 +1364,9 @@ __global__ __launch_bounds__(256) void k_ormtr_tfac(const double *__restrict__ A
 __global__ __launch_bounds__(512) void k_ormtr2(const double *__restrict__ Ab, int64_t sA, int m,
                                                 const double *__restrict__ Tfb, int64_t sTf,
                                                 const double *__restrict__ Zb, int64_t sZ, int kk,
-                                                double *__restrict__ Utb, int64_t sU, int nslab, int zout) {
+                                                double *__restrict__ Utb, int64_t sU, int nslab, int zout,
+                                                const int *__restrict__ only) {
+  if (only != nullptr && only[blockIdx.x / nslab] == 0) return;  // job not selected
   constexpr int NB = 16, NWV = 8, CS = 64, VL = 516;
   extern __shared__ double lds[];
   double *V = lds;                   // NB x VL: row p = reflector i0 + p over rows 0..m-1
@@ -1420,7 +1496,9 @@ __global__ __launch_bounds__(512) void k_ormtr2(const double *__restrict__ Ab, i
 template <int MMAX>
 __global__ __launch_bounds__(512) void k_sytrd(double *__restrict__ Ab, int64_t sA, int m,
                                                  double *__restrict__ db, double *__restrict__ eb,
-                                                 double *__restrict__ taub, int64_t sv) {
+                                                 double *__restrict__ taub, int64_t sv,
+                                                 const int *__restrict__ only) {
+  if (only != nullptr && only[blockIdx.x] == 0) return;  // job not selected
   constexpr int NB = 8, NT = 512, NW = NT / WAVE, CPL = MMAX / WAVE, RU = 8;
   static_assert(MMAX == NT, "one entry of each column vector per thread");
   extern __shared__ double lds[];
@@ -1904,7 +1982,9 @@ __device__ void inv_iter_one(const double *sd, const double *se, int m, int kk, 
 __global__ __launch_bounds__(512) void k_tri_eig(const double *__restrict__ db, const double *__restrict__ eb,
                                                  int64_t sv, int m, int kk, double *__restrict__ Zb, int64_t sZ,
                                                  double *__restrict__ lamb, int64_t sl, double *__restrict__ scrb,
-                                                 int64_t sscr, int *__restrict__ flagb) {
+                                                 int64_t sscr, int *__restrict__ flagb,
+                                                 const int *__restrict__ only) {
+  if (only != nullptr && only[blockIdx.x] == 0) return;  // job not selected
   __shared__ double sd[1024], se[1024], se2[1024];
   __shared__ int s_need;
   __shared__ double slam[1024];
@@ -2027,6 +2107,93 @@ __global__ __launch_bounds__(512) void k_tri_eig(const double *__restrict__ db, 
 
 
 
+// svd_flags: per-job decisions of the Gram-matrix SVD step, from the top-kk
+// eigenvalues lam (descending) and Lz = Z^T Z of the back-transformed
+// eigenvectors Z (kk x kk).
+//   jac[job] = 1 when the kept set reaches below tau * lam_1 (an eigenvalue
+//     of G = Y Y^T that small carries an absolute error of the order of
+//     eps * lam_1, so its vector, and the decision whether a singular value
+//     there passes the cutoff, are not resolved): the job's SVD is redone
+//     from Y by one-sided Jacobi, which has high relative accuracy;
+//   otherwise nl[job] |= (max |Lz - I| > 1e-8): one Newton-Schulz step
+//     leaves ~E^2 of an orthogonality error E, so larger errors (vectors of
+//     near-degenerate eigenvalues just outside a cluster) go to the
+//     Householder re-orthonormalisation instead.  Jobs taking the Jacobi
+//     route get nl = 0.
+// One workgroup per job.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_svd_flags(const double *__restrict__ lamb, int64_t sl, int kk, double tau,
+                                                   const double *__restrict__ Lzb, int64_t sLz, int *__restrict__ nl,
+                                                   int *__restrict__ jac) {
+  __shared__ double red[256 / WAVE];
+  const int job = blockIdx.x, tid = threadIdx.x;
+  const double *lam = lamb + (int64_t)job * sl;
+  const double *Lz = Lzb + (int64_t)job * sLz;
+  const bool j = lam[0] > 0.0 && !(lam[kk - 1] >= tau * lam[0]);
+  double e = 0.0;
+  if (!j) {
+    for (int64_t q = tid; q < (int64_t)kk * kk; q += blockDim.x) {
+      const int a = (int)(q / kk), b = (int)(q % kk);
+      e = fmax(e, fabs(Lz[q] - (a == b ? 1.0 : 0.0)));
+    }
+  }
+  e = wave_max(e);
+  if (tid % WAVE == 0) red[tid / WAVE] = e;
+  __syncthreads();
+  if (tid == 0) {
+    double mx = 0.0;
+    for (int w = 0; w < (int)(blockDim.x / WAVE); ++w) mx = fmax(mx, red[w]);
+    jac[job] = j ? 1 : 0;
+    nl[job] = j ? 0 : ((nl[job] != 0 || !(mx <= 1e-8)) ? 1 : 0);
+  }
+}
+
+// Second level of the Gram route for the jobs selected by jac (their kept
+// set reached the noise floor).  deflate_prep: r1 = #{t < kk : lam_t >
+// tau lam_0} well-resolved eigenvectors; Q1 (m x kk, column t = t-th vector)
+// = Qz with the columns t >= r1 zeroed; flag[job] = 1 records the job.
+// merge_basis: Zq (m x kk) = [Q1 columns 0..r1-1 | the leading kk - r1
+// eigenvectors Z2 of the deflated Gram matrix].  One workgroup per job.
+__global__ __launch_bounds__(256) void k_deflate_prep(const double *__restrict__ lamb, int64_t sl, int kk, double tau,
+                                                      const double *__restrict__ Qb, int64_t sQ, int m,
+                                                      double *__restrict__ Q1b, int64_t sQ1, int *__restrict__ r1b,
+                                                      const int *__restrict__ jac, int *__restrict__ flag) {
+  const int job = blockIdx.x;
+  if (jac[job] == 0) return;
+  const double *lam = lamb + (int64_t)job * sl;
+  __shared__ int s_r1;
+  if (threadIdx.x == 0) {
+    int r = 0;
+    while (r < kk && lam[r] > tau * lam[0]) ++r;
+    s_r1 = r;
+    r1b[job] = r;
+    flag[job] = 1;
+  }
+  __syncthreads();
+  const int r1 = s_r1;
+  const double *Q = Qb + (int64_t)job * sQ;
+  double *Q1 = Q1b + (int64_t)job * sQ1;
+  for (int64_t e = threadIdx.x; e < (int64_t)m * kk; e += blockDim.x) {
+    const int t = (int)(e % kk);
+    Q1[e] = (t < r1) ? Q[e] : 0.0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_merge_basis(const double *__restrict__ Q1b, int64_t sQ1,
+                                                     const double *__restrict__ Z2b, int64_t sZ, int m, int kk,
+                                                     const int *__restrict__ r1b, const int *__restrict__ jac,
+                                                     double *__restrict__ Outb, int64_t sO) {
+  const int job = blockIdx.x;
+  if (jac[job] == 0) return;
+  const int r1 = r1b[job];
+  const double *Q1 = Q1b + (int64_t)job * sQ1, *Z2 = Z2b + (int64_t)job * sZ;
+  double *O = Outb + (int64_t)job * sO;
+  for (int64_t e = threadIdx.x; e < (int64_t)m * kk; e += blockDim.x) {
+    const int i = (int)(e / kk), t = (int)(e % kk);
+    O[e] = (t < r1) ? Q1[e] : Z2[(int64_t)i * kk + (t - r1)];
+  }
+}
+
 // svd_finish2: C (kk x n) holds Qz Y.  Row norms s_t; cutoff relative to the
 // largest; rows with s_t <= cutoff * s_max are zeroed together with column t
 // of U = Qz^T (m x kk, written to Ub).  rank = 1 + last kept index;
@@ -2035,9 +2202,11 @@ __global__ __launch_bounds__(256) void k_svd_finish2(const double *__restrict__ 
                                                      double *__restrict__ Cb, int64_t sC, int n, double cutoff,
                                                      const double *__restrict__ db, int64_t sv,
                                                      double *__restrict__ Ub, int64_t sU,
-                                                     int *__restrict__ rank_out, double *__restrict__ disc_out, int qt) {
+                                                     int *__restrict__ rank_out, double *__restrict__ disc_out, int qt,
+                                                     const int *__restrict__ only) {
   __shared__ double nr[1024];
   const int job = blockIdx.x;
+  if (only != nullptr && only[job] == 0) return;  // job not selected
   const double *Q = Qb + (int64_t)job * sQ;
   double *Cc = Cb + (int64_t)job * sC;
   double *U = Ub + (int64_t)job * sU;
@@ -2077,6 +2246,120 @@ __global__ __launch_bounds__(256) void k_svd_finish2(const double *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------
+// Transition one-body matrices g_ij = <bra|a+_i a_j|ket> for the energy
+// gradient.  At site j, the transfer-matrix product of an environment X
+// (bra bond x ket bond) with the ket site is F = X B_j, viewed
+// (l_bra, 2, r_ket); W = A_j R_{j+1}, viewed (l_bra, 2, r_ket), carries the
+// bra site and the right environment.  Closing the chain with the operator
+// entry op[s][t] (bra s, ket t) is the dot product sum_{a,d} F[a][t][d]
+// W[a][s][d].
+//   mode 0: F holds the stack of open environments of each ket (block r:
+//     start site i = r / 2; r even: c+ was placed at i, close with c
+//     (s = 0, t = 1) -> g[i][j]; r odd: c at i, close with c+ (s = 1, t = 0)
+//     -> g[j][i]).
+//   mode 1: F = E_j B_j of the plain left environment: n_j = c+c (s = t = 1)
+//     -> g[j][j].
+// One workgroup per (block, ket).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_rdm_close(const double *__restrict__ Fb, int64_t sF_ket, int64_t sF_blk,
+                                                   const double *__restrict__ Wb, int64_t sW, int lb, int rk,
+                                                   double *__restrict__ g, int n, int j, int mode) {
+  __shared__ double red[256 / WAVE];
+  const int r = blockIdx.x, k = blockIdx.y, tid = threadIdx.x;
+  const double *F = Fb + (int64_t)k * sF_ket + (int64_t)r * sF_blk;
+  const double *W = Wb + (int64_t)k * sW;
+  int s, t;
+  if (mode == 1) { s = 1; t = 1; }
+  else if ((r & 1) == 0) { s = 0; t = 1; }
+  else { s = 1; t = 0; }
+  double acc = 0.0;
+  const int64_t cnt = (int64_t)lb * rk;
+  for (int64_t e = tid; e < cnt; e += blockDim.x) {
+    const int a = (int)(e / rk), d = (int)(e % rk);
+    acc = fma(F[((int64_t)a * 2 + t) * rk + d], W[((int64_t)a * 2 + s) * rk + d], acc);
+  }
+  acc = wave_sum(acc);
+  if (tid % WAVE == 0) red[tid / WAVE] = acc;
+  __syncthreads();
+  if (tid == 0) {
+    double v = 0.0;
+    for (int w = 0; w < (int)(blockDim.x / WAVE); ++w) v += red[w];
+    double *gk = g + (int64_t)k * n * n;
+    if (mode == 1) gk[(int64_t)j * n + j] = v;
+    else if ((r & 1) == 0) gk[(int64_t)(r / 2) * n + j] = v;
+    else gk[(int64_t)j * n + (r / 2)] = v;
+  }
+}
+
+// dst = src with the physical index 1 negated (site (l, 2, r)): the bra site
+// of a transfer with the Jordan-Wigner Z = diag(1, -1) in between.
+__global__ void k_negate_odd(const double *__restrict__ src, double *__restrict__ dst, int l, int r) {
+  const int64_t total = (int64_t)l * 2 * r;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = (((e / r) & 1) ? -1.0 : 1.0) * src[e];
+}
+
+// Energy and gradient from the transition matrices (one workgroup):
+//   G^nu_pq = sum_{s', s} g^{(nu, s')}_{2p+s, 2q+s}      (ket (nu, s') = 2 nu + s')
+//   nn_{mu nu} = chi^mu^T G^nu chi^mu = <psi|N_mu N_nu|psi>
+//   E = 1/2 sum zeta_{mu nu} nn_{mu nu} + sum_{i,s} lam_i <psi|n_{u_i s}|psi>
+//   dzeta = nn / 2
+//   dchi[:, k] = (M_k + M_k^T) chi^k,  M_k = sum_nu (zeta_{k nu} + zeta_{nu k}) / 2 G^nu
+// chi (L x N), zeta (N x N), lam (L) row-major; ovl[2N + 2i + s] = <psi|n_{u_i s}|psi>.
+// Work: G (N L^2) and M (L^2) in global scratch Gw.
+__global__ __launch_bounds__(256) void k_grad_final(const double *__restrict__ g, int n, int L, int N,
+                                                    const double *__restrict__ chi, const double *__restrict__ zeta,
+                                                    const double *__restrict__ lam, const double *__restrict__ ovl,
+                                                    double *__restrict__ Gw, double *__restrict__ out) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  double *G = Gw, *Mk = Gw + (int64_t)N * L * L;
+  double *E = out, *dchi = out + 1, *dzeta = out + 1 + (int64_t)L * N;
+  for (int64_t e = tid; e < (int64_t)N * L * L; e += nt) {
+    const int nu = (int)(e / (L * L)), p = (int)((e / L) % L), q = (int)(e % L);
+    double v = 0.0;
+    for (int sp = 0; sp < 2; ++sp) {
+      const double *gk = g + (int64_t)(2 * nu + sp) * n * n;
+      for (int s = 0; s < 2; ++s) v += gk[(int64_t)(2 * p + s) * n + (2 * q + s)];
+    }
+    G[e] = v;
+  }
+  __syncthreads();
+  for (int64_t e = tid; e < (int64_t)N * N; e += nt) {
+    const int mu = (int)(e / N), nu = (int)(e % N);
+    const double *Gn = G + (int64_t)nu * L * L;
+    double v = 0.0;
+    for (int p = 0; p < L; ++p) {
+      double w = 0.0;
+      for (int q = 0; q < L; ++q) w += Gn[p * L + q] * chi[q * N + mu];
+      v += chi[p * N + mu] * w;
+    }
+    dzeta[e] = 0.5 * v;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double ev = 0.0;
+    for (int64_t e = 0; e < (int64_t)N * N; ++e) ev += zeta[e] * dzeta[e];  // 1/2 zeta nn
+    double et = 0.0;
+    for (int i = 0; i < L; ++i) et += lam[i] * (ovl[2 * N + 2 * i] + ovl[2 * N + 2 * i + 1]);
+    E[0] = ev + et;
+  }
+  for (int k = 0; k < N; ++k) {
+    __syncthreads();
+    for (int e = tid; e < L * L; e += nt) {
+      double v = 0.0;
+      for (int nu = 0; nu < N; ++nu) v += 0.5 * (zeta[k * N + nu] + zeta[nu * N + k]) * G[(int64_t)nu * L * L + e];
+      Mk[e] = v;
+    }
+    __syncthreads();
+    for (int p = tid; p < L; p += nt) {
+      double v = 0.0;
+      for (int q = 0; q < L; ++q) v += (Mk[p * L + q] + Mk[q * L + p]) * chi[q * N + k];
+      dchi[p * N + k] = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // host launch wrappers
 // ---------------------------------------------------------------------------
 static inline int cdiv64(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
@@ -2091,37 +2374,112 @@ void launch_construct(hipStream_t st, const CJob *jobs, int nb, int site, int n_
                      ra, lb, rb, out, out_stride, lo, ro);
 }
 
+// One launch of the batched GEMM with a BM x BN output tile.
+template <int MODE, int PREC, int BT>
+static void gemm_tile(hipStream_t st, int nb, const double *A, int64_t sA, int lda, const double *B, int64_t sB,
+                      int ldb, double *C, int64_t sC, int ldc, int M, int N, int K, double alpha, double beta,
+                      const int *only) {
+  const int tm = (M + BT - 1) / BT, tn = (N + BT - 1) / BT;
+  hipLaunchKernelGGL((k_gemm_mfma<MODE, BT, BT, PREC>), dim3(nb * tm * tn), dim3(256), 0, st, A, sA, lda, B, sB, ldb,
+                     C, sC, ldc, M, N, K, tm, tn, alpha, beta, only);
+}
+
+// ---------------------------------------------------------------------------
+// Tile autotuner.  The first time a shape class (mode, precision, M, N, K,
+// batch size rounded down to a power of two) is launched with beta = 0, no
+// job selection and no stream capture in progress, both tile candidates
+// (64 x 64 and 128 x 128) run on the call's own operands, timed with HIP
+// events, and the faster one is used for every later launch of that class.
+// The candidates accumulate every output element over K in the same order
+// (BK = 16 chunks, the same MFMA sequence within a chunk), so their results
+// are bitwise identical and the tuning launches leave the correct C.  Until
+// a class is tuned (or with THCK_AUTOTUNE=0) the default applies: 64 x 64
+// for FP64, 128 x 128 for FP32 / BF16x3 when M and N exceed 64.
+// ---------------------------------------------------------------------------
+struct TuneKey {
+  int mode, prec, M, N, K, nbc;
+  bool operator<(const TuneKey &o) const {
+    return std::tie(mode, prec, M, N, K, nbc) < std::tie(o.mode, o.prec, o.M, o.N, o.K, o.nbc);
+  }
+};
+struct TuneRec {
+  int tile;
+  float ms64, ms128;
+};
+static std::map<TuneKey, TuneRec> &tune_table() {
+  static auto *t = new std::map<TuneKey, TuneRec>();  // read by the exit report
+  return *t;
+}
+static bool autotune_on() {
+  static const bool on = [] {
+    const char *e = getenv("THCK_AUTOTUNE");
+    return !(e && e[0] == '0');
+  }();
+  return on;
+}
+
 template <int MODE, int PREC>
 static void gemm_mode(hipStream_t st, int nb, const double *A, int64_t sA, int lda, const double *B, int64_t sB,
-                      int ldb, double *C, int64_t sC, int ldc, int M, int N, int K, double alpha, double beta) {
-  // FP64: 64 x 64 tiles (the 128 x 128 FP64 tile holds 4 x 4 FP64
-  // accumulator blocks per wave and runs at one wave per SIMD; the smaller
-  // tile is faster on every batched shape of the path).  FP32 / BF16x3:
-  // 128 x 128 tiles when both dimensions exceed 64.
-  if (PREC != GEMM_F64 && M > 64 && N > 64) {
-    const int tm = (M + 127) / 128, tn = (N + 127) / 128;
-    hipLaunchKernelGGL((k_gemm_mfma<MODE, 128, 128, PREC>), dim3(nb * tm * tn), dim3(256), 0, st, A, sA, lda, B, sB,
-                       ldb, C, sC, ldc, M, N, K, tm, tn, alpha, beta);
-  } else {
-    const int tm = (M + 63) / 64, tn = (N + 63) / 64;
-    hipLaunchKernelGGL((k_gemm_mfma<MODE, 64, 64, PREC>), dim3(nb * tm * tn), dim3(256), 0, st, A, sA, lda, B, sB,
-                       ldb, C, sC, ldc, M, N, K, tm, tn, alpha, beta);
+                      int ldb, double *C, int64_t sC, int ldc, int M, int N, int K, double alpha, double beta,
+                      const int *only) {
+  int nbc = 1;
+  while (nbc * 2 <= nb) nbc *= 2;
+  const TuneKey key{MODE, PREC, M, N, K, nbc};
+  auto &tab = tune_table();
+  auto it = tab.find(key);
+  int tile = (PREC != GEMM_F64 && M > 64 && N > 64) ? 128 : 64;
+  if (it != tab.end()) {
+    tile = it->second.tile;
+  } else if (autotune_on() && beta == 0.0 && only == nullptr) {
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone) {
+      hipEvent_t e[3];
+      bool ok = true;
+      for (auto &x : e) ok = ok && hipEventCreate(&x) == hipSuccess;
+      if (ok) {
+        (void)hipEventRecord(e[0], st);
+        gemm_tile<MODE, PREC, 64>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta, only);
+        (void)hipEventRecord(e[1], st);
+        gemm_tile<MODE, PREC, 128>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta, only);
+        (void)hipEventRecord(e[2], st);
+        float t64 = 0.0f, t128 = 0.0f;
+        if (hipEventSynchronize(e[2]) == hipSuccess && hipEventElapsedTime(&t64, e[0], e[1]) == hipSuccess &&
+            hipEventElapsedTime(&t128, e[1], e[2]) == hipSuccess) {
+          tab[key] = TuneRec{t128 < t64 ? 128 : 64, t64, t128};
+        }
+      }
+      for (auto &x : e) (void)hipEventDestroy(x);
+      if (ok) return;  // C holds the product (both candidates wrote the same values)
+    }
+  }
+  if (tile == 128) gemm_tile<MODE, PREC, 128>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta, only);
+  else gemm_tile<MODE, PREC, 64>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta, only);
+}
+
+void gemm_tuning_report(FILE *f) {
+  static const char *pn[3] = {"f64", "f32", "bf16x3"};
+  for (const auto &kv : tune_table()) {
+    const TuneKey &k = kv.first;
+    fprintf(f, "[thck] gemm tile: mode %d %-6s %5d x %5d x %5d batch %4d: 64x64 %.3f ms, 128x128 %.3f ms -> %d\n",
+            k.mode, pn[k.prec], k.M, k.N, k.K, k.nbc, kv.second.ms64, kv.second.ms128, kv.second.tile);
   }
 }
+
+int gemm_tuned_classes() { return (int)tune_table().size(); }
 
 template <int PREC>
 static void gemm_prec(hipStream_t st, int nb, int mode, const double *A, int64_t sA, int lda, const double *B,
                       int64_t sB, int ldb, double *C, int64_t sC, int ldc, int M, int N, int K, double alpha,
-                      double beta) {
+                      double beta, const int *only) {
   switch (mode) {
     case GEMM_TB | GEMM_UPPER:
-      gemm_mode<GEMM_TB | GEMM_UPPER, PREC>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta);
+      gemm_mode<GEMM_TB | GEMM_UPPER, PREC>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta, only);
       break;
-    case 0: gemm_mode<0, PREC>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta); break;
-    case GEMM_TB: gemm_mode<GEMM_TB, PREC>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta); break;
-    case GEMM_TA: gemm_mode<GEMM_TA, PREC>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta); break;
+    case 0: gemm_mode<0, PREC>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta, only); break;
+    case GEMM_TB: gemm_mode<GEMM_TB, PREC>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta, only); break;
+    case GEMM_TA: gemm_mode<GEMM_TA, PREC>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta, only); break;
     case GEMM_TA | GEMM_TB:
-      gemm_mode<GEMM_TA | GEMM_TB, PREC>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta);
+      gemm_mode<GEMM_TA | GEMM_TB, PREC>(st, nb, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta, only);
       break;
     default: break;
   }
@@ -2129,14 +2487,14 @@ static void gemm_prec(hipStream_t st, int nb, int mode, const double *A, int64_t
 
 void launch_gemm(hipStream_t st, int nb, int mode, const double *A, int64_t sA, int lda, const double *B,
                  int64_t sB, int ldb, double *C, int64_t sC, int ldc, int M, int N, int K, double alpha,
-                 double beta, int prec) {
+                 double beta, int prec, const int *only) {
   if (nb <= 0 || M <= 0 || N <= 0) return;
   switch (prec) {
-    case GEMM_F32: gemm_prec<GEMM_F32>(st, nb, mode, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta); break;
+    case GEMM_F32: gemm_prec<GEMM_F32>(st, nb, mode, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta, only); break;
     case GEMM_BF16X3:
-      gemm_prec<GEMM_BF16X3>(st, nb, mode, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta);
+      gemm_prec<GEMM_BF16X3>(st, nb, mode, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta, only);
       break;
-    default: gemm_prec<GEMM_F64>(st, nb, mode, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta); break;
+    default: gemm_prec<GEMM_F64>(st, nb, mode, A, sA, lda, B, sB, ldb, C, sC, ldc, M, N, K, alpha, beta, only); break;
   }
 }
 
@@ -2183,7 +2541,7 @@ int launch_lq(hipStream_t st, int nb, double *X, int64_t sX, int m, int n, doubl
 
 
 int launch_jacobi(hipStream_t st, int nb, double *Y, int64_t sY, int m, int n, double *s, int64_t ss,
-                  int *sweeps, int max_sweeps) {
+                  int *sweeps, int max_sweeps, const int *only) {
   if (n <= 512) {
     constexpr int BS = 16, NMAX = 512;
     size_t lds = (2 * (2 * BS) * (2 * BS) + 2 * BS + 8 + 2 * BS * NMAX) * sizeof(double);
@@ -2194,7 +2552,7 @@ int launch_jacobi(hipStream_t st, int nb, double *Y, int64_t sY, int m, int n, d
       attr = true;
     }
     hipLaunchKernelGGL((k_jacobi_rows<BS, NMAX>), dim3(nb), dim3(256), lds, st, Y, sY, m, n, s, ss, sweeps,
-                       max_sweeps);
+                       max_sweeps, only);
     return 0;
   }
   if (n <= 1024) {
@@ -2207,7 +2565,7 @@ int launch_jacobi(hipStream_t st, int nb, double *Y, int64_t sY, int m, int n, d
       attr = true;
     }
     hipLaunchKernelGGL((k_jacobi_rows<BS, NMAX>), dim3(nb), dim3(256), lds, st, Y, sY, m, n, s, ss, sweeps,
-                       max_sweeps);
+                       max_sweeps, only);
     return 0;
   }
   return -1;
@@ -2215,16 +2573,16 @@ int launch_jacobi(hipStream_t st, int nb, double *Y, int64_t sY, int m, int n, d
 
 void launch_svd_select(hipStream_t st, int nb, const double *Y, int64_t sY, int m, int n, const double *s,
                        int64_t ss, int kk, double cutoff, double *W, int64_t sW, int *rank, double *disc,
-                       double *sv_out, int64_t ssv) {
+                       double *sv_out, int64_t ssv, const int *only) {
   hipLaunchKernelGGL(k_svd_select, dim3(nb), dim3(256), 0, st, Y, sY, m, n, s, ss, kk, cutoff, W, sW, rank, disc,
-                     sv_out, ssv);
+                     sv_out, ssv, only);
 }
 
 void launch_svd_finish(hipStream_t st, int nb, const double *Q, int64_t sQ, int m, int kk, const int *rank,
-                       double *U, int64_t sU, double *C, int64_t sC, int n) {
+                       double *U, int64_t sU, double *C, int64_t sC, int n, const int *only) {
   int gx = cdiv64((int64_t)m * kk > (int64_t)kk * n ? (int64_t)m * kk : (int64_t)kk * n, 256);
   if (gx > 2048) gx = 2048;
-  hipLaunchKernelGGL(k_svd_finish, dim3(gx, nb), dim3(256), 0, st, Q, sQ, m, kk, rank, U, sU, C, sC, n);
+  hipLaunchKernelGGL(k_svd_finish, dim3(gx, nb), dim3(256), 0, st, Q, sQ, m, kk, rank, U, sU, C, sC, n, only);
 }
 
 void launch_transpose(hipStream_t st, int nb, const double *src, int64_t ss, int r, int c, double *dst, int64_t sd) {
@@ -2264,11 +2622,12 @@ void launch_fill(hipStream_t st, int nb, double *p, int64_t stride, int64_t coun
   hipLaunchKernelGGL(k_fill, dim3(gx, nb), dim3(256), 0, st, p, stride, count, v);
 }
 
-void launch_copy(hipStream_t st, int nb, const double *src, int64_t ssrc, double *dst, int64_t sdst, int64_t count) {
+void launch_copy(hipStream_t st, int nb, const double *src, int64_t ssrc, double *dst, int64_t sdst, int64_t count,
+                 const int *only) {
   int gx = cdiv64(count, 256);
   if (gx > 2048) gx = 2048;
   if (gx < 1) gx = 1;
-  hipLaunchKernelGGL(k_copy, dim3(gx, nb), dim3(256), 0, st, src, ssrc, dst, sdst, count);
+  hipLaunchKernelGGL(k_copy, dim3(gx, nb), dim3(256), 0, st, src, ssrc, dst, sdst, count, only);
 }
 
 void launch_gather(hipStream_t st, int nb, const CJob *jobs, int which, int64_t off, double *dst, int64_t sdst,
@@ -2301,7 +2660,8 @@ void launch_scale(hipStream_t st, double *p, int64_t count, double c) {
 }
 
 
-int launch_sytrd(hipStream_t st, int nb, double *A, int64_t sA, int m, double *d, double *e, double *tau, int64_t sv) {
+int launch_sytrd(hipStream_t st, int nb, double *A, int64_t sA, int m, double *d, double *e, double *tau, int64_t sv,
+                 const int *only) {
   constexpr int MMAX = 512, NW = 512 / WAVE, NB = 8;
   if (m > MMAX) return -1;
   // V, W (NB x MMAX each), x, kept row, 4 group row sums, NW column partials,
@@ -2309,14 +2669,15 @@ int launch_sytrd(hipStream_t st, int nb, double *A, int64_t sA, int m, double *d
   const size_t lds = (2 * NB * MMAX + 2 * MMAX + 4 * MMAX + NW * MMAX + MMAX + 2 * NW + 2 * NB + NW) * sizeof(double);
   static bool attr = false;
   if (!attr) { set_lds(k_sytrd<MMAX>, lds); attr = true; }
-  hipLaunchKernelGGL(k_sytrd<MMAX>, dim3(nb), dim3(512), lds, st, A, sA, m, d, e, tau, sv);
+  hipLaunchKernelGGL(k_sytrd<MMAX>, dim3(nb), dim3(512), lds, st, A, sA, m, d, e, tau, sv, only);
   return 0;
 }
 
 int launch_tri_eig(hipStream_t st, int nb, const double *d, const double *e, int64_t sv, int m, int kk, double *Z,
-                   int64_t sZ, double *lam, int64_t sl, double *scr, int64_t sscr, int *needs_lq) {
+                   int64_t sZ, double *lam, int64_t sl, double *scr, int64_t sscr, int *needs_lq, const int *only) {
   if (m > 1024 || kk > 256) return -1;
-  hipLaunchKernelGGL(k_tri_eig, dim3(nb), dim3(512), 0, st, d, e, sv, m, kk, Z, sZ, lam, sl, scr, sscr, needs_lq);
+  hipLaunchKernelGGL(k_tri_eig, dim3(nb), dim3(512), 0, st, d, e, sv, m, kk, Z, sZ, lam, sl, scr, sscr, needs_lq,
+                     only);
   return 0;
 }
 
@@ -2326,26 +2687,41 @@ int64_t ormtr_tf_stride(int m) {
 }
 
 int launch_ormtr(hipStream_t st, int nb, const double *A, int64_t sA, int m, const double *tau, int64_t sv, double *Z,
-                 int64_t sZ, int kk, double *Ut, int64_t sU, bool zout, double *Tf, int64_t sTf) {
+                 int64_t sZ, int kk, double *Ut, int64_t sU, bool zout, double *Tf, int64_t sTf, const int *only) {
   if (m > 512) return -1;
   const int nslab = (kk + 63) / 64;
   if (nslab == 0 || nb <= 0) return 0;
   const int nref = m - 2;
   const int nblk = nref > 0 ? (nref + 15) / 16 : 0;
-  if (nblk > 0) hipLaunchKernelGGL(k_ormtr_tfac, dim3(nblk, nb), dim3(256), 0, st, A, sA, m, tau, sv, Tf, sTf);
+  if (nblk > 0) hipLaunchKernelGGL(k_ormtr_tfac, dim3(nblk, nb), dim3(256), 0, st, A, sA, m, tau, sv, Tf, sTf, only);
   const size_t lds = (16 * 516 + 8 * 16 * 64 + 2 * 16 * 64 + 256) * sizeof(double);
   static bool attr = false;
   if (!attr) { set_lds(k_ormtr2, lds); attr = true; }
   hipLaunchKernelGGL(k_ormtr2, dim3(nb * nslab), dim3(512), lds, st, A, sA, m, Tf, sTf, Z, sZ, kk, Ut, sU, nslab,
-                     zout ? 1 : 0);
+                     zout ? 1 : 0, only);
   return 0;
+}
+
+void launch_svd_flags(hipStream_t st, int nb, const double *lam, int64_t sl, int kk, double tau, const double *Lz,
+                      int64_t sLz, int *nl, int *jac) {
+  hipLaunchKernelGGL(k_svd_flags, dim3(nb), dim3(256), 0, st, lam, sl, kk, tau, Lz, sLz, nl, jac);
+}
+
+void launch_deflate_prep(hipStream_t st, int nb, const double *lam, int64_t sl, int kk, double tau, const double *Q,
+                         int64_t sQ, int m, double *Q1, int64_t sQ1, int *r1, const int *jac, int *flag) {
+  hipLaunchKernelGGL(k_deflate_prep, dim3(nb), dim3(256), 0, st, lam, sl, kk, tau, Q, sQ, m, Q1, sQ1, r1, jac, flag);
+}
+
+void launch_merge_basis(hipStream_t st, int nb, const double *Q1, int64_t sQ1, const double *Z2, int64_t sZ, int m,
+                        int kk, const int *r1, const int *jac, double *out, int64_t sO) {
+  hipLaunchKernelGGL(k_merge_basis, dim3(nb), dim3(256), 0, st, Q1, sQ1, Z2, sZ, m, kk, r1, jac, out, sO);
 }
 
 void launch_svd_finish2(hipStream_t st, int nb, const double *Q, int64_t sQ, int m, int kk, double *C, int64_t sC,
                         int n, double cutoff, const double *d, int64_t sv, double *U, int64_t sU, int *rank,
-                        double *disc, bool qt) {
+                        double *disc, bool qt, const int *only) {
   hipLaunchKernelGGL(k_svd_finish2, dim3(nb), dim3(256), 0, st, Q, sQ, m, kk, C, sC, n, cutoff, d, sv, U, sU, rank,
-                     disc, qt ? 1 : 0);
+                     disc, qt ? 1 : 0, only);
 }
 
 int64_t tri_eig_scratch(int m, int kk) { return 3 * (int64_t)m * kk + 8; }
@@ -2353,6 +2729,28 @@ int64_t tri_eig_scratch(int m, int kk) { return 3 * (int64_t)m * kk + 8; }
 void launch_ritz(hipStream_t st, const double *Mm, const double *S, int m, int ld, const double *alpha,
                  const double *beta, double *out_gen, double *out_tri, int *info) {
   hipLaunchKernelGGL(k_ritz, dim3(1), dim3(64), 0, st, Mm, S, m, ld, alpha, beta, out_gen, out_tri, info);
+}
+
+void launch_rdm_close(hipStream_t st, int nblk, int nket, const double *F, int64_t sF_ket, int64_t sF_blk,
+                      const double *W, int64_t sW, int lb, int rk, double *g, int n, int j, int mode) {
+  if (nblk <= 0 || nket <= 0) return;
+  hipLaunchKernelGGL(k_rdm_close, dim3(nblk, nket), dim3(256), 0, st, F, sF_ket, sF_blk, W, sW, lb, rk, g, n, j, mode);
+}
+
+void launch_negate_odd(hipStream_t st, const double *src, double *dst, int l, int r) {
+  int gx = cdiv64((int64_t)l * 2 * r, 256);
+  if (gx > 1024) gx = 1024;
+  hipLaunchKernelGGL(k_negate_odd, dim3(gx), dim3(256), 0, st, src, dst, l, r);
+}
+
+void launch_grad_final(hipStream_t st, const double *g, int n, int L, int N, const double *chi, const double *zeta,
+                       const double *lam, const double *ovl, double *Gw, double *out) {
+  hipLaunchKernelGGL(k_grad_final, dim3(1), dim3(256), 0, st, g, n, L, N, chi, zeta, lam, ovl, Gw, out);
+}
+
+void launch_ritz_vector(hipStream_t st, const double *Mm, const double *S, int m, int ld, int a, double *x,
+                        int *info) {
+  hipLaunchKernelGGL(k_ritz_vector, dim3(1), dim3(64), 0, st, Mm, S, m, ld, a, x, info);
 }
 
 }  // namespace thck

@@ -62,16 +62,18 @@ class ThcStats(C.Structure):
         ("max_bond", C.c_int32),
         ("jacobi_sweeps_max", C.c_int32),
         ("nonconverged", C.c_int32),
-        ("reserved", C.c_int32),
-        ("kernel_ms", C.c_double * 5),
-        ("kernel_flops", C.c_double * 5),
-        ("kernel_launches", C.c_int64 * 5),
-        ("kernel_bytes", C.c_double * 5),
+        ("svd_fallbacks", C.c_int32),
+        ("kernel_ms", C.c_double * 6),
+        ("kernel_flops", C.c_double * 6),
+        ("kernel_launches", C.c_int64 * 6),
+        ("kernel_bytes", C.c_double * 6),
+        ("graph_captures", C.c_int64),
+        ("graph_replays", C.c_int64),
     ]
-    KERNELS = ("lq", "sytrd", "tri_eig", "ormtr", "gemm")
+    KERNELS = ("lq", "sytrd", "tri_eig", "ormtr", "gemm", "svd_fallback")
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved" and not f.startswith("kernel_")}
+        return {f: getattr(self, f) for f, _ in self._fields_ if not f.startswith("kernel_")}
 
     def kernels(self):
         """Per kernel class: (summed ms, algorithmic flops, launches, algorithmic bytes);
@@ -82,11 +84,13 @@ class ThcStats(C.Structure):
 
 FLAG_SVD_JACOBI = 1      # one-sided Jacobi SVD in the truncation step
 FLAG_TIME_KERNELS = 2    # per-kernel-class device times / flops in ThcStats.kernels()
+FLAG_GRAPHS = 4          # compression batches captured into HIP graphs and replayed
 
 EXPORTS = [
     "thc_default_opts", "thc_mps_capacity", "thc_load_factors", "thc_destroy", "mps_apply_thc_H",
     "mps_sum_compress", "mps_overlap", "krylov_create", "krylov_destroy", "krylov_step",
     "krylov_get_vector", "krylov_get_matrices", "mps_compress", "mps_apply_layer", "thc_last_error",
+    "krylov_ritz_vector", "krylov_restart", "thc_energy_gradient",
 ]
 
 _lib = None
@@ -121,11 +125,15 @@ def load_library(path: str = LIB_PATH):
     lib.mps_compress.argtypes = [vp, P(ThcMps), P(ThcMps), P(ThcOpts), P(ThcStats), vp]
     lib.mps_apply_layer.argtypes = [vp, P(ThcMps), P(C.c_double), C.c_int32, P(ThcMps), P(ThcOpts),
                                     P(ThcStats), vp]
+    lib.krylov_ritz_vector.argtypes = [vp, C.c_int32, P(ThcMps), vp]
+    lib.krylov_restart.argtypes = [vp, C.c_int32, vp]
+    lib.thc_energy_gradient.argtypes = [vp, P(ThcMps), C.c_int32, P(C.c_double), P(C.c_double), P(C.c_double), vp]
     lib.thc_last_error.argtypes = []
     lib.thc_last_error.restype = C.c_char_p
     for name in ("thc_load_factors", "thc_destroy", "mps_apply_thc_H", "mps_sum_compress", "mps_overlap",
                  "krylov_create", "krylov_destroy", "krylov_step", "krylov_get_vector", "krylov_get_matrices",
-                 "mps_compress", "mps_apply_layer"):
+                 "mps_compress", "mps_apply_layer", "krylov_ritz_vector", "krylov_restart",
+                 "thc_energy_gradient"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -287,6 +295,18 @@ class Context:
                                         C.byref(stats) if stats is not None else None, _stream()))
         return out._written(od)
 
+    def energy_gradient(self, psi: DeviceMPS, prec="f64"):
+        """(E, dE/dchi (L x N), dE/dzeta (N x N)) of E = <psi|H|psi> for the
+        loaded factors (thc_energy_gradient)."""
+        p = PREC[prec] if isinstance(prec, str) else int(prec)
+        e = C.c_double()
+        dchi = np.zeros((self.L, self.N))
+        dzeta = np.zeros((self.N, self.N))
+        pd = psi.desc()
+        _check(self.lib.thc_energy_gradient(self.h, C.byref(pd), p, C.byref(e), _dptr(dchi), _dptr(dzeta),
+                                            _stream()))
+        return float(e.value), dchi, dzeta
+
     def overlap(self, a: DeviceMPS, b: DeviceMPS) -> float:
         r = C.c_double()
         ad, bd = a.desc(), b.desc()
@@ -320,6 +340,18 @@ class Krylov:
         self.steps += 1
         return np.array(g[:]), np.array(t[:]), float(b.value)
 
+    def ritz_vector(self, a: int = 0) -> DeviceMPS:
+        """The a-th Ritz vector (ascending Ritz values) of the steps taken."""
+        out = DeviceMPS(self.ctx.n, max(capacity(self.ctx.n, self.opts.D_max), 1), self.ctx.device)
+        od = out.desc()
+        _check(self.ctx.lib.krylov_ritz_vector(self.h, int(a), C.byref(od), _stream()))
+        return out._written(od)
+
+    def restart(self, a: int = 0):
+        """Restart from the a-th Ritz vector: a new Krylov space of up to K vectors."""
+        _check(self.ctx.lib.krylov_restart(self.h, int(a), _stream()))
+        self.steps = 0
+
     def vector(self, i: int, D: int) -> DeviceMPS:
         out = DeviceMPS(self.ctx.n, max(capacity(self.ctx.n, D), 1), self.ctx.device)
         od = out.desc()
@@ -345,3 +377,30 @@ class Krylov:
             self.close()
         except Exception:
             pass
+
+
+class ThcEnergy(torch.autograd.Function):
+    """E(chi, zeta) = <psi|H|psi> for a fixed MPS psi and one-body t, with the
+    hand-written adjoint of thc_energy_gradient as its backward.  chi (L x N)
+    and zeta (N x N) are float64 tensors (any device); the factors are loaded
+    into a fresh context on every call."""
+
+    @staticmethod
+    def forward(fctx, chi, zeta, t, psi, prec="f64"):
+        c = Context(np.asarray(t, dtype=np.float64), chi.detach().double().cpu().numpy(),
+                    zeta.detach().double().cpu().numpy(), device=psi.buf.device)
+        e, dchi, dzeta = c.energy_gradient(psi, prec)
+        c.close()
+        fctx.save_for_backward(torch.from_numpy(dchi).to(chi.device, chi.dtype),
+                               torch.from_numpy(dzeta).to(zeta.device, zeta.dtype))
+        return torch.tensor(e, dtype=chi.dtype, device=chi.device)
+
+    @staticmethod
+    def backward(fctx, g):
+        dchi, dzeta = fctx.saved_tensors
+        return g * dchi, g * dzeta, None, None, None
+
+
+def thc_energy(chi, zeta, t, psi: DeviceMPS, prec="f64"):
+    """Differentiable E = <psi|H(t, chi, zeta)|psi> (see ThcEnergy)."""
+    return ThcEnergy.apply(chi, zeta, t, psi, prec)

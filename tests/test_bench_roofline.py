@@ -58,3 +58,39 @@ def test_more_than_one_gpu_exits_with_a_message():
     assert p.returncode != 0
     assert "one GPU" in p.stderr
     assert p.stdout.strip() == ""
+
+
+def test_model_flops_reproduce_the_flop_model_of_the_scope():
+    # LAPACK-formula model of one compressed H|psi> at L = 20, N = 80, D = 256:
+    # 110.1 GFLOP per layer-compression (QR 21.3, absorb L 13.0, SVD 69.4,
+    # absorb S V^T 6.4), 8.51 PFLOP per H|psi> over 51,600 layer- and 25,640
+    # add-compressions
+    import bench
+    n = 40
+    chi = [min(2 ** j, 2 ** (n - j), 256) for j in range(n + 1)]
+    doubled = [1] + [2 * x for x in chi[1:-1]] + [1]
+    assert abs(bench.model_compress_flops(doubled, 256) / 1e9 - 110.13) < 0.01
+    assert abs(bench.model_flops_per_H(20, 80, 256) / 1e15 - 8.507) < 0.001
+    # an untruncated compression of a 4-site MPS by hand: bonds (1, 2, 4, 2, 1)
+    # LQ: site 3 (2 x 2 -> 2*(2*2*4 - 2*8/3)), site 2 (4 x 4), site 1 (2 x 8)
+    fl = bench.model_compress_flops([1, 2, 4, 2, 1], 16)
+    assert fl > 0
+
+
+def test_one_stage_sytrd_stream_bytes():
+    import bench
+    # m = 4: trailing sizes 3, 2 (columns 0, 1): 6 + 3 entries, no second panel
+    assert bench.one_stage_sytrd_bytes(4) == 8.0 * (6 + 3)
+    assert abs(bench.one_stage_sytrd_bytes(512) / 1e6 - 200.74) < 0.01
+
+
+def test_tridiagonalisation_at_the_method_bytes_is_alu_bound():
+    # the method's bytes of a 512 x 512 tridiagonalisation (m^2 + 3m doubles)
+    # against 4m^3/3 flops: ~85 flop/B, above the ridge, so the kernel is
+    # measured against the FP64 vector-ALU peak in TFLOP/s
+    m, nb = 512, 512
+    fl, by = 4.0 / 3.0 * m ** 3 * nb, 8.0 * (m * m + 3 * m) * nb
+    r = bench.roofline_of(*_stats(sytrd=(16.0, fl, by, 1), lq=(10.0, 1e12, 1e9, 1)))
+    assert r["_class"] == "sytrd" and r["bound"] == "alu" and r["unit"] == "TFLOP/s"
+    assert r["peak"] == pytest.approx(bench.FP64_VALU_PEAK_TFLOPS, rel=1e-3)
+    assert r["frac"] == pytest.approx(fl / 16e-3 / 1e12 / bench.FP64_VALU_PEAK_TFLOPS, rel=1e-3)

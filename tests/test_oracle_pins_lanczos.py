@@ -231,3 +231,25 @@ def test_thin_svd_both_drivers_reconstruct():
         ev = np.sort(np.linalg.eigvalsh(a.T @ a))[::-1]
         assert np.allclose(s[:5], np.sqrt(ev[:5]), rtol=1e-12, atol=0)
         assert np.all(s[5:] < 1e-13 * s[0])
+
+
+def test_hartree_fock_krylov_vectors_have_degenerate_schmidt_pairs():
+    # spin-free H and a closed-shell start: the Krylov vectors are spin-flip
+    # symmetric, so at bonds between spatial orbitals (even bond index) the
+    # Schmidt values come in exactly degenerate pairs; a truncation cut can
+    # fall inside such a pair, where the truncated state is not unique
+    # (reading A6)
+    from oracle import lanczos as OL
+    L, N = 4, 8
+    t, chi, zeta = synth.thc_factors(np.random.default_rng(0), L, N)
+    hf = synth.occupation_mps_tensors(synth.hartree_fock_occupation(L, 4))
+    st = OL.KrylovState(hf, 2)
+    OL.krylov_step(st, t, chi, zeta, D=64)
+    sv = M.schmidt_values(st.v[1])
+    pairs = 0
+    for bond, s in enumerate(sv, start=1):
+        s = s[s > 1e-12 * s[0]]
+        ties = int(np.sum(np.abs(np.diff(s)) < 1e-10 * s[0]))
+        if bond % 2 == 0:
+            pairs += ties
+    assert pairs >= 3
