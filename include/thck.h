@@ -216,6 +216,18 @@ thc_status mps_sum_compress(thc_ctx *ctx, int32_t k, const double *coeffs, const
 thc_status mps_overlap(thc_ctx *ctx, const thc_mps *a, const thc_mps *b, double *result,
                        void *hip_stream);
 
+/* Allocation-free <a|b>, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same transfer-matrix chain as mps_overlap, FP64; writes the
+ * value to *result_dev (device memory) on the given stream and returns
+ * without synchronising.  Needs no context.  The transfer matrices live in a
+ * file-scope device array of 4 * 512^2 + 64 doubles (8 MiB) per GPU, which
+ * the library holds until the process ends: bonds above 512 return
+ * THC_ECAPACITY with nothing launched.  All calls on one GPU share that
+ * array, so calls that overlap on one GPU (other streams, other threads)
+ * race; a later call simply overwrites it. */
+thc_status mps_overlap_noalloc(const thc_mps *a, const thc_mps *b, double *result_dev, void *hip_stream);
+
 /* Lanczos state (Sec. 2.2): Krylov vectors v_0..v_K, the H images w_i,
  * M_ij = <v_i|w_j> and S_ij = <v_i|v_j>, all in device memory owned by the
  * state.  krylov_create copies psi0 and normalises it. */

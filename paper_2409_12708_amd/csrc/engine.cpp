@@ -18,6 +18,7 @@
 #include <chrono>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1757,6 +1758,67 @@ thc_status mps_overlap(thc_ctx *ctx, const thc_mps *a, const thc_mps *b, double 
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(result, E, sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+  });
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Allocation-free overlap: the transfer matrices of the chain live in a
+// file-scope device array (one copy per GPU), found through
+// hipGetSymbolAddress once per device.
+// ===========================================================================
+namespace {
+constexpr int NOALLOC_MAX_BOND = 512;
+// E, E' (b x b) and F (b x 2b) of the chain, plus padding
+constexpr int64_t NOALLOC_SCRATCH_ELEMS = (int64_t)4 * NOALLOC_MAX_BOND * NOALLOC_MAX_BOND + 64;
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_ELEMS];
+
+// Device address of this GPU's scratch (the array's name is a host-side
+// stand-in in host code and must not be passed to a kernel).
+double *scratch_ptr() {
+  constexpr int MAX_DEV = 64;
+  static std::mutex mu;
+  static double *ptrs[MAX_DEV] = {};
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEV) raise(THC_EDEVICE, "device index out of range for the scratch table");
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptrs[dev]) {
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr) throw HipError{e, "hipGetSymbolAddress(scratch)"};
+    ptrs[dev] = static_cast<double *>(p);
+  }
+  return ptrs[dev];
+}
+}  // namespace
+
+extern "C" {
+
+thc_status mps_overlap_noalloc(const thc_mps *a, const thc_mps *b, double *result_dev, void *hip_stream) {
+  return run_guarded([&] {
+    check_mps(a, 0);
+    check_mps(b, a->n_sites);
+    if (!result_dev) raise(THC_EINVAL, "result_dev is NULL");
+    const int n = a->n_sites;
+    int maxb = 1;
+    for (int j = 0; j <= n; ++j) maxb = std::max(maxb, std::max(a->bonds[j], b->bonds[j]));
+    if (maxb > NOALLOC_MAX_BOND) raise(THC_ECAPACITY, "bond dimension above 512, the limit of the allocation-free overlap's scratch");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int64_t sz = (int64_t)maxb * maxb;
+    double *W = scratch_ptr();
+    double *E = W, *E2 = W + sz, *F = W + 2 * sz;
+    launch_fill(s, 1, E, 0, 1, 1.0);  // E_0 = [1]; nothing else is read before it is written
+    for (int j = 0; j < n; ++j) {
+      const int la = a->bonds[j], ra = a->bonds[j + 1], lb = b->bonds[j], rb = b->bonds[j + 1];
+      const double *Aj = a->data + a->offsets[j], *Bj = b->data + b->offsets[j];
+      launch_gemm_f64_fixed(s, 0, E, lb, Bj, 2 * rb, F, 2 * rb, la, 2 * rb, lb);
+      launch_gemm_f64_fixed(s, GEMM_TA, Aj, ra, F, rb, E2, rb, ra, rb, 2 * la);
+      std::swap(E, E2);
+    }
+    launch_copy(s, 1, E, 0, result_dev, 0, 1);
+    HIPCHK(hipGetLastError());
   });
 }
 

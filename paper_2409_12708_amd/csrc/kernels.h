@@ -40,6 +40,11 @@ constexpr int GEMM_F64 = 0, GEMM_F32 = 1, GEMM_BF16X3 = 2;
 void launch_gemm(hipStream_t st, int nb, int mode, const double *A, int64_t sA, int lda, const double *B,
                  int64_t sB, int ldb, double *C, int64_t sC, int ldc, int M, int N, int K, double alpha = 1.0,
                  double beta = 0.0, int prec = GEMM_F64, const int *only = nullptr);
+// One FP64 job (mode 0 or GEMM_TA) with the default 64 x 64 tiles: never
+// consults or updates the tile autotuner, so it creates no event, never
+// synchronises and shares no host state between threads.
+void launch_gemm_f64_fixed(hipStream_t st, int mode, const double *A, int lda, const double *B, int ldb, double *C,
+                           int ldc, int M, int N, int K);
 void launch_transpose(hipStream_t st, int nb, const double *src, int64_t ss, int r, int c, double *dst, int64_t sd);
 // LQ of X (m x n), k = min(m, n): L (m x k, row stride ldl), Q (k x n, row
 // stride ldq).  With tr, X is given transposed (n x m row-major) and Q is

@@ -2498,6 +2498,15 @@ void launch_gemm(hipStream_t st, int nb, int mode, const double *A, int64_t sA, 
   }
 }
 
+void launch_gemm_f64_fixed(hipStream_t st, int mode, const double *A, int lda, const double *B, int ldb, double *C,
+                           int ldc, int M, int N, int K) {
+  if (M <= 0 || N <= 0) return;
+  if (mode == GEMM_TA)
+    gemm_tile<GEMM_TA, GEMM_F64, 64>(st, 1, A, 0, lda, B, 0, ldb, C, 0, ldc, M, N, K, 1.0, 0.0, nullptr);
+  else
+    gemm_tile<0, GEMM_F64, 64>(st, 1, A, 0, lda, B, 0, ldb, C, 0, ldc, M, N, K, 1.0, 0.0, nullptr);
+}
+
 int lq_t_stride(int k) {
   const int NB = 16;
   return ((k + NB - 1) / NB) * (NB * NB + NB);  // covers both LQ kernels (k_lq2 uses NB*NB per panel)

@@ -90,7 +90,7 @@ EXPORTS = [
     "thc_default_opts", "thc_mps_capacity", "thc_load_factors", "thc_destroy", "mps_apply_thc_H",
     "mps_sum_compress", "mps_overlap", "krylov_create", "krylov_destroy", "krylov_step",
     "krylov_get_vector", "krylov_get_matrices", "mps_compress", "mps_apply_layer", "thc_last_error",
-    "krylov_ritz_vector", "krylov_restart", "thc_energy_gradient",
+    "krylov_ritz_vector", "krylov_restart", "thc_energy_gradient", "mps_overlap_noalloc",
 ]
 
 _lib = None
@@ -127,13 +127,14 @@ def load_library(path: str = LIB_PATH):
                                     P(ThcStats), vp]
     lib.krylov_ritz_vector.argtypes = [vp, C.c_int32, P(ThcMps), vp]
     lib.krylov_restart.argtypes = [vp, C.c_int32, vp]
+    lib.mps_overlap_noalloc.argtypes = [P(ThcMps), P(ThcMps), vp, vp]
     lib.thc_energy_gradient.argtypes = [vp, P(ThcMps), C.c_int32, P(C.c_double), P(C.c_double), P(C.c_double), vp]
     lib.thc_last_error.argtypes = []
     lib.thc_last_error.restype = C.c_char_p
     for name in ("thc_load_factors", "thc_destroy", "mps_apply_thc_H", "mps_sum_compress", "mps_overlap",
                  "krylov_create", "krylov_destroy", "krylov_step", "krylov_get_vector", "krylov_get_matrices",
                  "mps_compress", "mps_apply_layer", "krylov_ritz_vector", "krylov_restart",
-                 "thc_energy_gradient"):
+                 "thc_energy_gradient", "mps_overlap_noalloc"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
