@@ -45,8 +45,9 @@ FP64_MFMA_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix peak (vendor figure)
 HBM_PEAK_GBS = 8000.0         # MI355X HBM3E peak bandwidth (vendor figure)
 # FP64 vector ALU peak: 256 CUs x 4 SIMDs x 16 FP64 FMA lanes x 2 flops x 2.4 GHz
 FP64_VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
-# kernel classes whose arithmetic runs on the vector ALUs (the rest on MFMA)
-VALU_KERNELS = ("sytrd", "tri_eig")
+# kernel classes whose arithmetic runs on the vector ALUs (the rest on MFMA;
+# the tridiagonalisation class is the two-stage route's MFMA band reduction)
+VALU_KERNELS = ("tri_eig", "sb2st", "q2")
 SLICE_N = 8          # THC rank of the mixed-vs-FP64 slice
 PLAIN_SAMPLES = 4    # leaf layer-compressions timed one job per launch
 
@@ -59,20 +60,23 @@ def elapsed():
     return time.monotonic() - T_START
 
 
-KERNEL_FN = {"lq": "k_lq2", "sytrd": "k_sytrd", "tri_eig": "k_tri_eig", "ormtr": "k_ormtr2", "gemm": "k_gemm_mfma"}
+KERNEL_FN = {"lq": "k_lq2", "sytrd": "k_sy2sb", "tri_eig": "k_tri_eig", "ormtr": "k_ormtr2", "gemm": "k_gemm_mfma",
+             "sb2st": "k_sb2st", "q2": "k_q2apply"}
+KERNEL_SOURCES = ("kernels.hip", "band.hip")
 
 
 def kernel_digest(fn: str):
     """SHA-256 of a kernel's source text (from its signature line to its closing brace)."""
     import hashlib
-    path = os.path.join(ROOT, "paper_2409_12708_amd", "csrc", "kernels.hip")
-    src = open(path).read().splitlines()
-    try:
-        i = next(k for k, l in enumerate(src) if f"void {fn}(" in l)
-        j = next(k for k in range(i, len(src)) if src[k] == "}")
-    except StopIteration:
-        return None
-    return hashlib.sha256("\n".join(src[i:j + 1]).encode()).hexdigest()
+    for name in KERNEL_SOURCES:
+        src = open(os.path.join(ROOT, "paper_2409_12708_amd", "csrc", name)).read().splitlines()
+        try:
+            i = next(k for k, l in enumerate(src) if f"void {fn}(" in l)
+            j = next(k for k in range(i, len(src)) if src[k] == "}")
+        except StopIteration:
+            continue
+        return hashlib.sha256("\n".join(src[i:j + 1]).encode()).hexdigest()
+    return None
 
 
 def measured_traffic(kernel: str, workload: str, algorithmic_bytes_per_launch: float):
@@ -90,7 +94,10 @@ def measured_traffic(kernel: str, workload: str, algorithmic_bytes_per_launch: f
     return int(rec["measured_over_algorithmic"] * algorithmic_bytes_per_launch)
 
 
-KERNEL_LABEL = {"lq": "k_lq2 (Householder LQ with Q, FP64)", "sytrd": "k_sytrd (tridiagonalisation, FP64)",
+KERNEL_LABEL = {"lq": "k_lq2 (Householder LQ with Q, FP64)",
+                "sytrd": "k_sy2sb (tridiagonalisation: band reduction, FP64 MFMA)",
+                "sb2st": "k_sb2st (tridiagonalisation: band chase, FP64)",
+                "q2": "k_q2apply (band-chase back-transformation, FP64)",
                 "tri_eig": "k_tri_eig (bisection + inverse iteration, FP64)",
                 "ormtr": "k_ormtr2 (eigenvector back-transformation, FP64)", "gemm": "k_gemm_mfma (FP64)",
                 "svd_fallback": "second Gram level of the SVD (jobs at the noise floor)"}
@@ -180,6 +187,27 @@ def one_stage_sytrd_bytes(m: int, nb: int = 8) -> float:
     for i in range(m - 2):
         s = m - i - 1
         el += 0.5 * s * (s + 1.0) * (2.0 if (i > 0 and i % nb == 0) else 1.0)
+    return 8.0 * el
+
+
+def two_stage_sy2sb_bytes(m: int, bw: int = 16) -> float:
+    """Bytes the band reduction streams for an m x m matrix: per panel of bw
+    columns the trailing upper triangle (16 x 16 tiles, diagonal tiles whole)
+    read and written by the update, the panel read and written, and the next
+    trailing triangle read by the product."""
+    def tri(n):
+        t = -(-n // 16)
+        return t * (t + 1) / 2 * 256.0
+    el = 0.0
+    c0 = 0
+    while True:
+        if c0 > 0:
+            el += 2.0 * tri(m - c0)
+        r0 = c0 + bw
+        if m - r0 < 2:
+            break
+        el += 2.0 * bw * (m - r0) + tri(m - r0)
+        c0 += bw
     return 8.0 * el
 
 
@@ -411,8 +439,9 @@ def main():
         roofline["traffic_over_algorithmic"] = round(traffic / max(roofline["algorithmic_bytes_per_launch"], 1), 2)
     if dom == "sytrd":
         roofline["note"] = ("flops 4m^3/3 and bytes m^2 + 3m doubles per m x m matrix (the method's); the "
-                            "one-stage kernel streams the trailing triangle once per column, "
-                            f"{one_stage_sytrd_bytes(512) / 1e6:.1f} MB per 512 x 512 matrix")
+                            "two-stage band reduction streams the trailing triangle three times per panel of 16 "
+                            f"columns, {two_stage_sy2sb_bytes(512) / 1e6:.1f} MB per 512 x 512 matrix (the "
+                            f"one-stage kernel {one_stage_sytrd_bytes(512) / 1e6:.1f} MB)")
     executed = sum(st.flops_model for st in stats)
     n_comp = sum(st.n_compressions for st in stats)
     model_h = model_flops_per_H(L, N, D)

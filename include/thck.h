@@ -119,9 +119,14 @@ typedef struct {
  * back-transformation reads the reflectors (m^2/2) and Z and writes U;
  * bisection/inverse iteration reads d, e and writes the k vectors;
  * tridiagonalisation reads the upper triangle once and writes the
- * reflectors over it and d, e, tau (m^2 + 3m doubles; the one-stage kernel
- * of this library re-reads the trailing triangle once per column, which
- * only the measured traffic shows).  A launch that skips some of its jobs (the
+ * reflectors over it and d, e, tau (m^2 + 3m doubles; the kernels of this
+ * library re-read the trailing triangle, once per column in one stage,
+ * three times per 16 columns in two, which only the measured traffic
+ * shows).  The band chase of the two-stage route counts ~3072 flops and 16
+ * doubles of reflector per chase step (sweep j of an m x m band takes
+ * (m-3-j)/16 + 1 steps) plus its band in and d, e out; the application of
+ * its reflectors to k vectors 64 k flops per step, reading them and
+ * reading and writing the vectors.  A launch that skips some of its jobs (the
  * LQ re-orthonormalisation of the truncation step, run only where the
  * eigensolver's vectors need it) is counted as if every job ran; the
  * second Gram level's launches are timed in their own class with no flops or
@@ -135,14 +140,24 @@ typedef struct {
  * THC_FLAG_TIME_KERNELS.  Results are the same as without it. */
 #define THC_FLAG_GRAPHS 4ull
 
+/* opts.flags: tridiagonalise the Gram matrices of the SVD step in one stage
+ * (Householder, one column at a time) instead of the default two stages
+ * (blocked reduction to a band of half-bandwidth 16, then Householder bulge
+ * chasing of the band, with the chase's reflectors applied to the
+ * eigenvectors before those of the band reduction).  Both give the same
+ * eigenpairs to rounding. */
+#define THC_FLAG_SYTRD_ONE_STAGE 8ull
+
 enum {
   THC_K_LQ = 0,      /* Householder LQ with Q formation (canonical sweep and re-orthonormalisation) */
-  THC_K_SYTRD = 1,   /* tridiagonalisation of the Gram matrix */
+  THC_K_SYTRD = 1,   /* tridiagonalisation of the Gram matrix (two-stage route: its band reduction) */
   THC_K_TRI_EIG = 2, /* bisection + inverse iteration */
   THC_K_ORMTR = 3,   /* back-transformation of the eigenvectors */
   THC_K_GEMM = 4,    /* batched GEMMs of the compression */
   THC_K_SVD_FALLBACK = 5, /* second Gram level of the jobs at the noise floor (time only; flops not counted) */
-  THC_NK = 6
+  THC_K_SB2ST = 6,   /* two-stage route: bulge chasing of the band to tridiagonal form */
+  THC_K_Q2 = 7,      /* two-stage route: the chase's reflectors applied to the eigenvectors */
+  THC_NK = 8
 };
 
 typedef struct {

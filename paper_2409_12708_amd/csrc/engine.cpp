@@ -264,11 +264,12 @@ struct Plan {
   Profile out;
   // per-job workspace layout (elements)
   int64_t oB = 0, oT = 0, oL = 0, oQs = 0, oM = 0, oY = 0, oW = 0, oZ = 0, oC = 0, oLz = 0, oQz = 0, oTf = 0,
-          oS = 0, oU = 0, oG = 0, oDet = 0, oDet2 = 0, oZm = 0, oLam = 0, oScr = 0, oTo = 0;
+          oS = 0, oU = 0, oG = 0, oDet = 0, oDet2 = 0, oZm = 0, oLam = 0, oScr = 0, oTo = 0, oV2 = 0;
   int64_t sv = 0;  // stride of the d / e / tau vectors inside oDet
   std::vector<int64_t> qs_off;  // offset of Q_j inside Qs
   int64_t per_job = 0;
   double flops_per_job = 0.0;
+  double flops_two_stage_per_job = 0.0;  // the band chase and its back-transformation (two-stage route only)
 };
 
 double lq_flops(double m, double n) {  // LQ of m x n (m rows): R + thin Q, LAPACK counts, FMA = 2
@@ -280,6 +281,19 @@ double lq_flops(double m, double n) {  // LQ of m x n (m rows): R + thin Q, LAPA
 // d, e and tau written.  (The one-stage kernel re-reads the trailing
 // triangle once per column; that excess shows in the measured traffic.)
 double sytrd_bytes(int m) { return 8.0 * ((double)m * m + 3.0 * m); }
+
+// Two-stage route: reflectors of the band chase (sweep j has (m-3-j)/16 + 1
+// of at most 16 entries), each applied two-sided to its 16 x 16 blocks
+// (~3072 flops) and, in the back-transformation, to kk vectors (4 x 16 kk).
+double chase_steps(int m) {
+  double s = 0.0;
+  for (int x = 0; x <= m - 3; ++x) s += x / 16 + 1;
+  return s;
+}
+double sb2st_flops(int m) { return 3072.0 * chase_steps(m); }
+double sb2st_bytes(int m) { return 8.0 * (19.0 * m + 16.0 * chase_steps(m)); }
+double q2_flops(int m, int kk) { return 64.0 * kk * chase_steps(m); }
+double q2_bytes(int m, int kk) { return 8.0 * (2.0 * m * (double)kk + 16.0 * chase_steps(m)); }
 
 Plan make_plan(int kind, const Profile &pa, const Profile *pb, int D, bool rc_in = false) {
   Plan P;
@@ -322,7 +336,7 @@ Plan make_plan(int kind, const Profile &pa, const Profile *pb, int D, bool rc_in
   P.out.b = P.k;
   P.out.pack();
   int64_t mB = 0, mT = 0, mL = 0, mM = 0, mW = 0, mZ = 0, mQz = 0, mLz = 0, mS = 0, mTf = 0, mU = 0, mG = 0,
-          mZm = 0, mScr = 0, mTo = 0;
+          mZm = 0, mScr = 0, mTo = 0, mV2 = 0;
   P.qs_off.assign(n, 0);
   int64_t qs = 0;
   double fl = 0.0;
@@ -361,6 +375,8 @@ Plan make_plan(int kind, const Profile &pa, const Profile *pb, int D, bool rc_in
       mZm = std::max(mZm, (int64_t)m * kk);
       mScr = std::max(mScr, tri_eig_scratch(m, kk));
       mTo = std::max(mTo, ormtr_tf_stride(m));
+      mV2 = std::max(mV2, sb2st_v2_stride(m));
+      P.flops_two_stage_per_job += sb2st_flops(m) + q2_flops(m, kk);
       // the Gram route of the SVD as it runs: G = Y Y^T (upper half),
       // tridiagonalisation, back-transformation of kk vectors, one
       // Newton-Schulz step (Z^T Z and Z (Z^T Z)), C = Q^T Y
@@ -399,6 +415,7 @@ Plan make_plan(int kind, const Profile &pa, const Profile *pb, int D, bool rc_in
   P.oLam = take(std::max<int64_t>(mS, 1));
   P.oScr = take(std::max<int64_t>(mScr, 1));
   P.oTo = take(std::max<int64_t>(mTo, 1));
+  P.oV2 = take(std::max<int64_t>(mV2, 1));
   if (P.mode == 1) {
     P.sLt = std::max<int64_t>(P.sLt, 1);
     P.oLt = take(2 * ((P.sLt + 31) / 32 * 32));
@@ -579,6 +596,25 @@ struct Engine {
     timed(THC_K_SYTRD, 4.0 / 3.0 * m * (double)m * m * nb, sytrd_bytes(m) * nb, ShapeKey{THC_K_SYTRD, nb, m, m, 0, 0}, [&] { rc = launch_sytrd(st, nb, A, sA, m, d, e, tau, sv); });
     return rc;
   }
+  // the two-stage route (default): sy2sb timed as the tridiagonalisation
+  // (its flops and bytes), then the band chase
+  bool two_stage() const { return (o.flags & THC_FLAG_SYTRD_ONE_STAGE) == 0; }
+  int tridiag2(int nb, double *A, int64_t sA, int m, double *d, double *e, double *tau, int64_t sv, double *V2,
+               int64_t sV2) {
+    int rc = 0;
+    timed(THC_K_SYTRD, 4.0 / 3.0 * m * (double)m * m * nb, sytrd_bytes(m) * nb, ShapeKey{THC_K_SYTRD, nb, m, m, 0, 1},
+          [&] { rc = launch_sy2sb(st, nb, A, sA, m, tau, sv); });
+    if (rc != 0) return rc;
+    timed(THC_K_SB2ST, sb2st_flops(m) * nb, sb2st_bytes(m) * nb, ShapeKey{THC_K_SB2ST, nb, m, m, 0, 0},
+          [&] { rc = launch_sb2st(st, nb, A, sA, m, d, e, sv, V2, sV2); });
+    return rc;
+  }
+  int q2(int nb, const double *V2, int64_t sV2, int m, double *Z, int64_t sZ, int kk) {
+    int rc = 0;
+    timed(THC_K_Q2, q2_flops(m, kk) * nb, q2_bytes(m, kk) * nb, ShapeKey{THC_K_Q2, nb, m, kk, 0, 0},
+          [&] { rc = launch_q2apply(st, nb, V2, sV2, m, Z, sZ, kk); });
+    return rc;
+  }
   int tri_eig(int nb, const double *d, const double *e, int64_t sv, int m, int kk, double *Z, int64_t sZ, double *lam,
               int64_t sl, double *scr, int64_t sscr, int *needs_lq = nullptr) {
     int rc = 0;
@@ -586,10 +622,10 @@ struct Engine {
     return rc;
   }
   int ormtr(int nb, const double *A, int64_t sA, int m, const double *tau, int64_t sv, double *Z, int64_t sZ, int kk,
-            double *Ut, int64_t sU, bool zout, double *Tf, int64_t sTf) {
+            double *Ut, int64_t sU, bool zout, double *Tf, int64_t sTf, int off = 1) {
     int rc = 0;
-    timed(THC_K_ORMTR, 2.0 * m * (double)m * kk * nb, 8.0 * nb * (0.5 * m * (double)m + 2.0 * m * (double)kk), ShapeKey{THC_K_ORMTR, nb, m, kk, 0, zout ? 1 : 0},
-          [&] { rc = launch_ormtr(st, nb, A, sA, m, tau, sv, Z, sZ, kk, Ut, sU, zout, Tf, sTf); });
+    timed(THC_K_ORMTR, 2.0 * m * (double)m * kk * nb, 8.0 * nb * (0.5 * m * (double)m + 2.0 * m * (double)kk), ShapeKey{THC_K_ORMTR, nb, m, kk, off, zout ? 1 : 0},
+          [&] { rc = launch_ormtr(st, nb, A, sA, m, tau, sv, Z, sZ, kk, Ut, sU, zout, Tf, sTf, nullptr, off); });
     return rc;
   }
 
@@ -811,8 +847,9 @@ struct Engine {
     }
     // ---- left -> right SVD sweep ----
     double *Gb = W + P.oG, *Db = W + P.oDet, *Eb = Db + P.sv, *Taub = Db + 2 * P.sv, *Zm = W + P.oZm,
-           *Lam = W + P.oLam, *Scr = W + P.oScr;
+           *Lam = W + P.oLam, *Scr = W + P.oScr, *V2b = W + P.oV2;
     const bool jacobi = (o.flags & THC_FLAG_SVD_JACOBI) != 0;
+    const bool ts = two_stage();
     // sweep counts start at zero: the Gram route leaves them there except
     // for the jobs it hands to Jacobi (a fill kernel, not a memset node,
     // should the caller capture the stream into a graph)
@@ -859,11 +896,16 @@ struct Engine {
         // Gram G = Y Y^T, Y = M_j (m x nc)
         // (the tridiagonalisation reads the upper triangle only)
         gemm(nb, GEMM_TB | GEMM_UPPER, Mb, S, nc, Mb, S, nc, Gb, S, m, m, m, nc);
-        if (sytrd(nb, Gb, S, m, Db, Eb, Taub, S) != 0) raise(THC_EINVAL, "site matrix too tall for sytrd");
+        // (two-stage: G -> band -> tridiagonal; else one stage)
+        if ((ts ? tridiag2(nb, Gb, S, m, Db, Eb, Taub, S, V2b, S) : sytrd(nb, Gb, S, m, Db, Eb, Taub, S)) != 0)
+          raise(THC_EINVAL, "site matrix too tall for the tridiagonalisation");
         if (tri_eig(nb, Db, Eb, S, m, kk, Zm, S, Lam, S, Scr, S, nl_d) != 0)
           raise(THC_EINVAL, "site matrix too tall for the tridiagonal eigensolver");
-        // eigenvectors as the columns of Z (m x kk)
-        if (ormtr(nb, Gb, S, m, Taub, S, Zm, S, kk, Zb, S, true, W + P.oTo, S) != 0) raise(THC_EINVAL, "ormtr size");
+        // eigenvectors as the columns of Z (m x kk): the chase's reflectors,
+        // then those of the band reduction (or of the one-stage reduction)
+        if (ts && q2(nb, V2b, S, m, Zm, S, kk) != 0) raise(THC_EINVAL, "site matrix too tall for the band chase");
+        if (ormtr(nb, Gb, S, m, Taub, S, Zm, S, kk, Zb, S, true, W + P.oTo, S, ts ? 16 : 1) != 0)
+          raise(THC_EINVAL, "ormtr size");
         // orthonormal columns spanning the top-kk eigenvectors, Qz (m x kk).
         // Inverse iteration returns them orthonormal to rounding except where
         // the eigensolver flags the job (completions below its noise floor, a
@@ -1012,7 +1054,7 @@ struct Engine {
     ++batch_counter;
     cs.compressions += nb;
     cs.launches += launches;
-    cs.flops += P.flops_per_job * nb;
+    cs.flops += (P.flops_per_job + (two_stage() ? P.flops_two_stage_per_job : 0.0)) * nb;
   }
   // THCK_PROGRESS=1: a line on stderr after a compression batch, at most
   // every 30 s, so that long calls show that they advance

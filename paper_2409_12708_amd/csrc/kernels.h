@@ -90,9 +90,21 @@ int launch_tri_eig(hipStream_t st, int nb, const double *d, const double *e, int
 // U = Q_H Z; written as rows of Ut (kk x m), or with zout as Z itself (m x kk).
 // Tf: workspace for the blocks' compact-WY factors, ormtr_tf_stride(m) per job.
 int64_t ormtr_tf_stride(int m);
+// off: row offset of the reflectors (1 after sytrd, 16 after sy2sb).
 int launch_ormtr(hipStream_t st, int nb, const double *A, int64_t sA, int m, const double *tau, int64_t sv, double *Z,
                  int64_t sZ, int kk, double *Ut, int64_t sU, bool zout, double *Tf, int64_t sTf,
+                 const int *only = nullptr, int off = 1);
+// Two-stage tridiagonalisation (band.hip), m <= 512.  sy2sb: A (upper
+// triangle) to half-bandwidth 16, reflectors for ormtr with off = 16 (tau
+// needs m entries).  sb2st: the band to d, e; the chase's reflectors into V2
+// (sb2st_v2_stride(m) doubles per job).  q2apply: Z (m x kk) <- Q2 Z.
+int launch_sy2sb(hipStream_t st, int nb, double *A, int64_t sA, int m, double *tau, int64_t sv,
                  const int *only = nullptr);
+int64_t sb2st_v2_stride(int m);
+int launch_sb2st(hipStream_t st, int nb, const double *A, int64_t sA, int m, double *d, double *e, int64_t sv,
+                 double *V2, int64_t sV2, const int *only = nullptr);
+int launch_q2apply(hipStream_t st, int nb, const double *V2, int64_t sV2, int m, double *Z, int64_t sZ, int kk,
+                   const int *only = nullptr);
 // Per-job flags of the Gram SVD step (see kernels.hip): jac = redo by Jacobi,
 // nl |= Householder re-orthonormalisation needed.
 void launch_svd_flags(hipStream_t st, int nb, const double *lam, int64_t sl, int kk, double tau, const double *Lz,

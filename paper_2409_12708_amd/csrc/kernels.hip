@@ -22,33 +22,10 @@
 #include <stdint.h>
 #include <type_traits>
 
+#include "device_util.h"
 #include "kernels.h"
 
 namespace thck {
-
-static constexpr int WAVE = 64;
-
-// Wave-wide reductions (all 64 lanes active; the result is returned in every
-// lane).  Within each row of 16 lanes, an inclusive scan by DPP row shifts of
-// 1, 2, 4, 8 (zeros shifted in) leaves the row total in lane 15 of the row;
-// the four row totals are then read with readlane.
-template <int CTRL>
-__device__ __forceinline__ double dpp_shift(double v, double fill) {
-  const int lo = __builtin_amdgcn_update_dpp(__double2loint(fill), __double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(fill), __double2hiint(v), CTRL, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ double read_lane(double v, int l) {
-  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
-                          __builtin_amdgcn_readlane(__double2loint(v), l));
-}
-__device__ __forceinline__ double wave_sum(double v) {
-  v += dpp_shift<0x111>(v, 0.0);  // row_shr:1
-  v += dpp_shift<0x112>(v, 0.0);  // row_shr:2
-  v += dpp_shift<0x114>(v, 0.0);  // row_shr:4
-  v += dpp_shift<0x118>(v, 0.0);  // row_shr:8
-  return (read_lane(v, 15) + read_lane(v, 31)) + (read_lane(v, 47) + read_lane(v, 63));
-}
 
 // Round-robin (circle method) schedule over P players (P even): in round r
 // the players are listed as [0, 1 + (r mod (P-1)), 1 + (r+1 mod (P-1)), ...]
@@ -59,15 +36,6 @@ __device__ __forceinline__ void rr_pair(int k, int r, int P, int &p, int &q) {
   p = rr_player(k, r, P);
   q = rr_player(P - 1 - k, r, P);
   if (p > q) { int t = p; p = q; q = t; }
-}
-
-__device__ __forceinline__ double wave_max(double v) {
-  // lanes shifted in from outside the row take the lane's own value
-  v = fmax(v, dpp_shift<0x111>(v, v));
-  v = fmax(v, dpp_shift<0x112>(v, v));
-  v = fmax(v, dpp_shift<0x114>(v, v));
-  v = fmax(v, dpp_shift<0x118>(v, v));
-  return fmax(fmax(read_lane(v, 15), read_lane(v, 31)), fmax(read_lane(v, 47), read_lane(v, 63)));
 }
 
 // ---------------------------------------------------------------------------
@@ -123,20 +91,10 @@ __global__ void k_construct(const CJob *__restrict__ jobs, int site, int n_sites
   }
 }
 
-// ---------------------------------------------------------------------------
-// MFMA FP64 helpers (v_mfma_f64_16x16x4f64 on gfx950).  Operand layouts:
-//   A (16x4):  lane l holds A[l%16][l/16]
-//   B (4x16):  lane l holds B[l/16][l%16]
-//   D (16x16): lane l, register r holds D[l/16 + 4r][l%16]
-// ---------------------------------------------------------------------------
-typedef double d4_t __attribute__((ext_vector_type(4)));
+// vector types of the FP32 / BF16 MFMA operands and of 64-bit buffer stores
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef short s4_t __attribute__((ext_vector_type(4)));
 typedef unsigned int u2_t __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ d4_t mfma16(double a, double b, d4_t c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
 
 // ---------------------------------------------------------------------------
 // gemm: C = op(A) * op(B), row-major FP64, batched.  A is M x K (lda), or
@@ -1293,7 +1251,8 @@ __global__ void k_ritz_vector(const double *__restrict__ Mm, const double *__res
 //   ormtr      U^T = Z^T Q_H^T, blocked compact-WY application
 // ---------------------------------------------------------------------------
 // ormtr_tfac: the forward compact-WY factor T of each block of 16 reflectors
-// left by sytrd (v_i[i+1] = 1, v_i[r] = A[i][r] for r >= i+2), so that
+// left by sytrd (off = 1) or by the band reduction sy2sb (off = 16):
+// v_i[i+off] = 1, v_i[r] = A[i][r] for r > i+off, so that
 // H_{i0} ... H_{i0+15} = I - V^T T V.  One workgroup per (block, matrix):
 // G[q][p] = v_q . v_p (q < p), then T[0:p, p] = -tau_p T[0:p, 0:p] G[0:p, p].
 // Output Tf[job][block] (16 x 16, row-major).
@@ -1301,7 +1260,7 @@ __global__ void k_ritz_vector(const double *__restrict__ Mm, const double *__res
 __global__ __launch_bounds__(256) void k_ormtr_tfac(const double *__restrict__ Ab, int64_t sA, int m,
                                                     const double *__restrict__ taub, int64_t sv,
                                                     double *__restrict__ Tfb, int64_t sTf,
-                                                    const int *__restrict__ only) {
+                                                    const int *__restrict__ only, int off) {
   constexpr int NB = 16, VL = 516;
   __shared__ double V[NB * VL];
   __shared__ double G[NB * NB], T[NB * NB], tv[NB];
@@ -1311,15 +1270,15 @@ __global__ __launch_bounds__(256) void k_ormtr_tfac(const double *__restrict__ A
   const double *tau = taub + (int64_t)job * sv;
   double *Tf = Tfb + (int64_t)job * sTf + (int64_t)bi * NB * NB;
   const int tid = threadIdx.x;
-  const int nref = m - 2, i0 = bi * NB;
+  const int nref = m - off - 1, i0 = bi * NB;
   const int pb = (nref - i0) < NB ? (nref - i0) : NB;
   for (int e = tid; e < NB * 512; e += 256) {
     const int q = e / 512, r = e % 512;
     const int i = i0 + q;
     double x = 0.0;
     if (q < pb && r < m) {
-      if (r == i + 1) x = 1.0;
-      else if (r > i + 1) x = A[(int64_t)i * m + r];
+      if (r == i + off) x = 1.0;
+      else if (r > i + off) x = A[(int64_t)i * m + r];
     }
     V[q * VL + r] = x;
   }
@@ -1329,7 +1288,7 @@ __global__ __launch_bounds__(256) void k_ormtr_tfac(const double *__restrict__ A
     const int q = tid / NB, p = tid % NB;
     double acc = 0.0;
     if (q < p)
-      for (int r = i0 + p + 1; r < m; ++r) acc += V[q * VL + r] * V[p * VL + r];
+      for (int r = i0 + p + off; r < m; ++r) acc += V[q * VL + r] * V[p * VL + r];
     G[tid] = acc;
   }
   __syncthreads();
@@ -1348,8 +1307,8 @@ __global__ __launch_bounds__(256) void k_ormtr_tfac(const double *__restrict__ A
 }
 
 // ---------------------------------------------------------------------------
-// ormtr2: U = Q_H Z = H_0 H_1 ... H_{m-3} Z for the reflectors left by
-// sytrd and m <= 512, with the blocks' T factors from ormtr_tfac.  Z is
+// ormtr2: U = Q_H Z = H_0 H_1 ... H_{m-off-2} Z for the reflectors left by
+// sytrd or sy2sb and m <= 512, with the blocks' T factors from ormtr_tfac.  Z is
 // cut into slabs of 64 columns, one workgroup (8 waves) per slab; wave w
 // keeps rows [64w, 64w + 64) of its slab in registers for the whole pass,
 // as 4 x 4 MFMA blocks in the accumulator layout (lane l, register r <->
@@ -1365,7 +1324,7 @@ __global__ __launch_bounds__(512) void k_ormtr2(const double *__restrict__ Ab, i
                                                 const double *__restrict__ Tfb, int64_t sTf,
                                                 const double *__restrict__ Zb, int64_t sZ, int kk,
                                                 double *__restrict__ Utb, int64_t sU, int nslab, int zout,
-                                                const int *__restrict__ only) {
+                                                const int *__restrict__ only, int off) {
   if (only != nullptr && only[blockIdx.x / nslab] == 0) return;  // job not selected
   constexpr int NB = 16, NWV = 8, CS = 64, VL = 516;
   extern __shared__ double lds[];
@@ -1394,7 +1353,7 @@ __global__ __launch_bounds__(512) void k_ormtr2(const double *__restrict__ Ab, i
         z[i][j][r] = (row < m && col < kk) ? Z[(int64_t)row * kk + col] : 0.0;
       }
 
-  const int nref = m - 2;
+  const int nref = m - off - 1;
   const int nblk = nref > 0 ? (nref + NB - 1) / NB : 0;
   for (int bi = nblk - 1; bi >= 0; --bi) {
     const int i0 = bi * NB;
@@ -1406,8 +1365,8 @@ __global__ __launch_bounds__(512) void k_ormtr2(const double *__restrict__ Ab, i
       const int i = i0 + q, r = tid;
       double x = 0.0;
       if (q < pb && r < m) {
-        if (r == i + 1) x = 1.0;
-        else if (r > i + 1) x = A[(int64_t)i * m + r];
+        if (r == i + off) x = 1.0;
+        else if (r > i + off) x = A[(int64_t)i * m + r];
       }
       V[q * VL + r] = x;
     }
@@ -2696,18 +2655,20 @@ int64_t ormtr_tf_stride(int m) {
 }
 
 int launch_ormtr(hipStream_t st, int nb, const double *A, int64_t sA, int m, const double *tau, int64_t sv, double *Z,
-                 int64_t sZ, int kk, double *Ut, int64_t sU, bool zout, double *Tf, int64_t sTf, const int *only) {
-  if (m > 512) return -1;
+                 int64_t sZ, int kk, double *Ut, int64_t sU, bool zout, double *Tf, int64_t sTf, const int *only,
+                 int off) {
+  if (m > 512 || off < 1) return -1;
   const int nslab = (kk + 63) / 64;
   if (nslab == 0 || nb <= 0) return 0;
-  const int nref = m - 2;
+  const int nref = m - off - 1;
   const int nblk = nref > 0 ? (nref + 15) / 16 : 0;
-  if (nblk > 0) hipLaunchKernelGGL(k_ormtr_tfac, dim3(nblk, nb), dim3(256), 0, st, A, sA, m, tau, sv, Tf, sTf, only);
+  if (nblk > 0)
+    hipLaunchKernelGGL(k_ormtr_tfac, dim3(nblk, nb), dim3(256), 0, st, A, sA, m, tau, sv, Tf, sTf, only, off);
   const size_t lds = (16 * 516 + 8 * 16 * 64 + 2 * 16 * 64 + 256) * sizeof(double);
   static bool attr = false;
   if (!attr) { set_lds(k_ormtr2, lds); attr = true; }
   hipLaunchKernelGGL(k_ormtr2, dim3(nb * nslab), dim3(512), lds, st, A, sA, m, Tf, sTf, Z, sZ, kk, Ut, sU, nslab,
-                     zout ? 1 : 0, only);
+                     zout ? 1 : 0, only, off);
   return 0;
 }
 

@@ -53,6 +53,9 @@ class ThcOpts(C.Structure):
     ]
 
 
+NK = 8  # kernel classes of thc_stats (THC_NK)
+
+
 class ThcStats(C.Structure):
     _fields_ = [
         ("discarded_weight_max", C.c_double),
@@ -63,14 +66,14 @@ class ThcStats(C.Structure):
         ("jacobi_sweeps_max", C.c_int32),
         ("nonconverged", C.c_int32),
         ("svd_fallbacks", C.c_int32),
-        ("kernel_ms", C.c_double * 6),
-        ("kernel_flops", C.c_double * 6),
-        ("kernel_launches", C.c_int64 * 6),
-        ("kernel_bytes", C.c_double * 6),
+        ("kernel_ms", C.c_double * NK),
+        ("kernel_flops", C.c_double * NK),
+        ("kernel_launches", C.c_int64 * NK),
+        ("kernel_bytes", C.c_double * NK),
         ("graph_captures", C.c_int64),
         ("graph_replays", C.c_int64),
     ]
-    KERNELS = ("lq", "sytrd", "tri_eig", "ormtr", "gemm", "svd_fallback")
+    KERNELS = ("lq", "sytrd", "tri_eig", "ormtr", "gemm", "svd_fallback", "sb2st", "q2")
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if not f.startswith("kernel_")}
@@ -85,6 +88,7 @@ class ThcStats(C.Structure):
 FLAG_SVD_JACOBI = 1      # one-sided Jacobi SVD in the truncation step
 FLAG_TIME_KERNELS = 2    # per-kernel-class device times / flops in ThcStats.kernels()
 FLAG_GRAPHS = 4          # compression batches captured into HIP graphs and replayed
+FLAG_SYTRD_ONE_STAGE = 8  # one-stage tridiagonalisation in the SVD step (default: two stages)
 
 EXPORTS = [
     "thc_default_opts", "thc_mps_capacity", "thc_load_factors", "thc_destroy", "mps_apply_thc_H",

@@ -9,7 +9,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 import bench  # noqa: E402
 
-NAMES = ("lq", "sytrd", "tri_eig", "ormtr", "gemm")
+NAMES = ("lq", "sytrd", "tri_eig", "ormtr", "gemm", "sb2st", "q2")
 
 
 def _stats(**per):
@@ -42,7 +42,7 @@ def test_compute_bound_kernel_goes_under_its_unit_peak():
     assert r["achieved"] == pytest.approx(2e12 / 20e-3 / 1e12, rel=1e-3)
     assert r["algorithmic_bytes_per_launch"] == int(1e10 / 4)
     # a vector-ALU class above the ridge is priced against the ALU peak
-    r = bench.roofline_of(*_stats(sytrd=(20.0, 2e12, 1e10, 4)))
+    r = bench.roofline_of(*_stats(sb2st=(20.0, 2e12, 1e10, 4)))
     assert r["bound"] == "alu" and r["peak"] == pytest.approx(bench.FP64_VALU_PEAK_TFLOPS, rel=1e-3)
 
 
@@ -84,13 +84,24 @@ def test_one_stage_sytrd_stream_bytes():
     assert abs(bench.one_stage_sytrd_bytes(512) / 1e6 - 200.74) < 0.01
 
 
-def test_tridiagonalisation_at_the_method_bytes_is_alu_bound():
+def test_tridiagonalisation_at_the_method_bytes_is_compute_bound():
     # the method's bytes of a 512 x 512 tridiagonalisation (m^2 + 3m doubles)
-    # against 4m^3/3 flops: ~85 flop/B, above the ridge, so the kernel is
-    # measured against the FP64 vector-ALU peak in TFLOP/s
+    # against 4m^3/3 flops: ~85 flop/B, above the ridge, so the band
+    # reduction (FP64 MFMA) is measured against the FP64 matrix peak in TFLOP/s
     m, nb = 512, 512
     fl, by = 4.0 / 3.0 * m ** 3 * nb, 8.0 * (m * m + 3 * m) * nb
     r = bench.roofline_of(*_stats(sytrd=(16.0, fl, by, 1), lq=(10.0, 1e12, 1e9, 1)))
-    assert r["_class"] == "sytrd" and r["bound"] == "alu" and r["unit"] == "TFLOP/s"
-    assert r["peak"] == pytest.approx(bench.FP64_VALU_PEAK_TFLOPS, rel=1e-3)
-    assert r["frac"] == pytest.approx(fl / 16e-3 / 1e12 / bench.FP64_VALU_PEAK_TFLOPS, rel=1e-3)
+    assert r["_class"] == "sytrd" and r["bound"] == "mfma" and r["unit"] == "TFLOP/s"
+    assert r["peak"] == pytest.approx(bench.FP64_MFMA_PEAK_TFLOPS, rel=1e-3)
+    assert r["frac"] == pytest.approx(fl / 16e-3 / 1e12 / bench.FP64_MFMA_PEAK_TFLOPS, rel=1e-3)
+
+
+def test_two_stage_band_reduction_stream_bytes():
+    # m = 34: panel 0 (rows 16..33: 18 x 16 panel, product over a 2 x 2
+    # tile triangle), then the update of A[16:, 16:] (2 x 2 tiles), then
+    # panel 1 has 2 rows (rows 32, 33): product over 1 tile, update of
+    # A[32:, 32:] (1 tile); the loop ends at c0 = 48
+    el = (2 * 16 * 18 + 3 * 256) + (2 * 3 * 256) + (2 * 16 * 2 + 1 * 256) + (2 * 1 * 256)
+    assert bench.two_stage_sy2sb_bytes(34) == 8.0 * el
+    # 512 x 512: ~8x less than the one-stage stream
+    assert bench.two_stage_sy2sb_bytes(512) < bench.one_stage_sytrd_bytes(512) / 5

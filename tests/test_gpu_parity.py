@@ -17,13 +17,14 @@ from oracle import thc as TH
 
 pytestmark = pytest.mark.gpu
 
-# Both SVD methods of the truncation step: 0 = eigenpairs of the Gram matrix
-# (default; jobs whose kept eigenvalues reach the Gram route's noise floor,
-# 32 m eps of the largest, are redone by Jacobi), 1 = one-sided block Jacobi
-# for every job.  Both meet the
-# untruncated FP64 bar of 1e-12 on the Hartree-Fock-derived states used here
-# (rank-deficient, Schmidt spectra spanning > 20 decades).
-SVD_MODES = [(0, 1e-12), (1, 1e-12)]
+# The SVD methods of the truncation step: 0 = eigenpairs of the Gram matrix
+# (default; two-stage tridiagonalisation; jobs whose kept eigenvalues reach
+# the Gram route's noise floor, 32 m eps of the largest, get a second Gram
+# level), 8 = the same with the one-stage tridiagonalisation, 1 = one-sided
+# block Jacobi for every job.  All meet the untruncated FP64 bar of 1e-12 on
+# the Hartree-Fock-derived states used here (rank-deficient, Schmidt spectra
+# spanning > 20 decades).
+SVD_MODES = [(0, 1e-12), (8, 1e-12), (1, 1e-12)]
 
 
 def _norm_mps(rng, n, D):
