@@ -454,69 +454,83 @@ __global__ __launch_bounds__(512) void k_lq2(double *__restrict__ Xb, int64_t sX
       P[p * VLD + c] = (p < pb) ? X[XI(i0 + p, i0 + c)] : 0.0;
     }
     __syncthreads();
-    if (wid == 0) {
-      // panel rows one after the other; row p lives in registers (lane l
-      // holds columns l + 64 t), the earlier reflectors are read from LDS
+    {
+      // right-looking over the panel rows: wave p mod 8 forms reflector p
+      // from row p (columns > p), then every wave applies it to the later
+      // rows it owns (rows w and w + 8); lane l holds columns l + 64 t
       constexpr int CPL = NMAX / WAVE;
+      const int wv = __builtin_amdgcn_readfirstlane(wid);
       for (int p = 0; p < pb; ++p) {
         double *row = P + p * VLD;
-        double rr[CPL];
-#pragma unroll
-        for (int t = 0; t < CPL; ++t) {
-          const int c = lane + WAVE * t;
-          rr[t] = (c < w) ? row[c] : 0.0;
-        }
-        for (int q = 0; q < p; ++q) {
-          const double *v = P + q * VLD;
-          double vv[CPL];
-          double s = 0.0;
+        if (wv == p % NWV) {
+          double rr[CPL];
 #pragma unroll
           for (int t = 0; t < CPL; ++t) {
             const int c = lane + WAVE * t;
-            vv[t] = (c > q && c < w) ? v[c] : (c == q ? 1.0 : 0.0);
-            s += rr[t] * vv[t];
+            rr[t] = (c < w) ? row[c] : 0.0;
           }
-          s = wave_sum(s) * tau[q];
-#pragma unroll
-          for (int t = 0; t < CPL; ++t) rr[t] -= s * vv[t];
-        }
-        double amax = 0.0;
-#pragma unroll
-        for (int t = 0; t < CPL; ++t) {
-          const int c = lane + WAVE * t;
-          if (c > p && c < w) amax = fmax(amax, fabs(rr[t]));
-        }
-        amax = wave_max(amax);
-        const double alpha = __shfl(rr[0], p, WAVE);
-        double tp, beta, sc = 1.0;
-        if (!(amax > 1e-290)) {
-          tp = 0.0;
-          beta = alpha;
-        } else {
-          const double scl = fmax(amax, fabs(alpha)), inv = 1.0 / scl;
-          double ss = 0.0;
+          double amax = 0.0;
 #pragma unroll
           for (int t = 0; t < CPL; ++t) {
             const int c = lane + WAVE * t;
-            const double x = rr[t] * inv;
-            if (c > p && c < w) ss += x * x;
+            if (c > p && c < w) amax = fmax(amax, fabs(rr[t]));
           }
-          ss = wave_sum(ss);
-          const double as = alpha * inv;
-          const double bs = -copysign(sqrt(as * as + ss), alpha);
-          beta = bs * scl;
-          tp = (bs - as) / bs;
-          sc = inv / (as - bs);
-        }
+          amax = wave_max(amax);
+          const double alpha = row[p];
+          double tp, beta, sc = 1.0;
+          if (!(amax > 1e-290)) {
+            tp = 0.0;
+            beta = alpha;
+          } else {
+            const double scl = fmax(amax, fabs(alpha)), inv = 1.0 / scl;
+            double ss = 0.0;
 #pragma unroll
-        for (int t = 0; t < CPL; ++t) {
-          const int c = lane + WAVE * t;
-          if (c < w) row[c] = (c > p) ? rr[t] * sc : (c == p ? beta : rr[t]);
+            for (int t = 0; t < CPL; ++t) {
+              const int c = lane + WAVE * t;
+              const double x = rr[t] * inv;
+              if (c > p && c < w) ss += x * x;
+            }
+            ss = wave_sum(ss);
+            const double as = alpha * inv;
+            const double bs = -copysign(sqrt(as * as + ss), alpha);
+            beta = bs * scl;
+            tp = (bs - as) / bs;
+            sc = inv / (as - bs);
+          }
+#pragma unroll
+          for (int t = 0; t < CPL; ++t) {
+            const int c = lane + WAVE * t;
+            if (c < w && c >= p) row[c] = (c > p) ? rr[t] * sc : beta;
+          }
+          if (lane == 0) tau[p] = tp;
         }
-        if (lane == 0) tau[p] = tp;
+        __syncthreads();
+        // H_p on the rows after p: x -= tau (v . x) v, v = e_p + row p beyond p
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int r = wv + NWV * h;
+          if (r > p && r < pb) {
+            double *xr = P + r * VLD;
+            double vv[CPL], xv[CPL];
+            double sacc = 0.0;
+#pragma unroll
+            for (int t = 0; t < CPL; ++t) {
+              const int c = lane + WAVE * t;
+              vv[t] = (c > p && c < w) ? row[c] : (c == p ? 1.0 : 0.0);
+              xv[t] = (c >= p && c < w) ? xr[c] : 0.0;
+              sacc += vv[t] * xv[t];
+            }
+            const double f = wave_sum(sacc) * tau[p];
+#pragma unroll
+            for (int t = 0; t < CPL; ++t) {
+              const int c = lane + WAVE * t;
+              if (c >= p && c < w) xr[c] = xv[t] - f * vv[t];
+            }
+          }
+        }
+        __syncthreads();
       }
     }
-    __syncthreads();
     // G[q][p] = v_q . v_p (q < p), one dot product per wave at a time
     for (int dd = wid; dd < NB * NB; dd += NWV) {
       const int q = dd / NB, p = dd % NB;
@@ -565,8 +579,9 @@ __global__ __launch_bounds__(512) void k_lq2(double *__restrict__ Xb, int64_t sX
     const int r = (int)(e / k), c = (int)(e % k);
     Lo[(int64_t)r * ldl + c] = (c <= r) ? X[XI(r, c)] : 0.0;
   }
+  // Q = I (k x n), walked in its storage order (with TR, Q^T: column index slowest)
   for (int64_t e = tid; e < (int64_t)k * n; e += blockDim.x) {
-    const int r = (int)(e / n), c = (int)(e % n);
+    const int r = TR ? (int)(e % k) : (int)(e / n), c = TR ? (int)(e / k) : (int)(e % n);
     Qo[TR ? (int64_t)c * ldq + r : (int64_t)r * ldq + c] = (r == c) ? 1.0 : 0.0;
   }
   __syncthreads();
