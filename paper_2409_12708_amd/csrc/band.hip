@@ -559,8 +559,13 @@ __global__ __launch_bounds__(512) void k_sb2st(const double *__restrict__ Ab, in
   const int wvs = __builtin_amdgcn_readfirstlane(tid / WAVE);
   for (int i = tid; i < WSC; i += NT) S[i] = 0.0;
   lds_barrier();
-  for (int c = tid; c < m; c += NT)
-    for (int dd = 0; dd <= BW && c + dd < m; ++dd) S[c * CW + dd] = A[(int64_t)c * m + c + dd];
+  for (int c = tid; c < m; c += NT) {
+    double bnd[BW + 1];  // the band's column c, loads in flight together
+#pragma unroll
+    for (int dd = 0; dd <= BW; ++dd) bnd[dd] = (c + dd < m) ? A[(int64_t)c * m + c + dd] : 0.0;
+#pragma unroll
+    for (int dd = 0; dd <= BW; ++dd) S[c * CW + dd] = bnd[dd];
+  }
   __syncthreads();
   if (m >= 3) {
     const int NS = (m - 3) / BW + 1;

@@ -38,6 +38,26 @@ __device__ __forceinline__ void rr_pair(int k, int r, int P, int &p, int &q) {
   if (p > q) { int t = p; p = q; q = t; }
 }
 
+// Element loop with UF loads in flight: for e = tid, tid + nthr, ... < total,
+// first load(e) for UF elements (independent loads), then store(e, value).
+// A plain loop waits out the memory latency once per element.
+template <int UF, class Load, class Store>
+__device__ __forceinline__ void copy_loop(int64_t total, int tid, int nthr, Load load, Store store) {
+  for (int64_t e0 = tid; e0 < total; e0 += (int64_t)UF * nthr) {
+    double v[UF];
+#pragma unroll
+    for (int u = 0; u < UF; ++u) {
+      const int64_t e = e0 + (int64_t)u * nthr;
+      v[u] = (e < total) ? load(e) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < UF; ++u) {
+      const int64_t e = e0 + (int64_t)u * nthr;
+      if (e < total) store(e, v[u]);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // construct: layer MPO applied to one site, or direct sum of two MPS.
 // Layer: W_j = [[Z, y_j o], [0, I]], o = c (annihilation) or c^T (creation).
@@ -449,10 +469,16 @@ __global__ __launch_bounds__(512) void k_lq2(double *__restrict__ Xb, int64_t sX
   for (int i0 = 0; i0 < k; i0 += NB) {
     const int pb = (k - i0) < NB ? (k - i0) : NB;
     const int w = n - i0;
-    for (int e = tid; e < NB * w; e += blockDim.x) {
-      const int p = TR ? e % NB : e / w, c = TR ? e / NB : e % w;
-      P[p * VLD + c] = (p < pb) ? X[XI(i0 + p, i0 + c)] : 0.0;
-    }
+    copy_loop<8>(
+        (int64_t)NB * w, tid, blockDim.x,
+        [&](int64_t e) -> double {
+          const int p = TR ? (int)(e % NB) : (int)(e / w), c = TR ? (int)(e / NB) : (int)(e % w);
+          return (p < pb) ? X[XI(i0 + p, i0 + c)] : 0.0;
+        },
+        [&](int64_t e, double v) {
+          const int p = TR ? (int)(e % NB) : (int)(e / w), c = TR ? (int)(e / NB) : (int)(e % w);
+          P[p * VLD + c] = v;
+        });
     __syncthreads();
     {
       // right-looking over the panel rows: wave p mod 8 forms reflector p
@@ -531,18 +557,41 @@ __global__ __launch_bounds__(512) void k_lq2(double *__restrict__ Xb, int64_t sX
         __syncthreads();
       }
     }
-    // G[q][p] = v_q . v_p (q < p), one dot product per wave at a time
-    for (int dd = wid; dd < NB * NB; dd += NWV) {
-      const int q = dd / NB, p = dd % NB;
-      if (q < p) {
-        double sacc = 0.0;
-        if (p < pb) {
-          const double *vq = P + q * VLD, *vp = P + p * VLD;
-          for (int c = p + lane; c < w; c += WAVE) sacc += vq[c] * (c == p ? 1.0 : vp[c]);
-          sacc = wave_sum(sacc);
-        }
-        if (lane == 0) Gd[dd] = sacc;
+    // store the panel (L part + reflectors); then make P the explicit V
+    // (unit diagonal, zeros left of it) for the Gram matrix and the update
+    for (int e = tid; e < pb * w; e += blockDim.x) {
+      const int p = TR ? e % pb : e / w, c = TR ? e / pb : e % w;
+      X[XI(i0 + p, i0 + c)] = P[p * VLD + c];
+    }
+    __syncthreads();
+    for (int e = tid; e < NB * w; e += blockDim.x) {
+      const int p = e / w, c = e % w;
+      if (p >= pb || c < p) P[p * VLD + c] = 0.0;
+      else if (c == p) P[p * VLD + c] = 1.0;
+    }
+    __syncthreads();
+    {
+      // G = V V^T (16 x 16) on MFMA: wave wv over its chunk of columns, the
+      // partials summed in LDS
+      const int wv = __builtin_amdgcn_readfirstlane(wid);
+      const int li = lane % 16, lk = lane / 16;
+      const int chunk = ((w + NWV - 1) / NWV + 3) / 4 * 4;
+      const int cb = wv * chunk, ce = min(w, cb + chunk);
+      d4_t g = {0.0, 0.0, 0.0, 0.0};
+      for (int c4 = cb; c4 < ce; c4 += 4) {
+        const int c = c4 + lk;
+        const double v = (c < ce) ? P[li * VLD + c] : 0.0;
+        g = mfma16(v, v, g);
       }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Wp[wv * 256 + (lk + 4 * r) * 16 + li] = g[r];
+    }
+    __syncthreads();
+    if (tid < 256) {
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < NWV; ++q) acc += Wp[q * 256 + tid];
+      Gd[tid] = acc;
     }
     __syncthreads();
     if (tid < NB) {
@@ -557,28 +606,18 @@ __global__ __launch_bounds__(512) void k_lq2(double *__restrict__ Xb, int64_t sX
       }
     }
     __syncthreads();
-    // store the panel (L part + reflectors), T for the Q pass; make P the
-    // explicit V (unit diagonal, zeros left of it) for the MFMA update
-    for (int e = tid; e < pb * w; e += blockDim.x) {
-      const int p = TR ? e % pb : e / w, c = TR ? e / pb : e % w;
-      X[XI(i0 + p, i0 + c)] = P[p * VLD + c];
-    }
     for (int e = tid; e < 256; e += blockDim.x) Ts[(int64_t)(i0 / NB) * 256 + e] = T[e];
-    __syncthreads();
-    for (int e = tid; e < NB * w; e += blockDim.x) {
-      const int p = e / w, c = e % w;
-      if (p >= pb || c < p) P[p * VLD + c] = 0.0;
-      else if (c == p) P[p * VLD + c] = 1.0;
-    }
-    __syncthreads();
     // trailing rows: X_r <- X_r - (X_r V^T) T V
     block_reflect_rows<NWV, TR>(X, TR ? m : n, (int64_t)m * n * 8, i0 + pb, m, i0, w, P, VLD, T, Wp, WT);
   }
 
-  for (int64_t e = tid; e < (int64_t)m * k; e += blockDim.x) {
-    const int r = (int)(e / k), c = (int)(e % k);
-    Lo[(int64_t)r * ldl + c] = (c <= r) ? X[XI(r, c)] : 0.0;
-  }
+  copy_loop<8>(
+      (int64_t)m * k, tid, blockDim.x,
+      [&](int64_t e) -> double {
+        const int r = (int)(e / k), c = (int)(e % k);
+        return (c <= r) ? X[XI(r, c)] : 0.0;
+      },
+      [&](int64_t e, double v) { Lo[(e / k) * ldl + e % k] = v; });
   // Q = I (k x n), walked in its storage order (with TR, Q^T: column index slowest)
   for (int64_t e = tid; e < (int64_t)k * n; e += blockDim.x) {
     const int r = TR ? (int)(e % k) : (int)(e / n), c = TR ? (int)(e / k) : (int)(e % n);
@@ -590,15 +629,17 @@ __global__ __launch_bounds__(512) void k_lq2(double *__restrict__ Xb, int64_t sX
     const int i0 = pi * NB;
     const int pb = (k - i0) < NB ? (k - i0) : NB;
     const int w = n - i0;
-    for (int e = tid; e < NB * w; e += blockDim.x) {
-      const int p = TR ? e % NB : e / w, c = TR ? e / NB : e % w;
-      double v = 0.0;
-      if (p < pb) {
-        if (c == p) v = 1.0;
-        else if (c > p) v = X[XI(i0 + p, i0 + c)];
-      }
-      P[p * VLD + c] = v;
-    }
+    copy_loop<8>(
+        (int64_t)NB * w, tid, blockDim.x,
+        [&](int64_t e) -> double {
+          const int p = TR ? (int)(e % NB) : (int)(e / w), c = TR ? (int)(e / NB) : (int)(e % w);
+          if (p >= pb || c < p) return 0.0;
+          return (c == p) ? 1.0 : X[XI(i0 + p, i0 + c)];
+        },
+        [&](int64_t e, double v) {
+          const int p = TR ? (int)(e % NB) : (int)(e / w), c = TR ? (int)(e / NB) : (int)(e % w);
+          P[p * VLD + c] = v;
+        });
     for (int e = tid; e < 256; e += blockDim.x) {
       const int q = e / 16, p = e % 16;
       TT[e] = Ts[(int64_t)pi * 256 + p * 16 + q];  // T^T
@@ -1287,16 +1328,14 @@ __global__ __launch_bounds__(256) void k_ormtr_tfac(const double *__restrict__ A
   const int tid = threadIdx.x;
   const int nref = m - off - 1, i0 = bi * NB;
   const int pb = (nref - i0) < NB ? (nref - i0) : NB;
-  for (int e = tid; e < NB * 512; e += 256) {
-    const int q = e / 512, r = e % 512;
-    const int i = i0 + q;
-    double x = 0.0;
-    if (q < pb && r < m) {
-      if (r == i + off) x = 1.0;
-      else if (r > i + off) x = A[(int64_t)i * m + r];
-    }
-    V[q * VL + r] = x;
-  }
+  copy_loop<8>(
+      (int64_t)NB * 512, tid, 256,
+      [&](int64_t e) -> double {
+        const int q = (int)(e / 512), r = (int)(e % 512), i = i0 + q;
+        if (q >= pb || r >= m || r < i + off) return 0.0;
+        return (r == i + off) ? 1.0 : A[(int64_t)i * m + r];
+      },
+      [&](int64_t e, double x) { V[(e / 512) * VL + e % 512] = x; });
   if (tid < NB) tv[tid] = (tid < pb) ? tau[i0 + tid] : 0.0;
   __syncthreads();
   {
