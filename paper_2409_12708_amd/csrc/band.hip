@@ -27,7 +27,6 @@ constexpr int BW = 16;          // half-bandwidth of the intermediate band
 constexpr int VLD = 17;         // row stride of the n x 16 panel arrays in LDS
 constexpr int NT = 512;         // threads per workgroup
 constexpr int NW = NT / WAVE;   // waves per workgroup
-constexpr int LAG = 4;          // phases between the starts of consecutive sweeps
 
 // Householder reflector H = I - tau v v^T, v[0] = 1, H x = beta e_0, from
 // alpha = x[0], amx = max |x[1:]|, s2 = |x[1:]|^2.  Returns false when the
@@ -540,15 +539,22 @@ __device__ __forceinline__ void chase_step(double *S, int m, int j, int k, int N
 }
 }  // namespace
 
-template <int MMAX>
-__global__ __launch_bounds__(512) void k_sb2st(const double *__restrict__ Ab, int64_t sA, int m,
+// CNT threads (CNT / 64 waves), sweeps CLAG phases apart: the active sweeps
+// of a phase are those with 0 <= P - CLAG j < (m-3-j)/16 + 1 <= 32, at most
+// ceil(32 / CLAG), each run by wave j mod (CNT / 64).  CLAG = 3 gives the
+// same result as CLAG = 4 bit for bit (a step of sweep j+1 three phases
+// behind sweep j touches only entries the latter no longer does).
+template <int MMAX, int CNT, int CLAG>
+__global__ __launch_bounds__(CNT) void k_sb2st(const double *__restrict__ Ab, int64_t sA, int m,
                                                 double *__restrict__ db, double *__restrict__ eb, int64_t sv,
                                                 double *__restrict__ V2b, int64_t sV2,
                                                 const int *__restrict__ only) {
   if (only != nullptr && only[blockIdx.x] == 0) return;  // job not selected
   constexpr int CW = 2 * BW;     // entries kept per band column
+  constexpr int CNW = CNT / WAVE;
+  static_assert((MMAX - 3) / BW + 1 <= CLAG * CNW, "more sweeps in flight than waves");
   // MMAX x CW band, then WAVE pad entries (masked writes), one zero (masked
-  // reads), NW x 32 scratch (each wave's v and w broadcasts)
+  // reads), CNW x 32 scratch (each wave's v and w broadcasts)
   extern __shared__ double S[];
   constexpr int PADB = MMAX * CW, ZSLOT = PADB + WAVE, WSC = ZSLOT + 1;
   const double *A = Ab + (int64_t)blockIdx.x * sA;
@@ -557,9 +563,9 @@ __global__ __launch_bounds__(512) void k_sb2st(const double *__restrict__ Ab, in
   double *V2 = V2b + (int64_t)blockIdx.x * sV2;
   const int tid = threadIdx.x, lane = tid % WAVE;
   const int wvs = __builtin_amdgcn_readfirstlane(tid / WAVE);
-  for (int i = tid; i < WSC; i += NT) S[i] = 0.0;
+  for (int i = tid; i < WSC; i += CNT) S[i] = 0.0;
   lds_barrier();
-  for (int c = tid; c < m; c += NT) {
+  for (int c = tid; c < m; c += CNT) {
     double bnd[BW + 1];  // the band's column c, loads in flight together
 #pragma unroll
     for (int dd = 0; dd <= BW; ++dd) bnd[dd] = (c + dd < m) ? A[(int64_t)c * m + c + dd] : 0.0;
@@ -569,18 +575,18 @@ __global__ __launch_bounds__(512) void k_sb2st(const double *__restrict__ Ab, in
   __syncthreads();
   if (m >= 3) {
     const int NS = (m - 3) / BW + 1;
-    const int nph = LAG * (m - 3) + 1;
+    const int nph = CLAG * (m - 3) + 1;
     for (int P = 0; P < nph; ++P) {
-      const int jhi = min(P / LAG, m - 3);
-      const int j = jhi - (((jhi - wvs) % NW) + NW) % NW;  // largest j <= jhi run by this wave
+      const int jhi = min(P / CLAG, m - 3);
+      const int j = jhi - (((jhi - wvs) % CNW) + CNW) % CNW;  // largest j <= jhi run by this wave
       if (j >= 0) {
-        const int k = P - LAG * j;
+        const int k = P - CLAG * j;
         if (k < (m - 3 - j) / BW + 1) chase_step<CW>(S, m, j, k, NS, V2, lane, ZSLOT, PADB, S + WSC + 2 * BW * wvs);
       }
       lds_barrier();
     }
   }
-  for (int c = tid; c < m; c += NT) {
+  for (int c = tid; c < m; c += CNT) {
     d[c] = S[c * CW];
     if (c + 1 < m) e[c] = S[c * CW + 1];
   }
@@ -726,13 +732,14 @@ int launch_sb2st(hipStream_t st, int nb, const double *A, int64_t sA, int m, dou
   constexpr int MMAX = 512;
   if (m > MMAX) return -1;
   if (nb <= 0) return 0;
-  const size_t lds = ((size_t)MMAX * 2 * BW + WAVE + 1 + NW * 2 * BW) * sizeof(double);  // band, pad, zero, scratch
+  constexpr int CNT = 768, CLAG = 3;  // 12 waves, sweeps 3 phases apart
+  const size_t lds = ((size_t)MMAX * 2 * BW + WAVE + 1 + (CNT / WAVE) * 2 * BW) * sizeof(double);  // band, pad, zero, scratch
   static bool attr = false;
   if (!attr) {
-    set_lds_band(k_sb2st<MMAX>, lds);
+    set_lds_band(k_sb2st<MMAX, CNT, CLAG>, lds);
     attr = true;
   }
-  hipLaunchKernelGGL(k_sb2st<MMAX>, dim3(nb), dim3(NT), lds, st, A, sA, m, d, e, sv, V2, sV2, only);
+  hipLaunchKernelGGL((k_sb2st<MMAX, CNT, CLAG>), dim3(nb), dim3(CNT), lds, st, A, sA, m, d, e, sv, V2, sV2, only);
   return 0;
 }
 
