@@ -25,6 +25,7 @@ namespace thck {
 namespace {
 constexpr int BW = 16;          // half-bandwidth of the intermediate band
 constexpr int VLD = 17;         // row stride of the n x 16 panel arrays in LDS
+constexpr int R_ROWS = 512 - 16; // rows of the panel arrays (m <= 512)
 constexpr int NT = 512;         // threads per workgroup
 constexpr int NW = NT / WAVE;   // waves per workgroup
 
@@ -238,6 +239,94 @@ __device__ void gram16(const double *X, const double *Y, int R, double *sc, doub
 }
 }  // namespace
 
+// Householder QR of the n x 16 panel P = A^T[r0:, c0:c0+16] (column q of P is
+// row c0 + q of the stored upper triangle, from column r0 on), by columns:
+// wave w holds columns w and w + 8 in registers (rows l + 64 i in lane l).
+// Column q's owner applies the earlier reflectors to it (as every wave does
+// to its columns), forms reflector q, writes v to V (rows of stride VLD) and
+// tau to tl; after the barrier every wave applies it to its columns after q.
+// At the end each wave stores its columns (R above the diagonal, beta on
+// it, the reflector tail below) back to A.
+__device__ void panel_qr_cols(double *A, int m, int c0, int r0, int n, double *V, double *tl, int wvs, int lane) {
+  constexpr int RPL = 8;  // rows per lane (n <= 512)
+  double col[2][RPL];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int q = wvs + NW * h;
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      const int t = lane + WAVE * i;
+      col[h][i] = (t < n) ? A[(int64_t)(c0 + q) * m + r0 + t] : 0.0;
+    }
+  }
+#pragma unroll
+  for (int h2 = 0; h2 < 2; ++h2) {
+#pragma unroll 1
+    for (int qq = 0; qq < NW; ++qq) {
+      const int q = qq + NW * h2;
+      if (wvs == qq) {  // the owner of column q (its register slot h2)
+        double x[RPL];
+        double am = 0.0, ss = 0.0;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const int t = lane + WAVE * i;
+          x[i] = (t > q && t < n) ? col[h2][i] : 0.0;
+          am = fmax(am, fabs(x[i]));
+          ss = fma(x[i], x[i], ss);
+        }
+        const double amx = wave_max(am), s2 = wave_sum(ss);
+        const double alpha = read_lane(col[h2][0], q);  // row q < 16: lane q, i = 0
+        double tp, scv, ei;
+        if (!house_direct(alpha, amx, s2, tp, scv, ei)) {
+          const double scl = fmax(amx, fabs(alpha)), inv = 1.0 / scl;
+          double s3 = 0.0;
+#pragma unroll
+          for (int i = 0; i < RPL; ++i) s3 = fma(x[i] * inv, x[i] * inv, s3);
+          house_scaled(alpha, scl, wave_sum(s3), tp, scv, ei);
+        }
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const int t = lane + WAVE * i;
+          const double v = (t == q) ? ((q < n) ? 1.0 : 0.0) : x[i] * scv;
+          if (t < R_ROWS) V[t * VLD + q] = (t < n) ? v : 0.0;
+          if (t == q) col[h2][i] = ei;
+          else if (t > q) col[h2][i] = v;
+        }
+        if (lane == 0) tl[q] = tp;
+      }
+      lds_barrier();
+      // H_q on this wave's columns after q: c -= tau (v . c) v (rows >= q)
+      const double tp = tl[q];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int c = wvs + NW * h;
+        if (c > q) {
+          double vv[RPL], acc = 0.0;
+#pragma unroll
+          for (int i = 0; i < RPL; ++i) {
+            const int t = lane + WAVE * i;
+            vv[i] = (t >= q && t < n) ? V[t * VLD + q] : 0.0;
+            acc = fma(vv[i], col[h][i], acc);
+          }
+          const double f = tp * wave_sum(acc);
+#pragma unroll
+          for (int i = 0; i < RPL; ++i) col[h][i] -= f * vv[i];
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int q = wvs + NW * h;
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      const int t = lane + WAVE * i;
+      if (t < n) A[(int64_t)(c0 + q) * m + r0 + t] = col[h][i];
+    }
+  }
+  lds_barrier();  // V and tl complete for every wave
+}
+
 // ---------------------------------------------------------------------------
 // sy2sb: Q1^T A Q1 = B with B of half-bandwidth 16, for the symmetric A given
 // by its upper triangle (row-major, row stride m, m <= 512).  Panel p (columns
@@ -281,62 +370,13 @@ __global__ __launch_bounds__(512) void k_sy2sb(double *__restrict__ Ab, int64_t 
     }
     const int r0 = c0 + BW, n = m - r0;
     if (n < 2) break;
-    // ---- panel QR: panel row t in row t of Ys, owned by thread t ----
-    double *pr = Ys + tid * VLD;  // dereferenced only for tid < n <= R
-    if (tid < n)
-      for (int q = 0; q < BW; ++q) pr[q] = A[(int64_t)(c0 + q) * m + r0 + tid];
-    for (int q = 0; q < BW; ++q) {
-      const double xq = (tid < n) ? pr[q] : 0.0;
-      const double xb = (tid > q && tid < n) ? xq : 0.0;
-      const double am = wave_max(fabs(xb));
-      const double ss = wave_sum(xb * xb);
-      if (lane == 0) {
-        red[wid] = am;
-        red[NW + wid] = ss;
-      }
-      if (tid == q) red[4 * NW] = xq;
-      lds_barrier();
-      double amx = 0.0, s2 = 0.0;
-#pragma unroll
-      for (int w = 0; w < NW; ++w) {
-        amx = fmax(amx, red[w]);
-        s2 += red[NW + w];
-      }
-      const double alpha = red[4 * NW];
-      double tp, scv, ei;
-      if (!house_direct(alpha, amx, s2, tp, scv, ei)) {
-        const double scl = fmax(amx, fabs(alpha)), inv = 1.0 / scl;
-        const double t3 = wave_sum((xb * inv) * (xb * inv));
-        if (lane == 0) red[2 * NW + wid] = t3;
-        lds_barrier();
-        double s3 = 0.0;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) s3 += red[2 * NW + w];
-        house_scaled(alpha, scl, s3, tp, scv, ei);
-      }
-      const double v = (tid == q && q < n) ? 1.0 : xb * scv;
-      // w_c = v . P[:, c] for the columns after q, then P[:, c] -= tau v w_c
-      for (int c = q + 1; c < BW; ++c) {
-        const double pc = wave_sum(tid < n ? v * pr[c] : 0.0);
-        if (lane == 0) red[4 * NW + 1 + wid * BW + c] = pc;
-      }
-      lds_barrier();
-      if (tid < n) {
-        for (int c = q + 1; c < BW; ++c) {
-          double wc = 0.0;
-#pragma unroll
-          for (int w = 0; w < NW; ++w) wc += red[4 * NW + 1 + w * BW + c];
-          pr[c] -= tp * v * wc;
-        }
-        if (tid == q) pr[q] = ei;
-        else if (tid > q) pr[q] = v;
-      }
-      if (tid < R) Vs[tid * VLD + q] = v;
-      if (tid == 0) tl[q] = tp;
-    }
-    if (tid < n)
-      for (int q = 0; q < BW; ++q) A[(int64_t)(c0 + q) * m + r0 + tid] = pr[q];
-    lds_barrier();
+    // ---- panel QR: wave w owns panel columns w and w + 8 (rows l + 64 i in
+    //      lane l); column q's owner forms its reflector (wave reductions)
+    //      and writes v to Vs, then every wave applies it to its later
+    //      columns: one barrier per column ----
+    for (int e = n + tid; e < R; e += NT)
+      for (int q = 0; q < BW; ++q) Vs[e * VLD + q] = 0.0;  // rows past the panel: V = 0
+    panel_qr_cols(A, m, c0, r0, n, Vs, tl, wvs, lane);
     if (tid < BW) tau[c0 + tid] = tl[tid];
     // ---- T: G = V^T V, T[0:p, p] = -tau_p T[0:p, 0:p] G[0:p, p] ----
     gram16(Vs, Vs, R, sc, Gq, tid, wvs, li, lk);
