@@ -1874,6 +1874,29 @@ __device__ __forceinline__ int sturm_count(const double *d, const double *e2, in
   return cnt;
 }
 
+// The same count, also returning S = sum_k p_k' / p_k over the pivots p_k of
+// T - x I (p_k' = dp_k/dx, carried by differentiating the recurrence): S is
+// d/dx log|det(T - x I)|, so -1/S is the Newton step towards a root.  S is
+// not finite where a pivot is at the pivmin floor.
+__device__ __forceinline__ int sturm_newton(const double *d, const double *e2, int m, double x, double pivmin,
+                                            double &S) {
+  int cnt = 0;
+  double q = d[0] - x, dq = -1.0, s = 0.0;
+  if (fabs(q) < pivmin) q = -pivmin;
+  if (q < 0.0) ++cnt;
+  for (int k = 1; k < m; ++k) {
+    const double r = rcp_nr(q);
+    const double t = e2[k - 1] * r;
+    s = fma(dq, r, s);
+    dq = fma(t * r, dq, -1.0);
+    q = (d[k] - x) - t;
+    if (fabs(q) < pivmin) q = -pivmin;
+    if (q < 0.0) ++cnt;
+  }
+  S = fma(dq, rcp_nr(q), s);
+  return cnt;
+}
+
 // tri_eig: top-kk eigenpairs of the tridiagonal (d, e), one workgroup of
 // 512 threads per matrix (two fit on a CU; a 1024-thread workgroup runs
 // alone), kk <= 256.  Eigenvalues: trisection on Sturm counts to full
@@ -2053,38 +2076,105 @@ __global__ __launch_bounds__(512) void k_tri_eig(const double *__restrict__ db, 
   __syncthreads();
   const int nsig = s_nsig;
   if (tid == 0) s_need = nsig < kk;  // pseudo-random completions among the returned vectors
-  // trisection: two consecutive lanes share eigenvalue t and each evaluates
-  // the Sturm count at one of the points a + (b - a) (s + 1) / 3, so every
-  // step shrinks the bracket three-fold; the two lanes agree on the new
-  // bracket through the wave ballot
-  constexpr int NSUB = 2;
+  // Eigenvalues in three stages, two consecutive lanes per eigenvalue t
+  // (index j = m - 1 - t in ascending order), bracket [a, b) with
+  // count(a) <= j < count(b):
+  // 1. multisection: every thread takes the Sturm count at one point of a
+  //    grid over the spectrum, half equally spaced, half geometric from the
+  //    noise floor up (decaying spectra), and each pair starts from the
+  //    tightest bracket that the grid gives;
+  // 2. while the bracket holds other eigenvalues too (count(a) < j or
+  //    count(b) > j + 1), trisection: the lanes take the counts at
+  //    a + (b - a) (s + 1) / 3;
+  // 3. once j is alone in it, safeguarded Newton on det(T - x I): the count
+  //    recurrence also carries d(pivot)/dx, which gives the Newton step
+  //    1 / sum(pivot' / pivot); lane 0 takes the count at the Newton point,
+  //    lane 1 a little beyond it, and when the step has fallen below the
+  //    tolerance both lanes take points a quarter-tolerance either side,
+  //    which closes the bracket.
+  // Every count narrows the bracket, so the stopping rule is the bracket's
+  // width as in plain bisection: b - a <= 4.4e-16 max(|a|, |b|) + 1e-18.
+  constexpr int NSUB = 2, NGRID = 512;
   constexpr double THIRD = 1.0 / 3.0;
+  const double a0 = fmax(lo_s - pad, noise), b0 = hi_s + pad;
+  __shared__ double s_gx[NGRID];
+  __shared__ int s_gc[NGRID];
+  for (int i = tid; i < NGRID; i += blockDim.x) {
+    double x = 0.0;
+    int c = 0;
+    if (nsig > 0) {
+      constexpr int HG = NGRID / 2;
+      x = (i < HG) ? a0 + (b0 - a0) * (double)(i + 1) / (double)(HG + 1)
+                   : noise * exp2((double)(i - HG + 1) / (double)(NGRID - HG + 1) * log2(b0 / noise));
+      c = sturm_count(sd, se2, m, x, pivmin);
+    }
+    s_gx[i] = x;
+    s_gc[i] = c;
+  }
+  __syncthreads();
   const int lane = tid % WAVE;
   for (int g = tid / NSUB; g < ((kk + 63) / 64) * 64; g += blockDim.x / NSUB) {
     const int t = g, sub = tid % NSUB;
     const bool act = t < kk && t < nsig;
     const int j = m - 1 - t;  // index in ascending order
-    double a = fmax(lo_s - pad, noise), b = hi_s + pad;
-    bool done = !act;
-    // 3^48 > 1e22: from a bracket of width ~2 (T is scaled to norm 1) to
-    // the 1e-18 floor below
-    for (int it = 0; it < 48; ++it) {
-      if (!done && !(b - a > 2.2e-16 * fmax(fabs(a), fabs(b)) + 1e-18 * tn)) done = true;
-      if (__ballot(!done) == 0ull) break;
-      const double x = a + (b - a) * (double)(sub + 1) * THIRD;
-      const bool above = done ? false : (sturm_count(sd, se2, m, x, pivmin) > j);
-      const unsigned long long bal = __ballot(above);
-      if (!done) {
-        const unsigned int grp = (unsigned int)((bal >> (lane & ~(NSUB - 1))) & ((1u << NSUB) - 1u));
-        if (grp == 0u) {
-          a = a + (b - a) * (double)NSUB * THIRD;
-        } else {
-          const int s0 = __builtin_ctz(grp);
-          const double lo2 = (s0 == 0) ? a : a + (b - a) * (double)s0 * THIRD;
-          const double hi2 = a + (b - a) * (double)(s0 + 1) * THIRD;
-          a = lo2;
-          b = hi2;
+    double a = a0, b = b0;
+    int ca = -1, cb = m + 1;  // counts at a and b, where known
+    if (act) {
+      // each half of the grid is increasing in x: bisect it for the last
+      // point with count <= j (invariant count[lo] <= j < count[hi])
+      for (int h0 = 0; h0 < NGRID; h0 += NGRID / 2) {
+        int lo = h0 - 1, hi = h0 + NGRID / 2;
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (s_gc[mid] <= j) lo = mid; else hi = mid;
         }
+        if (lo >= h0 && s_gx[lo] > a) { a = s_gx[lo]; ca = s_gc[lo]; }
+        if (hi < h0 + NGRID / 2 && s_gx[hi] < b) { b = s_gx[hi]; cb = s_gc[hi]; }
+      }
+    }
+    bool done = !act, hasx = false;
+    double xc = 0.0, dl = 0.0, sg = 1.0;
+    for (int it = 0; it < 64; ++it) {
+      const double tol = 4.4e-16 * fmax(fabs(a), fabs(b)) + 1e-18 * tn;
+      if (!done && !(b - a > tol)) done = true;
+      if (__ballot(!done) == 0ull) break;
+      const bool iso = (ca == j) && (cb == j + 1);
+      const double h = 0.25 * tol;
+      double p;
+      if (!iso || !hasx) {
+        p = iso ? ((sub == 0) ? 0.5 * (a + b) : a + 0.75 * (b - a)) : a + (b - a) * (double)(sub + 1) * THIRD;
+      } else {
+        const double nud = fmin(fmax(dl, h), 0.5 * (b - a));
+        const double c = (xc <= a) ? a + nud : ((xc >= b) ? b - nud : xc);
+        if (dl <= tol) {
+          p = (sub == 0) ? fmax(c - h, a) : fmin(c + h, b);
+        } else if (sub == 0) {
+          p = c;
+        } else {
+          const double q1 = c + sg * fmax(h, 0.5 * dl);
+          p = (q1 > a && q1 < b) ? q1 : 0.5 * (c + (sg > 0.0 ? b : a));
+        }
+      }
+      double S = 0.0;
+      const int n = done ? 0 : sturm_newton(sd, se2, m, p, pivmin, S);
+      // the pair's two evaluations, in lane order, on both lanes
+      const double po = __shfl_xor(p, 1), So = __shfl_xor(S, 1);
+      const int no = __shfl_xor(n, 1);
+      if (!done) {
+        const double p0 = sub ? po : p, p1 = sub ? p : po, S0 = sub ? So : S, S1 = sub ? S : So;
+        const int n0 = sub ? no : n, n1 = sub ? n : no;
+        if (n0 > j) { if (p0 < b) { b = p0; cb = n0; } } else if (p0 > a) { a = p0; ca = n0; }
+        if (n1 > j) { if (p1 < b) { b = p1; cb = n1; } } else if (p1 > a) { a = p1; ca = n1; }
+        // Newton step from the point with the smaller step (the closer one)
+        const double D0 = 1.0 / S0, D1 = 1.0 / S1;
+        const bool f0 = isfinite(D0), f1 = isfinite(D1);
+        const bool use0 = f0 && (!f1 || fabs(D0) <= fabs(D1));
+        const double D = use0 ? D0 : D1;
+        hasx = (f0 || f1);
+        xc = (use0 ? p0 : p1) - D;
+        dl = fabs(D);
+        sg = (D <= 0.0) ? 1.0 : -1.0;
+        hasx = hasx && isfinite(xc);
       }
     }
     if (t < kk && sub == 0) {
