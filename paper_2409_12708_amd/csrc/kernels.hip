@@ -1913,7 +1913,8 @@ __device__ __forceinline__ int sturm_newton(const double *d, const double *e2, i
 // Output Z (m x kk, column t = eigenvector t) and lambda (kk, descending);
 // with flagb, per job 1 where Z need not be orthonormal (noise-floor
 // completions among the kk vectors, a cluster split at the member cap), else 0.
-// Scratch per job: 3 m kk doubles (the bands of U), laid out [r][t].
+// Scratch per job: tri_eig_scratch(m, kk) doubles (first solutions and
+// elimination checkpoints), laid out [r][t].
 // pseudo-random start component (k, t) of inverse iteration, in [-1/2, 1/2)
 __device__ __forceinline__ double inv_iter_start(int k, int t) {
   unsigned int h = (unsigned int)k * 2654435761u ^ ((unsigned int)(t + 1) * 40503u) ^ 0x9e3779b9u;
@@ -1923,89 +1924,166 @@ __device__ __forceinline__ double inv_iter_start(int k, int t) {
 
 // Two steps of inverse iteration for eigenvalue lm, vector t (column t of Z,
 // layout [r][t]).  Each step factors T - lm I with partial pivoting (rows k
-// and k+1 swapped when |sub-diagonal| > |pivot|) and applies the row
-// operations to the right-hand side in the same pass, storing only the
-// three bands of U; the back substitution accumulates the sum of squares.
-// The first right-hand side is generated on the fly; the second is the first
-// solution, scaled as it is read.  Members of a cluster (q0 < t) are
-// normalised, orthogonalised against members q0..t-1 and normalised again
-// after each step.
+// and k+1 swapped when |sub-diagonal| > |pivot|), applying the row operations
+// to the right-hand side as it goes, then back-substitutes.  U is not
+// stored: the elimination keeps, every IIC rows, the state it resumes from
+// (pivot row entries r0, r1 and the right-hand side value), and the back
+// substitution, chunk by chunk from the last, redoes that chunk's
+// elimination in registers and solves it.  Memory traffic per step: the
+// right-hand side read twice, the solution written once, 3 m / IIC
+// checkpoint values.  The first right-hand side is generated on the fly; the
+// first solution goes to scratch X and, scaled as it is read, is the second
+// right-hand side, whose solution goes to Z.  Members of a cluster (q0 < t)
+// are normalised, orthogonalised against members q0..t-1 and normalised
+// again after each step.
+constexpr int IIC = 8;
+// offset of the hand-over from k_tri_eig to k_tri_vec in a job's scratch
+__host__ __device__ inline int64_t tri_vec_tail(int m, int kk) {
+  return ((int64_t)m + 3 * ((m + IIC - 1) / IIC)) * kk;
+}
+
+struct ElimState {
+  double r0, r1, y;  // pivot row (diagonal, super-diagonal) and its right-hand side entry
+};
+
+// One elimination step at row k (k + 1 < m): produces row k of U (u0, u1, u2)
+// and the transformed right-hand side z_k, and moves the state to row k + 1.
+// yk1 is the right-hand side entry of row k + 1.  Without a swap
+// (|r0| >= |e_k|; a zero pivot taken as tiny) row k + 1 loses
+// e_k / r0 times row k; with one, row k loses r0 / e_k times row k + 1 and
+// the two change places.  Written with selects: the lanes of a wave take
+// different branches.
+__device__ __forceinline__ void elim_step(const double *sd, const double *se, int m, int k, double lm, double tiny,
+                                          double yk1, ElimState &s, double &u0, double &u1, double &u2, double &z) {
+  const double l = se[k], an = sd[k + 1] - lm, bn = (k + 2 < m) ? se[k + 1] : 0.0;
+  const bool sw = fabs(s.r0) < fabs(l);
+  const double r0 = (s.r0 == 0.0) ? tiny : s.r0;
+  const double mult = qdiv(sw ? s.r0 : l, sw ? l : r0);
+  u0 = sw ? l : r0;
+  u1 = sw ? an : s.r1;
+  u2 = sw ? bn : 0.0;
+  z = sw ? yk1 : s.y;
+  const double pa = sw ? s.r1 : an, pb = sw ? an : s.r1;
+  const double ya = sw ? s.y : yk1;
+  s.r0 = pa - mult * pb;
+  s.r1 = sw ? -mult * bn : bn;
+  s.y = ya - mult * z;
+}
+
 __device__ void inv_iter_one(const double *sd, const double *se, int m, int kk, int t, double lm, double tiny,
-                             double *U0, double *U1, double *U2, double *Z, int q0) {
+                             double *X, double *CK, double *Z, int q0) {
   if (!(tiny > 1e-250)) {  // T = 0: every vector is an eigenvector; use e_t
     for (int k = 0; k < m; ++k) Z[(int64_t)k * kk + t] = (k == t) ? 1.0 : 0.0;
     return;
   }
-  double rs = 1.0;  // scale of the right-hand side held in Z
+  const int nc = (m + IIC - 1) / IIC;
+  double rs = 1.0;  // scale of the right-hand side held in X
   for (int iter = 0; iter < 2; ++iter) {
-    double r0 = sd[0] - lm, r1 = (m > 1) ? se[0] : 0.0, r2 = 0.0;
-    double yk = (iter == 0) ? inv_iter_start(0, t) : Z[t] * rs;
-    for (int k = 0; k + 1 < m; ++k) {
-      const double l = se[k], an = sd[k + 1] - lm, bn = (k + 2 < m) ? se[k + 1] : 0.0;
-      const int64_t o = (int64_t)k * kk + t;
-      double yk1 = (iter == 0) ? inv_iter_start(k + 1, t) : Z[o + kk] * rs;
-      if (fabs(r0) >= fabs(l)) {
-        if (r0 == 0.0) r0 = tiny;
-        const double mult = qdiv(l, r0);
-        U0[o] = r0; U1[o] = r1; U2[o] = r2;
-        r0 = an - mult * r1;
-        r1 = bn - mult * r2;
-        yk1 -= mult * yk;
-      } else {
-        const double mult = qdiv(r0, l);
-        U0[o] = l; U1[o] = an; U2[o] = bn;
-        const double n0 = r1 - mult * an, n1 = r2 - mult * bn;
-        r0 = n0;
-        r1 = n1;
-        const double tmp = yk;
-        yk = yk1;
-        yk1 = tmp - mult * yk1;
+    const double *R = X;              // right-hand side of step 1
+    double *O = (iter == 0) ? X : Z;  // this step's solution
+    // right-hand side entries k0 + 1 .. k0 + IIC of chunk c (rows past m - 1 unused)
+    auto load_rhs = [&](int c, double(&v)[IIC]) {
+#pragma unroll
+      for (int i = 0; i < IIC; ++i) {
+        const int k = c * IIC + 1 + i;
+        v[i] = (k < m) ? ((iter == 0) ? inv_iter_start(k, t) : R[(int64_t)k * kk + t] * rs) : 0.0;
       }
-      r2 = 0.0;
-      Z[o] = yk;
-      yk = yk1;
-    }
-    if (r0 == 0.0) r0 = tiny;
+    };
+    // forward elimination, keeping the state at the start of every chunk;
+    // the next chunk's right-hand side is loaded while this one is eliminated
     {
-      const int64_t o = (int64_t)(m - 1) * kk + t;
-      U0[o] = r0; U1[o] = 0.0; U2[o] = 0.0;
-      Z[o] = yk;
-    }
-    // back substitution with running rescaling: a solve against a nearly
-    // singular (T - lambda I) grows by up to 1/eps per tiny pivot, so the
-    // partial solution is scaled down whenever it exceeds 1e150 (entries stay
-    // below 1e150, so the sum of their squares cannot overflow)
-    double x1 = 0.0, x2 = 0.0, s2 = 0.0;
-    for (int k = m - 1; k >= 0; --k) {
-      const int64_t o = (int64_t)k * kk + t;
-      const double iu = rcp_nr(U0[o]);
-      double x = (Z[o] - U1[o] * x1 - U2[o] * x2) * iu;
-      if (fabs(x) > 1e150) {
-        const double sc = 1e-150;
-        for (int q = k + 1; q < m; ++q) Z[(int64_t)q * kk + t] *= sc;
-        for (int q = 0; q < k; ++q) Z[(int64_t)q * kk + t] *= sc;  // remaining right-hand side
-        x1 *= sc;
-        x2 *= sc;
-        s2 *= sc * sc;
-        x = (Z[o] * sc - U1[o] * x1 - U2[o] * x2) * iu;
+      ElimState s{sd[0] - lm, (m > 1) ? se[0] : 0.0, (iter == 0) ? inv_iter_start(0, t) : R[t] * rs};
+      double nx[IIC];
+      load_rhs(0, nx);
+      for (int c = 0; c < nc; ++c) {
+        double cur[IIC];
+#pragma unroll
+        for (int i = 0; i < IIC; ++i) cur[i] = nx[i];
+        if (c + 1 < nc) load_rhs(c + 1, nx);
+        const int k0 = c * IIC, k1 = min(k0 + IIC, m - 1);
+        double *ck = CK + (int64_t)c * 3 * kk + t;
+        ck[0] = s.r0;
+        ck[kk] = s.r1;
+        ck[2 * kk] = s.y;
+#pragma unroll
+        for (int i = 0; i < IIC; ++i) {
+          double u0, u1, u2, z;
+          if (k0 + i < k1) elim_step(sd, se, m, k0 + i, lm, tiny, cur[i], s, u0, u1, u2, z);
+        }
       }
-      Z[o] = x;
-      x2 = x1;
-      x1 = x;
-      s2 += x * x;
+    }
+    // back substitution, last chunk first: each chunk's elimination is redone
+    // from its checkpoint with U and z kept in registers, while the previous
+    // chunk's checkpoint and right-hand side are loaded.  Running rescaling:
+    // a solve against a nearly singular (T - lambda I) grows by up to 1/eps
+    // per tiny pivot, so the partial solution is scaled down whenever it
+    // exceeds 1e150 (entries stay below 1e150, so the sum of their squares
+    // cannot overflow); bs is the scale that the rows still to come are taken at
+    double x1 = 0.0, x2 = 0.0, s2 = 0.0, bs = 1.0;
+    double nx[IIC], n0, n1, n2;
+    auto load_ck = [&](int c) {
+      const double *ck = CK + (int64_t)c * 3 * kk + t;
+      n0 = ck[0];
+      n1 = ck[kk];
+      n2 = ck[2 * kk];
+    };
+    load_rhs(nc - 1, nx);
+    load_ck(nc - 1);
+    for (int c = nc - 1; c >= 0; --c) {
+      const int k0 = c * IIC;
+      ElimState s{n0, n1, n2};
+      double cur[IIC];
+#pragma unroll
+      for (int i = 0; i < IIC; ++i) cur[i] = nx[i];
+      if (c > 0) {
+        load_rhs(c - 1, nx);
+        load_ck(c - 1);
+      }
+      double U0[IIC], U1[IIC], U2[IIC], Zr[IIC];
+#pragma unroll
+      for (int i = 0; i < IIC; ++i) {
+        const int k = k0 + i;
+        if (k + 1 < m) {
+          elim_step(sd, se, m, k, lm, tiny, cur[i], s, U0[i], U1[i], U2[i], Zr[i]);
+        } else if (k + 1 == m) {  // last row
+          if (s.r0 == 0.0) s.r0 = tiny;
+          U0[i] = s.r0; U1[i] = 0.0; U2[i] = 0.0; Zr[i] = s.y;
+        }
+      }
+#pragma unroll
+      for (int i = IIC - 1; i >= 0; --i) {
+        const int k = k0 + i;
+        if (k < m) {
+          const double iu = rcp_nr(U0[i]);
+          double x = (Zr[i] * bs - U1[i] * x1 - U2[i] * x2) * iu;
+          if (fabs(x) > 1e150) {
+            const double sc = 1e-150;
+            for (int q = k + 1; q < m; ++q) O[(int64_t)q * kk + t] *= sc;
+            x1 *= sc;
+            x2 *= sc;
+            s2 *= sc * sc;
+            bs *= sc;
+            x = (Zr[i] * bs - U1[i] * x1 - U2[i] * x2) * iu;
+          }
+          O[(int64_t)k * kk + t] = x;
+          x2 = x1;
+          x1 = x;
+          s2 += x * x;
+        }
+      }
     }
     const double inv = (s2 > 0.0 && isfinite(s2)) ? 1.0 / sqrt(s2) : 0.0;
     if (q0 < t) {
-      for (int k = 0; k < m; ++k) Z[(int64_t)k * kk + t] *= inv;
+      for (int k = 0; k < m; ++k) O[(int64_t)k * kk + t] *= inv;
       for (int q = q0; q < t; ++q) {
         double dt = 0.0;
-        for (int k = 0; k < m; ++k) dt += Z[(int64_t)k * kk + q] * Z[(int64_t)k * kk + t];
-        for (int k = 0; k < m; ++k) Z[(int64_t)k * kk + t] -= dt * Z[(int64_t)k * kk + q];
+        for (int k = 0; k < m; ++k) dt += Z[(int64_t)k * kk + q] * O[(int64_t)k * kk + t];
+        for (int k = 0; k < m; ++k) O[(int64_t)k * kk + t] -= dt * Z[(int64_t)k * kk + q];
       }
       double s3 = 0.0;
-      for (int k = 0; k < m; ++k) { const double x = Z[(int64_t)k * kk + t]; s3 += x * x; }
+      for (int k = 0; k < m; ++k) { const double x = O[(int64_t)k * kk + t]; s3 += x * x; }
       const double inv3 = (s3 > 0.0) ? 1.0 / sqrt(s3) : 0.0;
-      for (int k = 0; k < m; ++k) Z[(int64_t)k * kk + t] *= inv3;
+      for (int k = 0; k < m; ++k) O[(int64_t)k * kk + t] *= inv3;
       rs = 1.0;
     } else if (iter == 1) {
       for (int k = 0; k < m; ++k) Z[(int64_t)k * kk + t] *= inv;
@@ -2016,8 +2094,7 @@ __device__ void inv_iter_one(const double *sd, const double *se, int m, int kk, 
 }
 
 __global__ __launch_bounds__(512) void k_tri_eig(const double *__restrict__ db, const double *__restrict__ eb,
-                                                 int64_t sv, int m, int kk, double *__restrict__ Zb, int64_t sZ,
-                                                 double *__restrict__ lamb, int64_t sl, double *__restrict__ scrb,
+                                                 int64_t sv, int m, int kk, double *__restrict__ lamb, int64_t sl, double *__restrict__ scrb,
                                                  int64_t sscr, int *__restrict__ flagb,
                                                  const int *__restrict__ only) {
   if (only != nullptr && only[blockIdx.x] == 0) return;  // job not selected
@@ -2027,12 +2104,9 @@ __global__ __launch_bounds__(512) void k_tri_eig(const double *__restrict__ db, 
   __shared__ double s_lo, s_hi, s_tn;
   const double *d0 = db + (int64_t)blockIdx.x * sv;
   const double *e0 = eb + (int64_t)blockIdx.x * sv;
-  double *Z = Zb + (int64_t)blockIdx.x * sZ;
   double *lam = lamb + (int64_t)blockIdx.x * sl;
   double *scr = scrb + (int64_t)blockIdx.x * sscr;
   const int tid = threadIdx.x;
-  const int64_t MK = (int64_t)m * kk;
-  double *U0 = scr, *U1 = scr + MK, *U2 = scr + 2 * MK;
   for (int k = tid; k < m; k += blockDim.x) {
     sd[k] = d0[k];
     const double ek = (k + 1 < m) ? e0[k] : 0.0;
@@ -2066,11 +2140,10 @@ __global__ __launch_bounds__(512) void k_tri_eig(const double *__restrict__ db, 
   const double tn = (tn_raw > 1e-280) ? 1.0 : 0.0;
   const double lo_s = s_lo * tsc, hi_s = s_hi * tsc;
   const double pivmin = 1e-290;
-  const double tiny = (tn > 0.0) ? 2.2e-16 : 0.0;
   const double pad = 1e-12 * tn + 1e-290;
   // eigenvalues above the noise floor: m - #{lambda < noise}; the rest only
   // need to complete an orthonormal basis (re-orthonormalisation follows)
-  const double gap = 1e-6, noise = 1e-14 * tn;
+  const double noise = 1e-14 * tn;
   __shared__ int s_nsig;
   if (tid == 0) s_nsig = (tn > 0.0) ? m - sturm_count(sd, se2, m, noise, pivmin) : 0;
   __syncthreads();
@@ -2183,6 +2256,45 @@ __global__ __launch_bounds__(512) void k_tri_eig(const double *__restrict__ db, 
     }
   }
   __syncthreads();
+  // hand-over to k_tri_vec: scaled eigenvalues, the scale, the count above the noise floor
+  double *tail = scr + tri_vec_tail(m, kk);
+  for (int t = tid; t < kk; t += blockDim.x) tail[t] = slam[t];
+  if (tid == 0) {
+    tail[kk] = tsc;
+    tail[kk + 1] = (double)nsig;
+    tail[kk + 2] = tn;
+  }
+  if (flagb != nullptr && tid == 0) flagb[blockIdx.x] = s_need;
+}
+
+// tri_vec: the eigenvectors of the eigenvalues that k_tri_eig found (same
+// jobs, same scratch), one thread per vector, 256 threads per job.
+__global__ __launch_bounds__(256) void k_tri_vec(const double *__restrict__ db, const double *__restrict__ eb,
+                                                 int64_t sv, int m, int kk, double *__restrict__ Zb, int64_t sZ,
+                                                 double *__restrict__ scrb, int64_t sscr, int *__restrict__ flagb,
+                                                 const int *__restrict__ only) {
+  if (only != nullptr && only[blockIdx.x] == 0) return;  // job not selected
+  __shared__ double sd[1024], se[1024], slam[256];
+  __shared__ int s_need;
+  const double *d0 = db + (int64_t)blockIdx.x * sv;
+  const double *e0 = eb + (int64_t)blockIdx.x * sv;
+  double *Z = Zb + (int64_t)blockIdx.x * sZ;
+  double *scr = scrb + (int64_t)blockIdx.x * sscr;
+  double *Xs = scr, *CKs = scr + (int64_t)m * kk;  // first solutions, elimination checkpoints
+  const double *tail = scr + tri_vec_tail(m, kk);
+  const int tid = threadIdx.x;
+  const double tsc = tail[kk];
+  const int nsig = (int)tail[kk + 1];
+  for (int k = tid; k < m; k += blockDim.x) {
+    sd[k] = d0[k] * tsc;
+    se[k] = ((k + 1 < m) ? e0[k] : 0.0) * tsc;
+  }
+  for (int t = tid; t < kk; t += blockDim.x) slam[t] = tail[t];
+  if (tid == 0) s_need = 0;
+  __syncthreads();
+  const double tn = tail[kk + 2];  // 1, or 0 for T = 0
+  const double tiny = (tn > 0.0) ? 2.2e-16 : 0.0;
+  const double gap = 1e-6;
   for (int t = tid; t < kk; t += blockDim.x) {
     if (t >= nsig) {  // noise: a pseudo-random direction, orthonormalised later
       for (int k = 0; k < m; ++k) {
@@ -2202,10 +2314,10 @@ __global__ __launch_bounds__(512) void k_tri_eig(const double *__restrict__ db, 
     if (!leader) continue;
     int t1 = t + 1;
     while (t1 < kk && t1 < nsig && close(t1) && (t1 % 32 != 0)) ++t1;
-    for (int u = t; u < t1; ++u) inv_iter_one(sd, se, m, kk, u, slam[u], tiny, U0, U1, U2, Z, t);
+    for (int u = t; u < t1; ++u) inv_iter_one(sd, se, m, kk, u, slam[u], tiny, Xs, CKs, Z, t);
   }
   __syncthreads();
-  if (flagb != nullptr && tid == 0) flagb[blockIdx.x] = s_need;
+  if (flagb != nullptr && tid == 0 && s_need) flagb[blockIdx.x] = 1;
 }
 
 
@@ -2788,8 +2900,8 @@ int launch_sytrd(hipStream_t st, int nb, double *A, int64_t sA, int m, double *d
 int launch_tri_eig(hipStream_t st, int nb, const double *d, const double *e, int64_t sv, int m, int kk, double *Z,
                    int64_t sZ, double *lam, int64_t sl, double *scr, int64_t sscr, int *needs_lq, const int *only) {
   if (m > 1024 || kk > 256) return -1;
-  hipLaunchKernelGGL(k_tri_eig, dim3(nb), dim3(512), 0, st, d, e, sv, m, kk, Z, sZ, lam, sl, scr, sscr, needs_lq,
-                     only);
+  hipLaunchKernelGGL(k_tri_eig, dim3(nb), dim3(512), 0, st, d, e, sv, m, kk, lam, sl, scr, sscr, needs_lq, only);
+  hipLaunchKernelGGL(k_tri_vec, dim3(nb), dim3(256), 0, st, d, e, sv, m, kk, Z, sZ, scr, sscr, needs_lq, only);
   return 0;
 }
 
@@ -2838,7 +2950,7 @@ void launch_svd_finish2(hipStream_t st, int nb, const double *Q, int64_t sQ, int
                      disc, qt ? 1 : 0, only);
 }
 
-int64_t tri_eig_scratch(int m, int kk) { return 3 * (int64_t)m * kk + 8; }
+int64_t tri_eig_scratch(int m, int kk) { return tri_vec_tail(m, kk) + kk + 8; }
 
 void launch_ritz(hipStream_t st, const double *Mm, const double *S, int m, int ld, const double *alpha,
                  const double *beta, double *out_gen, double *out_tri, int *info) {
