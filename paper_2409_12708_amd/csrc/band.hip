@@ -545,10 +545,10 @@ __device__ __forceinline__ void chase_step(double *S, int m, int j, int k, int N
   const double vi = (li == 0) ? 1.0 : xl * sc;  // the lane's own v (rows 0, 1; 0 past n)
   if (part == 0) {
     wsc[li] = vi;
-    if (li < n) {
-      V2[((int64_t)j * NS + k) * BW + li] = (li == 0) ? tp : vi;
-      S[xad] = (li == 0) ? ei : 0.0;  // the annihilated column: beta, then zeros
-    }
+    // all 16 entries: v is zero past the block, which lets the back
+    // transformation read whole blocks without bounds
+    V2[((int64_t)j * NS + k) * BW + li] = (li == 0) ? tp : vi;
+    if (li < n) S[xad] = (li == 0) ? ei : 0.0;  // the annihilated column: beta, then zeros
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -649,7 +649,7 @@ __global__ __launch_bounds__(CNT) void k_sb2st(const double *__restrict__ Ab, in
 // doubles: the workgroup loads it with one coalesced load per thread, 8
 // sweeps ahead, and stages it through a two-slot LDS ring.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(512) void k_q2apply(const double *__restrict__ V2b, int64_t sV2, int m,
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_q2apply(const double *__restrict__ V2b, int64_t sV2, int m,
                                                  double *__restrict__ Zb, int64_t sZ, int kk, int nslab,
                                                  const int *__restrict__ only) {
   const int job = blockIdx.x / nslab, slab = blockIdx.x % nslab;
@@ -694,12 +694,11 @@ __global__ __launch_bounds__(512) void k_q2apply(const double *__restrict__ V2b,
     if (i < 0) return;
     const int j = m - 3 - i;
     if (kq >= (m - 3 - j) / BW + 1) return;
-    const int r0 = j + 1 + BW * kq;
     const double *vp = ring + (i & 1) * RB + kq * BW;
-    double vr[16];
+    double vr[16];  // zero past row m - 1 (so rows past m - 1 stay zero)
     vr[0] = 1.0;
 #pragma unroll
-    for (int q = 1; q < 16; ++q) vr[q] = (r0 + q < m) ? vp[q] : 0.0;
+    for (int q = 1; q < 16; ++q) vr[q] = vp[q];
     double dot = 0.0;
 #pragma unroll
     for (int q = 0; q < 16; ++q) dot = fma(vr[q], w[(q - u + 16) & 15], dot);
