@@ -1310,7 +1310,8 @@ __global__ void k_ritz_vector(const double *__restrict__ Mm, const double *__res
 // left by sytrd (off = 1) or by the band reduction sy2sb (off = 16):
 // v_i[i+off] = 1, v_i[r] = A[i][r] for r > i+off, so that
 // H_{i0} ... H_{i0+15} = I - V^T T V.  One workgroup per (block, matrix):
-// G[q][p] = v_q . v_p (q < p), then T[0:p, p] = -tau_p T[0:p, 0:p] G[0:p, p].
+// G = V V^T (v_q . v_p; the entries q < p are used) on MFMA, then
+// T[0:p, p] = -tau_p T[0:p, 0:p] G[0:p, p].
 // Output Tf[job][block] (16 x 16, row-major).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_ormtr_tfac(const double *__restrict__ Ab, int64_t sA, int m,
@@ -1319,7 +1320,7 @@ __global__ __launch_bounds__(256) void k_ormtr_tfac(const double *__restrict__ A
                                                     const int *__restrict__ only, int off) {
   constexpr int NB = 16, VL = 516;
   __shared__ double V[NB * VL];
-  __shared__ double G[NB * NB], T[NB * NB], tv[NB];
+  __shared__ double G[NB * NB], T[NB * NB], tv[NB], Gp[4 * NB * NB];
   const int bi = blockIdx.x, job = blockIdx.y;
   if (only != nullptr && only[job] == 0) return;  // job not selected
   const double *A = Ab + (int64_t)job * sA;
@@ -1339,12 +1340,20 @@ __global__ __launch_bounds__(256) void k_ormtr_tfac(const double *__restrict__ A
   if (tid < NB) tv[tid] = (tid < pb) ? tau[i0 + tid] : 0.0;
   __syncthreads();
   {
-    const int q = tid / NB, p = tid % NB;
-    double acc = 0.0;
-    if (q < p)
-      for (int r = i0 + p + off; r < m; ++r) acc += V[q * VL + r] * V[p * VL + r];
-    G[tid] = acc;
+    // G = V V^T on MFMA (A and B take the same lane value): wave w over rows
+    // 128 w .. 128 w + 127 of the reflectors, the four partials summed in LDS
+    const int lane = tid % WAVE, wv = tid / WAVE, li = lane % 16, lk = lane / 16;
+    d4_t g = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
+    for (int k0 = 128 * wv; k0 < 128 * wv + 128; k0 += 4) {
+      const double v = V[li * VL + k0 + lk];
+      g = mfma16(v, v, g);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Gp[wv * 256 + (lk + 4 * r) * NB + li] = g[r];
   }
+  __syncthreads();
+  G[tid] = Gp[tid] + Gp[256 + tid] + Gp[512 + tid] + Gp[768 + tid];
   __syncthreads();
   if (tid < NB) {
     const int q = tid;
@@ -1372,7 +1381,9 @@ __global__ __launch_bounds__(256) void k_ormtr_tfac(const double *__restrict__ A
 //   W  = V Z        16 x 64, each wave over its 64 rows, summed in LDS
 //   X  = T W
 //   Z -= V^T X      accumulated into the resident blocks
-// Z is read once and written once.
+// Z is read once and written once.  Block bi's reflectors are zero above row
+// 16 bi + off, so row tiles above it are skipped; the next block's V and T
+// are loaded into registers while this block is applied.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(512) void k_ormtr2(const double *__restrict__ Ab, int64_t sA, int m,
                                                 const double *__restrict__ Tfb, int64_t sTf,
@@ -1409,49 +1420,65 @@ __global__ __launch_bounds__(512) void k_ormtr2(const double *__restrict__ Ab, i
 
   const int nref = m - off - 1;
   const int nblk = nref > 0 ? (nref + NB - 1) / NB : 0;
-  for (int bi = nblk - 1; bi >= 0; --bi) {
+  // block bi's V (thread tid: entries V[q][tid], coalesced along the rows of
+  // A) and T, loaded into registers one block ahead
+  double vn[NB], tn = 0.0;
+  // raw rows i0 .. i0 + 15 of A at column tid (a buffer load per row: one
+  // lane offset, the row as a scalar offset; masked when written to LDS)
+  const __amdgpu_buffer_rsrc_t ars =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(A), 0, (int)((int64_t)m * m * 8), 0x00020000);
+  auto load_block = [&](int bi) {
     const int i0 = bi * NB;
-    const int pb = (nref - i0) < NB ? (nref - i0) : NB;
-    __syncthreads();  // the previous block's readers of V / T are done
-    // thread tid loads V[q][tid] (q = 0..15), coalesced along the rows of A
 #pragma unroll
-    for (int q = 0; q < NB; ++q) {
-      const int i = i0 + q, r = tid;
-      double x = 0.0;
-      if (q < pb && r < m) {
-        if (r == i + off) x = 1.0;
-        else if (r > i + off) x = A[(int64_t)i * m + r];
+    for (int q = 0; q < NB; ++q)
+      vn[q] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(ars, 8 * tid, 8 * (i0 + q) * m, 0));
+    if (tid < NB * NB) tn = Tf[(int64_t)bi * NB * NB + tid];
+  };
+  if (nblk > 0) load_block(nblk - 1);
+  // every barrier below orders LDS only: the global data of a thread
+  // (its Z entries, its V / T loads) is its own
+  for (int bi = nblk - 1; bi >= 0; --bi) {
+    const int rlo = bi * NB + off;  // rows < rlo: this block's V is zero there
+    lds_barrier();  // the previous block's readers of V / T are done
+    {
+      const int i0 = bi * NB;
+      const int pb = (nref - i0) < NB ? (nref - i0) : NB;
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const int i = i0 + q;
+        V[q * VL + tid] = (q < pb && tid < m && tid >= i + off) ? ((tid == i + off) ? 1.0 : vn[q]) : 0.0;
       }
-      V[q * VL + r] = x;
     }
-    if (tid < NB * NB) T[tid] = Tf[(int64_t)bi * NB * NB + tid];
-    __syncthreads();
+    if (tid < NB * NB) T[tid] = tn;
+    lds_barrier();
+    if (bi > 0) load_block(bi - 1);
     // partial W = V Z over this wave's rows
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       d4_t acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int i = 0; i < 4; ++i)
+        if (64 * wv + 16 * i + 15 >= rlo)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) acc = mfma16(V[li * VL + 64 * wv + 16 * i + 4 * r + lk], z[i][j][r], acc);
+          for (int r = 0; r < 4; ++r) acc = mfma16(V[li * VL + 64 * wv + 16 * i + 4 * r + lk], z[i][j][r], acc);
 #pragma unroll
       for (int r = 0; r < 4; ++r) Wp[(wv * NB + lk + 4 * r) * CS + 16 * j + li] = acc[r];
     }
-    __syncthreads();
+    lds_barrier();
     for (int e = tid; e < NB * CS; e += 512) {
       double acc = 0.0;
 #pragma unroll
       for (int w = 0; w < NWV; ++w) acc += Wp[w * NB * CS + e];
       Ws[e] = acc;
     }
-    __syncthreads();
+    lds_barrier();
     for (int e = tid; e < NB * CS; e += 512) {
       const int p = e / CS, c = e % CS;
       double acc = 0.0;
       for (int q = p; q < NB; ++q) acc += T[p * NB + q] * Ws[q * CS + c];
       Xs[e] = acc;
     }
-    __syncthreads();
+    lds_barrier();
     // Z -= V^T X
 #pragma unroll
     for (int s4 = 0; s4 < 4; ++s4) {
@@ -1460,6 +1487,7 @@ __global__ __launch_bounds__(512) void k_ormtr2(const double *__restrict__ Ab, i
       for (int j = 0; j < 4; ++j) b[j] = Xs[(4 * s4 + lk) * CS + 16 * j + li];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
+        if (64 * wv + 16 * i + 15 < rlo) continue;
         const double a = -V[(4 * s4 + lk) * VL + 64 * wv + 16 * i + li];
 #pragma unroll
         for (int j = 0; j < 4; ++j) z[i][j] = mfma16(a, b[j], z[i][j]);
