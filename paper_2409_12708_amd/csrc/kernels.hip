@@ -439,13 +439,13 @@ __device__ __forceinline__ void block_reflect_rows(double *__restrict__ X, int l
 }
 
 // lq2: X (m x n) = L Q by blocked Householder (panels of 16 rows, compact WY),
-// the trailing update and the formation of Q on MFMA tiles.  One workgroup
-// of 512 threads per matrix.  Same outputs and storage as k_lq.
+// the trailing update on MFMA tiles.  One workgroup of 512 threads per
+// matrix.  Outputs L, the reflectors (in X) and the T factor of every panel
+// (Tb); k_lq_q forms Q from them.
 template <int NMAX, bool TR>
 __global__ __launch_bounds__(512) void k_lq2(double *__restrict__ Xb, int64_t sX, int m, int n,
-                                             double *__restrict__ Lb, int64_t sL, double *__restrict__ Qb,
-                                             int64_t sQ, double *__restrict__ Tb, int64_t sT, int ldl, int ldq,
-                                             const int *__restrict__ only) {
+                                             double *__restrict__ Lb, int64_t sL, double *__restrict__ Tb,
+                                             int64_t sT, int ldl, const int *__restrict__ only) {
   if (only != nullptr && only[blockIdx.x] == 0) return;  // the whole workgroup: job not selected
   constexpr int NB = 16, NWV = 8;
   constexpr int VLD = NMAX + 1;     // padded row stride: rows of V fall in different LDS banks
@@ -459,7 +459,6 @@ __global__ __launch_bounds__(512) void k_lq2(double *__restrict__ Xb, int64_t sX
   double *Gd = tau + 16;            // 16 x 16 reflector dot products
   double *X = Xb + (int64_t)blockIdx.x * sX;
   double *Lo = Lb + (int64_t)blockIdx.x * sL;
-  double *Qo = Qb + (int64_t)blockIdx.x * sQ;
   double *Ts = Tb + (int64_t)blockIdx.x * sT;
   const int tid = threadIdx.x, lane = tid % WAVE, wid = tid / WAVE;
   const int k = m < n ? m : n;
@@ -618,17 +617,66 @@ __global__ __launch_bounds__(512) void k_lq2(double *__restrict__ Xb, int64_t sX
         return (c <= r) ? X[XI(r, c)] : 0.0;
       },
       [&](int64_t e, double v) { Lo[(e / k) * ldl + e % k] = v; });
-  // Q = I (k x n), walked in its storage order (with TR, Q^T: column index slowest)
-  for (int64_t e = tid; e < (int64_t)k * n; e += blockDim.x) {
-    const int r = TR ? (int)(e % k) : (int)(e / n), c = TR ? (int)(e / k) : (int)(e % n);
-    Qo[TR ? (int64_t)c * ldq + r : (int64_t)r * ldq + c] = (r == c) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  const int npanel = (k + NB - 1) / NB;
-  for (int pi = npanel - 1; pi >= 0; --pi) {
+
+}
+
+// lq_q: Q (k x n, k = min(m, n)) of the LQ that k_lq2 left (reflectors in X,
+// T factors in Tb): Q = rows 0..k-1 of H_0 H_1 ... H_{k-1}, applied to I
+// panel by panel, last first; row r of Q only changes under the panels
+// that start at or before it.  Rows of Q transform independently, so one
+// workgroup (8 waves) owns a slab of 16 rows for the whole pass and applies
+// to it the panels s, s-1, ..., 0 of its slab s; wave w holds columns
+// [w NMAX/8, (w+1) NMAX/8) as 16 x 16 tiles in the transposed accumulator
+// layout (lane l, register r <-> row r0 + l%16, column c + l/16 + 4r),
+// which is also the A operand of the 16x16x4 step over those four columns:
+//   W  = Q V^T      16 x 16, each wave over its columns, summed in LDS
+//   X  = W T^T
+//   Q -= X V        into the resident tiles (as Q^T -= V^T X^T)
+// Column tiles left of a panel's first column are skipped.  Q is written
+// once; V is read once per slab, and a matrix's slabs sit on one XCD (block
+// index b: XCD b mod 8) so that they share its panels in L2.
+template <int NMAX, bool TR>
+__global__ __launch_bounds__(512) void k_lq_q(const double *__restrict__ Xb, int64_t sX, int m, int n,
+                                              double *__restrict__ Qb, int64_t sQ, const double *__restrict__ Tb,
+                                              int64_t sT, int ldq, int nb, int nslab,
+                                              const int *__restrict__ only) {
+  constexpr int NB = 16, NWV = 8, VLD = NMAX + 1, CW = NMAX / NWV, NT16 = CW / 16;
+  // blocks b = x + 8 y: XCD x runs slab y % nslab of job 8 (y / nslab) + x
+  const int bx = blockIdx.x % 8, by = blockIdx.x / 8;
+  const int job = (by / nslab) * 8 + bx, s = by % nslab;
+  if (job >= nb) return;
+  if (only != nullptr && only[job] == 0) return;  // job not selected
+  extern __shared__ double lds[];
+  double *P = lds;               // NB x VLD: the panel's V over all n columns
+  double *Wp = P + NB * VLD;     // NWV x 256 partial W ([row][p])
+  double *Ws = Wp + NWV * 256;   // 256: W
+  double *Xs = Ws + 256;         // 256: X = W T^T ([row][p])
+  double *Tt = Xs + 256;         // 256: T^T
+  const double *X = Xb + (int64_t)job * sX;
+  double *Q = Qb + (int64_t)job * sQ;
+  const double *Ts = Tb + (int64_t)job * sT;
+  const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
+  const int li = lane % 16, lk = lane / 16;
+  const int k = m < n ? m : n;
+  const int r0 = 16 * s, cb = wv * CW;
+  auto XI = [&](int r, int c) -> int64_t { return TR ? (int64_t)c * m + r : (int64_t)r * n + c; };
+  d4_t q[NT16];
+#pragma unroll
+  for (int t = 0; t < NT16; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = r0 + li, col = cb + 16 * t + lk + 4 * r;
+      q[t][r] = (row == col && row < k) ? 1.0 : 0.0;
+    }
+  // P holds zeros left of every panel's columns: zeroed once here, and each
+  // panel (first columns decreasing) rewrites columns from its own first one
+  for (int e = tid; e < NB * VLD; e += blockDim.x) P[e] = 0.0;
+  for (int pi = s; pi >= 0; --pi) {
     const int i0 = pi * NB;
     const int pb = (k - i0) < NB ? (k - i0) : NB;
     const int w = n - i0;
+    lds_barrier();  // the previous panel's readers of P / Tt are done
+    // V[p][i0 + c] = 0 for c < p, 1 at c = p, the reflector beyond
     copy_loop<8>(
         (int64_t)NB * w, tid, blockDim.x,
         [&](int64_t e) -> double {
@@ -638,17 +686,65 @@ __global__ __launch_bounds__(512) void k_lq2(double *__restrict__ Xb, int64_t sX
         },
         [&](int64_t e, double v) {
           const int p = TR ? (int)(e % NB) : (int)(e / w), c = TR ? (int)(e / NB) : (int)(e % w);
-          P[p * VLD + c] = v;
+          P[p * VLD + i0 + c] = v;
         });
-    for (int e = tid; e < 256; e += blockDim.x) {
-      const int q = e / 16, p = e % 16;
-      TT[e] = Ts[(int64_t)pi * 256 + p * 16 + q];  // T^T
-    }
+    if (tid < 256) Tt[tid] = Ts[(int64_t)pi * 256 + (tid % 16) * 16 + tid / 16];
     __syncthreads();
-    // Q_r <- Q_r - (Q_r V^T) T^T V for rows i0..k-1
-    block_reflect_rows<NWV, TR>(Qo, ldq, (int64_t)(TR ? (int64_t)(n - 1) * ldq + k : (int64_t)(k - 1) * ldq + n) * 8,
-                                i0, k, i0, w, P, VLD, TT, Wp, WT);
+    // partial W = Q V^T over this wave's columns
+    {
+      d4_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int t = 0; t < NT16; ++t)
+        if (cb + 16 * t + 15 >= i0)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int c = cb + 16 * t + 4 * r + lk;
+            acc = mfma16(q[t][r], (c < n) ? P[li * VLD + c] : 0.0, acc);
+          }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Wp[wv * 256 + (lk + 4 * r) * 16 + li] = acc[r];
+    }
+    lds_barrier();
+    if (tid < 256) {
+      double acc = 0.0;
+#pragma unroll
+      for (int w = 0; w < NWV; ++w) acc += Wp[w * 256 + tid];
+      Ws[tid] = acc;
+    }
+    lds_barrier();
+    if (tid < 256) {
+      const int r = tid / 16, p = tid % 16;
+      double acc = 0.0;
+#pragma unroll
+      for (int qq = 0; qq < 16; ++qq) acc += Ws[r * 16 + qq] * Tt[qq * 16 + p];
+      Xs[tid] = acc;
+    }
+    lds_barrier();
+    // Q^T -= V^T X^T on the resident tiles: A = V^T (lane: column li of the
+    // tile, reflector k0 + lk), B = X^T (lane: reflector k0 + lk, row li)
+    {
+      double bx4[4];
+#pragma unroll
+      for (int k4 = 0; k4 < 4; ++k4) bx4[k4] = Xs[li * 16 + 4 * k4 + lk];
+#pragma unroll
+      for (int t = 0; t < NT16; ++t) {
+        if (cb + 16 * t + 15 < i0) continue;
+        const int c = cb + 16 * t + li;
+#pragma unroll
+        for (int k4 = 0; k4 < 4; ++k4) {
+          const double a = (c < n) ? -P[(4 * k4 + lk) * VLD + c] : 0.0;
+          q[t] = mfma16(a, bx4[k4], q[t]);
+        }
+      }
+    }
   }
+#pragma unroll
+  for (int t = 0; t < NT16; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = r0 + li, col = cb + 16 * t + lk + 4 * r;
+      if (row < k && col < n) Q[TR ? (int64_t)col * ldq + row : (int64_t)row * ldq + col] = q[t][r];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -2766,13 +2862,18 @@ static void lq_variant(hipStream_t st, int nb, double *X, int64_t sX, int m, int
                        int64_t sQ, double *Tw, int64_t sT, int ldl, int ldq, const int *only) {
   constexpr int NWV = 8;
   constexpr size_t lds = (16 * (NMAX + 1) + 256 + 256 + (NWV + 1) * 256 + 256 + 16 + 256) * sizeof(double);
+  constexpr size_t lds_q = (16 * (NMAX + 1) + NWV * 256 + 3 * 256) * sizeof(double);
   static bool attr = false;
   if (!attr) {
     set_lds(k_lq2<NMAX, TR>, lds);
+    set_lds(k_lq_q<NMAX, TR>, lds_q);
     attr = true;
   }
-  hipLaunchKernelGGL((k_lq2<NMAX, TR>), dim3(nb), dim3(512), lds, st, X, sX, m, n, L, sL, Q, sQ, Tw, sT, ldl, ldq,
-                     only);
+  hipLaunchKernelGGL((k_lq2<NMAX, TR>), dim3(nb), dim3(512), lds, st, X, sX, m, n, L, sL, Tw, sT, ldl, only);
+  const int k = m < n ? m : n, nslab = (k + 15) / 16;
+  if (nslab > 0)
+    hipLaunchKernelGGL((k_lq_q<NMAX, TR>), dim3((nb + 7) / 8 * 8 * nslab), dim3(512), lds_q, st, X, sX, m, n, Q, sQ,
+                       Tw, sT, ldq, nb, nslab, only);
 }
 
 int launch_lq(hipStream_t st, int nb, double *X, int64_t sX, int m, int n, double *L, int64_t sL, double *Q,
