@@ -21,6 +21,9 @@ mps          MPS primitives: layer apply (eq. elementary_MPO + App. C),
 hamiltonian  Algorithm 1 (sequential sum) and the pairwise reduction tree
              (Sec. 4.5, Fig. 11) for H = T + V.
 lanczos      Global Krylov (Lanczos) step with Gram-Schmidt (Sec. 2.2).
+evolution    Krylov time evolution exp(-i delta H~) of a complex state held as
+             a pair of real MPS (Sec. 2.2, App. A).
+gradient     Energy gradient with respect to the THC factors (Sec. 2.3).
 hf           Closed-form Hartree-Fock energy of eq. 1 for a determinant.
 
 Parity status: every function is pinned by
