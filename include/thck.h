@@ -294,6 +294,54 @@ thc_status krylov_get_vector(thc_krylov *state, int32_t i, thc_mps *out, void *h
 /* Copy the (m x m) leading blocks of M and S (host, row-major), m = steps taken. */
 thc_status krylov_get_matrices(thc_krylov *state, double *Mm, double *S, int32_t *m);
 
+/* Krylov time evolution (Sec. 2.2: psi(t + delta) = sum_i a_i v_i with
+ * a(delta) = exp(-i delta H~) a(0); error bounds in App. A) of complex states
+ * under the real H of each instance's context, n_steps steps of size delta,
+ * for n_inst independent instances (their own contexts, so L and N may
+ * differ, and their own opts, so D may differ), all on one stream, one
+ * time step of each instance in turn.
+ *
+ * A complex state is a pair of real MPS, psi = re + i im.  Because H is
+ * real, H acts on the two parts separately; each part is compressed on its
+ * own to opts[q].D_max by the rules of mps_sum_compress.  Per step, with
+ * v_0 = psi / ||psi||: w_i = compressed H v_i, M_ji = <v_j|w_i> (complex,
+ * j <= i); unless i = K-1, v_{i+1} = r / ||r|| for r = compressed
+ * (w_i - sum_j M_ji v_j), with S and M extended.  The basis stops early
+ * (m < K) when ||r|| <= 1e-10 sqrt(sum_j |M_ji|^2 + ||r||^2): the Krylov space
+ * is invariant and the step exact.  The coefficients a over v_0..v_{m-1}
+ * follow from the effective Hamiltonian of eq. eff_H (H_sym = (M + M^H)/2
+ * in a basis orthonormal in the metric S, over the eigen-directions of S
+ * above 1e-10, eq. reortho), computed on the device in FP64, and
+ * psi(t + delta) = ||psi|| sum_i a_i v_i.  A complex combination
+ * sum_j c_j x_j is two sum-compressions: the real part over the terms
+ * (Re c_j, x_j,re), (-Im c_j, x_j,im), the imaginary part over
+ * (Re c_j, x_j,im), (Im c_j, x_j,re), j ascending, dropping absent parts
+ * and exactly zero coefficients (a part with no term left is zero).
+ *
+ *   ctxs[q]       context of instance q (n = 2L sites).
+ *   psi_re[q]     real part (device MPS; NULL = zero).
+ *   psi_im        NULL (every imaginary part zero) or n_inst entries, each
+ *                 NULL (zero) or a device MPS.  A part whose norm is zero
+ *                 is treated as absent.  Not both parts zero.
+ *   opts[q]       options of instance q (D_max, precision of the absorb
+ *                 contractions: FP32 / BF16x3 parts are the complex64 form).
+ *   K             Krylov vectors per step, 1..16.
+ *   out_re[q], out_im[q]  caller MPS for the final parts, capacity at least
+ *                 thc_mps_capacity(n, D_max) (and the input's size); a zero
+ *                 part is written as the bond-1 MPS of zeros, canonical = 0.
+ *                 Inputs are copied before any output is written, so outputs
+ *                 may alias inputs.
+ *   krylov_dims   host n_inst x n_steps (nullable): basis size m of each step.
+ *   st            accumulated statistics of every compression (nullable).
+ * Synchronises (after every compression batch, every overlap and at the
+ * end).  Returns THC_EINVAL for zero-norm states or bad shapes,
+ * THC_ENONFINITE for non-finite inputs or coefficients, THC_ECAPACITY for
+ * small outputs; outputs are unspecified on error. */
+thc_status krylov_evolve(int32_t n_inst, thc_ctx *const *ctxs, const thc_mps *const *psi_re,
+                         const thc_mps *const *psi_im, const thc_opts *opts, int32_t K, double delta,
+                         int32_t n_steps, thc_mps *const *out_re, thc_mps *const *out_im, int32_t *krylov_dims,
+                         thc_stats *st, void *hip_stream);
+
 /* Compress one MPS to D (QR sweep then SVD truncation sweep, Fig. 3). */
 thc_status mps_compress(thc_ctx *ctx, const thc_mps *in, thc_mps *out, const thc_opts *o,
                         thc_stats *st, void *hip_stream);

@@ -4,9 +4,9 @@ The compute lives in libthck.so (hand-written HIP for gfx950, C ABI in
 include/thck.h); ``thck`` is the ctypes binding.
 """
 from .thck import (Context, DeviceMPS, Krylov, ThcEnergy, ThcError, ThcStats, capacity,  # noqa: F401
-                   load_library, make_opts, thc_energy, EXPORTS, FLAG_GRAPHS, FLAG_SVD_JACOBI, FLAG_SYTRD_ONE_STAGE,
+                   evolve, load_library, make_opts, thc_energy, EXPORTS, FLAG_GRAPHS, FLAG_SVD_JACOBI, FLAG_SYTRD_ONE_STAGE,
                    FLAG_TIME_KERNELS)
 
-__all__ = ["Context", "DeviceMPS", "Krylov", "ThcEnergy", "ThcError", "ThcStats", "capacity", "load_library",
+__all__ = ["Context", "DeviceMPS", "Krylov", "ThcEnergy", "ThcError", "ThcStats", "capacity", "evolve", "load_library",
            "make_opts", "thc_energy", "EXPORTS", "FLAG_GRAPHS", "FLAG_SVD_JACOBI", "FLAG_SYTRD_ONE_STAGE",
            "FLAG_TIME_KERNELS"]

@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstdint>
 #include <cstring>
@@ -2188,6 +2189,345 @@ thc_status krylov_get_matrices(thc_krylov *k, double *Mm, double *S, int32_t *m)
       if (S) S[a * mm + b] = k->S[a * R + b];
     }
   return THC_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Krylov time evolution (Sec. 2.2: psi(t + delta) = sum_i a_i v_i with
+// a(delta) = exp(-i delta H~) a(0); error bounds in App. A).  H is real, so a
+// complex state is held as a pair of real MPS, its real and imaginary part,
+// either of which may be the zero MPS (not stored); H acts on each part
+// alone, overlaps combine four real ones, and a complex combination
+// sum_j c_j x_j is two real sum-compressions: the real part over the terms
+// (Re c_j, x_j,re), (-Im c_j, x_j,im), the imaginary part over
+// (Re c_j, x_j,im), (Im c_j, x_j,re), j ascending, leaving out absent parts
+// and exactly zero coefficients.
+// ===========================================================================
+namespace {
+
+using cplx = std::complex<double>;
+constexpr double EVOLVE_BREAKDOWN = 1e-10;
+
+struct RPart {
+  std::unique_ptr<DevBuf> buf = std::make_unique<DevBuf>();
+  std::vector<int> b;
+  std::vector<int64_t> off;
+  int canon = 0;
+  bool zero = true;
+};
+
+struct CState {
+  RPart re, im;
+};
+
+struct EvolveWork {
+  int n = 0;
+  int64_t cap = 0;
+  std::vector<CState> v, w;
+  std::vector<double> hM, hS;  // host staging: Mr, Mi, Sr, Si (K x K each)
+  DevBuf dMS, dA, dInfo;
+};
+
+void part_init(RPart &p, int n, int64_t cap) {
+  p.buf->ensure((size_t)std::max<int64_t>(cap, 1) * sizeof(double));
+  p.b.assign(n + 1, 1);
+  p.off.assign(n, 0);
+  p.canon = 0;
+  p.zero = true;
+}
+
+thc_mps part_view(RPart &p, int n) {
+  thc_mps m{};
+  m.n_sites = n;
+  m.d = 2;
+  m.bonds = p.b.data();
+  m.offsets = p.off.data();
+  m.data = p.buf->as<double>();
+  m.capacity = (int64_t)(p.buf->bytes / sizeof(double));
+  m.canonical = p.canon;
+  return m;
+}
+
+int64_t used_elems(const std::vector<int> &b, const std::vector<int64_t> &off) {
+  int64_t u = 0;
+  for (size_t j = 0; j < off.size(); ++j) u = std::max(u, off[j] + (int64_t)b[j] * 2 * b[j + 1]);
+  return u;
+}
+
+void add_stats(thc_stats &a, const thc_stats &s) {
+  a.discarded_weight_max = std::max(a.discarded_weight_max, s.discarded_weight_max);
+  a.flops_model += s.flops_model;
+  a.n_compressions += s.n_compressions;
+  a.n_launches += s.n_launches;
+  a.max_bond = std::max(a.max_bond, s.max_bond);
+  a.jacobi_sweeps_max = std::max(a.jacobi_sweeps_max, s.jacobi_sweeps_max);
+  a.nonconverged += s.nonconverged;
+  a.svd_fallbacks += s.svd_fallbacks;
+  a.graph_captures += s.graph_captures;
+  a.graph_replays += s.graph_replays;
+  for (int q = 0; q < THC_NK; ++q) {
+    a.kernel_ms[q] += s.kernel_ms[q];
+    a.kernel_flops[q] += s.kernel_flops[q];
+    a.kernel_launches[q] += s.kernel_launches[q];
+    a.kernel_bytes[q] += s.kernel_bytes[q];
+  }
+}
+
+void check(thc_status r) {
+  if (r != THC_OK) raise(r, thc_last_error());
+}
+
+double rov(thc_ctx *ctx, RPart &a, RPart &b, int n, hipStream_t st) {
+  if (a.zero || b.zero) return 0.0;
+  thc_mps x = part_view(a, n), y = part_view(b, n);
+  double r = 0.0;
+  check(mps_overlap(ctx, &x, &y, &r, st));
+  return r;
+}
+
+// <a|b> = <a_r|b_r> + <a_i|b_i> + i (<a_r|b_i> - <a_i|b_r>)
+cplx cov(thc_ctx *ctx, CState &a, CState &b, int n, hipStream_t st) {
+  return cplx(rov(ctx, a.re, b.re, n, st) + rov(ctx, a.im, b.im, n, st),
+              rov(ctx, a.re, b.im, n, st) - rov(ctx, a.im, b.re, n, st));
+}
+
+void part_copy(RPart &src, RPart &dst, int n, hipStream_t st) {
+  dst.zero = src.zero;
+  if (src.zero) return;
+  const int64_t u = used_elems(src.b, src.off);
+  dst.buf->ensure((size_t)std::max<int64_t>(u, 1) * sizeof(double));
+  HIPCHK(hipMemcpyAsync(dst.buf->p, src.buf->p, (size_t)u * sizeof(double), hipMemcpyDeviceToDevice, st));
+  dst.b = src.b;
+  dst.off = src.off;
+  dst.canon = src.canon;
+  (void)n;
+}
+
+void cscale(CState &x, double c, hipStream_t st) {
+  for (RPart *p : {&x.re, &x.im})
+    if (!p->zero) launch_scale(st, p->buf->as<double>() + p->off[0], (int64_t)p->b[0] * 2 * p->b[1], c);
+  HIPCHK(hipGetLastError());
+}
+
+// out <- compressed sum_j c_j x_j (out must not be one of the x_j)
+void ccombine(thc_ctx *ctx, const thc_opts &o, const std::vector<cplx> &c, const std::vector<CState *> &x,
+              CState &out, int n, thc_stats &acc, hipStream_t st) {
+  for (int part = 0; part < 2; ++part) {
+    std::vector<double> co;
+    std::vector<thc_mps> views;
+    for (size_t j = 0; j < x.size(); ++j) {
+      const double first = c[j].real(), second = part == 0 ? -c[j].imag() : c[j].imag();
+      RPart &same = part == 0 ? x[j]->re : x[j]->im, &other = part == 0 ? x[j]->im : x[j]->re;
+      if (!same.zero && first != 0.0) { co.push_back(first); views.push_back(part_view(same, n)); }
+      if (!other.zero && second != 0.0) { co.push_back(second); views.push_back(part_view(other, n)); }
+    }
+    RPart &dst = part == 0 ? out.re : out.im;
+    if (co.empty()) { dst.zero = true; continue; }
+    std::vector<const thc_mps *> ptrs;
+    for (auto &v : views) ptrs.push_back(&v);
+    thc_mps ov = part_view(dst, n);
+    thc_stats s{};
+    check(mps_sum_compress(ctx, (int)co.size(), co.data(), ptrs.data(), &ov, &o, &s, st));
+    add_stats(acc, s);
+    dst.canon = ov.canonical;
+    dst.zero = false;
+  }
+}
+
+void capply(thc_ctx *ctx, const thc_opts &o, CState &x, CState &out, int n, thc_stats &acc, hipStream_t st) {
+  for (int part = 0; part < 2; ++part) {
+    RPart &src = part == 0 ? x.re : x.im, &dst = part == 0 ? out.re : out.im;
+    dst.zero = src.zero;
+    if (src.zero) continue;
+    thc_mps iv = part_view(src, n), ov = part_view(dst, n);
+    thc_stats s{};
+    check(mps_apply_thc_H(ctx, &iv, &ov, &o, &s, st));
+    add_stats(acc, s);
+    dst.canon = ov.canonical;
+  }
+}
+
+// One time step psi(t) -> psi(t + delta) with at most K Krylov vectors;
+// returns the basis size used (smaller than K when the space is invariant).
+int evolve_step(thc_ctx *ctx, const thc_opts &o, EvolveWork &W, CState &psi, int K, double delta, thc_stats &acc,
+                hipStream_t st) {
+  const int n = W.n;
+  const double nn = cov(ctx, psi, psi, n, st).real();
+  if (!(nn > 0.0) || !std::isfinite(nn)) raise(THC_EINVAL, "state has zero or non-finite norm");
+  const double nrm = std::sqrt(nn);
+  part_copy(psi.re, W.v[0].re, n, st);
+  part_copy(psi.im, W.v[0].im, n, st);
+  cscale(W.v[0], 1.0 / nrm, st);
+  std::vector<cplx> Mm(K * K), S(K * K);
+  S[0] = cov(ctx, W.v[0], W.v[0], n, st);
+  int m = K;
+  for (int i = 0; i < K; ++i) {
+    capply(ctx, o, W.v[i], W.w[i], n, acc, st);
+    for (int j = 0; j <= i; ++j) Mm[j * K + i] = cov(ctx, W.v[j], W.w[i], n, st);
+    if (i == K - 1) break;
+    std::vector<cplx> c{1.0};
+    std::vector<CState *> x{&W.w[i]};
+    for (int j = 0; j <= i; ++j) {
+      c.push_back(-Mm[j * K + i]);
+      x.push_back(&W.v[j]);
+    }
+    ccombine(ctx, o, c, x, W.v[i + 1], n, acc, st);
+    const double rr = cov(ctx, W.v[i + 1], W.v[i + 1], n, st).real();
+    if (!std::isfinite(rr)) raise(THC_ENONFINITE, "non-finite Krylov residual");
+    const double b = std::sqrt(std::max(rr, 0.0));
+    double hn = b * b;
+    for (int j = 0; j <= i; ++j) hn += std::norm(Mm[j * K + i]);
+    if (!(b > EVOLVE_BREAKDOWN * std::sqrt(hn))) {
+      m = i + 1;
+      break;
+    }
+    cscale(W.v[i + 1], 1.0 / b, st);
+    for (int j = 0; j <= i + 1; ++j) {
+      S[(i + 1) * K + j] = cov(ctx, W.v[i + 1], W.v[j], n, st);
+      S[j * K + i + 1] = std::conj(S[(i + 1) * K + j]);
+    }
+    for (int l = 0; l <= i; ++l) Mm[(i + 1) * K + l] = cov(ctx, W.v[i + 1], W.w[l], n, st);
+  }
+  // a(delta) on the device
+  W.hM.assign(4 * K * K, 0.0);
+  for (int q = 0; q < K * K; ++q) {
+    W.hM[q] = Mm[q].real();
+    W.hM[K * K + q] = Mm[q].imag();
+    W.hM[2 * K * K + q] = S[q].real();
+    W.hM[3 * K * K + q] = S[q].imag();
+  }
+  W.dMS.ensure(4 * K * K * sizeof(double));
+  W.dA.ensure(2 * K * sizeof(double));
+  W.dInfo.ensure(4 * sizeof(int));
+  double *d = W.dMS.as<double>();
+  HIPCHK(hipMemcpyAsync(d, W.hM.data(), 4 * K * K * sizeof(double), hipMemcpyHostToDevice, st));
+  launch_evolve_coeffs(st, d, d + K * K, d + 2 * K * K, d + 3 * K * K, m, K, delta, nrm, W.dA.as<double>(),
+                       W.dInfo.as<int>());
+  HIPCHK(hipGetLastError());
+  std::vector<double> a(2 * m);
+  HIPCHK(hipMemcpyAsync(a.data(), W.dA.p, 2 * m * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  std::vector<cplx> c(m);
+  std::vector<CState *> x(m);
+  for (int i = 0; i < m; ++i) {
+    if (!std::isfinite(a[i]) || !std::isfinite(a[m + i])) raise(THC_ENONFINITE, "non-finite evolution coefficient");
+    c[i] = cplx(a[i], a[m + i]);
+    x[i] = &W.v[i];
+  }
+  ccombine(ctx, o, c, x, psi, n, acc, st);
+  return m;
+}
+
+// caller MPS -> owned part (NULL or zero norm -> the zero part)
+void load_part(thc_ctx *ctx, const thc_mps *src, RPart &p, int n, int64_t cap, hipStream_t st) {
+  p.zero = true;
+  p.b.assign(n + 1, 1);
+  p.off.assign(n, 0);
+  int64_t u = 0;
+  if (src) {
+    check_mps(src, n);
+    u = used_elems(std::vector<int>(src->bonds, src->bonds + n + 1),
+                   std::vector<int64_t>(src->offsets, src->offsets + n));
+  }
+  // sized once (a later growth would drop the contents)
+  p.buf->ensure((size_t)std::max<int64_t>(std::max(u, cap), 1) * sizeof(double));
+  if (!src) return;
+  HIPCHK(hipMemcpyAsync(p.buf->p, src->data, (size_t)u * sizeof(double), hipMemcpyDeviceToDevice, st));
+  p.b.assign(src->bonds, src->bonds + n + 1);
+  p.off.assign(src->offsets, src->offsets + n);
+  p.canon = src->canonical != 0;
+  p.zero = false;
+  const double nn = rov(ctx, p, p, n, st);
+  if (!std::isfinite(nn)) raise(THC_ENONFINITE, "non-finite input state");
+  if (nn == 0.0) p.zero = true;
+}
+
+// owned part -> caller MPS (the zero part as a bond-1 MPS of zeros)
+void store_part(RPart &p, thc_mps *dst, int n, hipStream_t st) {
+  if (!dst || dst->n_sites != n || dst->d != 2 || !dst->bonds || !dst->offsets || !dst->data)
+    raise(THC_EINVAL, "bad output MPS");
+  if (p.zero) {
+    if (dst->capacity < 2 * (int64_t)n) raise(THC_ECAPACITY, "output capacity below 2 n");
+    HIPCHK(hipMemsetAsync(dst->data, 0, 2 * (size_t)n * sizeof(double), st));
+    for (int j = 0; j <= n; ++j) dst->bonds[j] = 1;
+    for (int j = 0; j < n; ++j) dst->offsets[j] = 2 * j;
+    dst->canonical = 0;
+    return;
+  }
+  const int64_t u = used_elems(p.b, p.off);
+  if (dst->capacity < u) raise(THC_ECAPACITY, "output capacity below the evolved state's size");
+  HIPCHK(hipMemcpyAsync(dst->data, p.buf->p, (size_t)u * sizeof(double), hipMemcpyDeviceToDevice, st));
+  for (int j = 0; j <= n; ++j) dst->bonds[j] = p.b[j];
+  for (int j = 0; j < n; ++j) dst->offsets[j] = p.off[j];
+  dst->canonical = p.canon;
+}
+
+}  // namespace
+
+extern "C" {
+
+thc_status krylov_evolve(int32_t n_inst, thc_ctx *const *ctxs, const thc_mps *const *psi_re,
+                         const thc_mps *const *psi_im, const thc_opts *opts, int32_t K, double delta,
+                         int32_t n_steps, thc_mps *const *out_re, thc_mps *const *out_im, int32_t *krylov_dims,
+                         thc_stats *st, void *hip_stream) {
+  if (n_inst < 1 || !ctxs || !psi_re || !opts || !out_re || !out_im) return fail(THC_EINVAL, "NULL argument");
+  if (K < 1 || 2 * K > RITZ_MAX) return fail(THC_EINVAL, "K must be in [1, 16]");
+  if (n_steps < 0) return fail(THC_EINVAL, "n_steps must be >= 0");
+  if (!std::isfinite(delta)) return fail(THC_ENONFINITE, "non-finite time step");
+  return run_guarded([&] {
+    hipStream_t s = (hipStream_t)hip_stream;
+    std::vector<thc_opts> oo(n_inst);
+    std::vector<CState> state(n_inst);
+    int64_t cap = 0;
+    int nmax = 0;
+    for (int q = 0; q < n_inst; ++q) {
+      if (!ctxs[q]) raise(THC_EINVAL, "NULL context");
+      int D;
+      oo[q] = norm_opts(&opts[q], &D);
+      const int n = ctxs[q]->n;
+      cap = std::max(cap, thc_mps_capacity(n, D));
+      nmax = std::max(nmax, n);
+      for (thc_mps *o : {out_re[q], out_im[q]})
+        if (!o || o->n_sites != n) raise(THC_EINVAL, "bad output MPS");
+    }
+    // inputs are copied before any output is written, so outputs may alias them
+    for (int q = 0; q < n_inst; ++q) {
+      const int n = ctxs[q]->n;
+      load_part(ctxs[q], psi_re[q], state[q].re, n, cap, s);
+      load_part(ctxs[q], psi_im ? psi_im[q] : nullptr, state[q].im, n, cap, s);
+      if (state[q].re.zero && state[q].im.zero) raise(THC_EINVAL, "state has zero norm");
+    }
+    // one Krylov workspace, sized for the largest instance, used by each in turn
+    EvolveWork W;
+    W.cap = cap;
+    W.v.resize(K);
+    W.w.resize(K);
+    for (auto *vec : {&W.v, &W.w})
+      for (CState &c : *vec) {
+        part_init(c.re, nmax, cap);
+        part_init(c.im, nmax, cap);
+      }
+    thc_stats acc{};
+    for (int step = 0; step < n_steps; ++step)
+      for (int q = 0; q < n_inst; ++q) {
+        W.n = ctxs[q]->n;
+        for (auto *vec : {&W.v, &W.w})
+          for (CState &c : *vec) {
+            c.re.b.assign(W.n + 1, 1); c.re.off.assign(W.n, 0);
+            c.im.b.assign(W.n + 1, 1); c.im.off.assign(W.n, 0);
+          }
+        const int m = evolve_step(ctxs[q], oo[q], W, state[q], K, delta, acc, s);
+        if (krylov_dims) krylov_dims[q * n_steps + step] = m;
+      }
+    for (int q = 0; q < n_inst; ++q) {
+      const int n = ctxs[q]->n;
+      store_part(state[q].re, out_re[q], n, s);
+      store_part(state[q].im, out_im[q], n, s);
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    if (st) *st = acc;
+  });
 }
 
 }  // extern "C"

@@ -125,6 +125,10 @@ void launch_ritz(hipStream_t st, const double *Mm, const double *S, int m, int l
 // Coefficients of the a-th Ritz vector over v_0..v_{m-1} (device x, m).
 void launch_ritz_vector(hipStream_t st, const double *Mm, const double *S, int m, int ld, int a, double *x,
                         int *info);
+// Krylov time step: out[0..2m) = scale * (Re a, Im a) of exp(-i delta H~) e_0
+// from complex M, S given as real/imaginary parts (row stride ld); m <= 16.
+void launch_evolve_coeffs(hipStream_t st, const double *Mr, const double *Mi, const double *Sr, const double *Si,
+                          int m, int ld, double delta, double scale, double *out, int *info);
 
 // Energy gradient (see kernels.hip): closing dot products of the transition
 // one-body matrices, the Z-signed bra site, and the final contraction into

@@ -1395,6 +1395,98 @@ __global__ void k_ritz_vector(const double *__restrict__ Mm, const double *__res
   info[0] = 0;
 }
 
+// Krylov time step (Sec. 2.2): the coefficients a over the complex basis
+// v_0..v_{m-1} of exp(-i delta H~) v_0, H~ being the effective Hamiltonian
+// of eq. eff_H of H_sym = (M + M^H)/2 in a basis orthonormal in the metric S
+// (eq. reortho).  The complex m x m matrices arrive as real and imaginary
+// parts (row stride ld) and are embedded as the real symmetric 2m x 2m
+// matrices [[Re, -Im], [Im, Re]], under which a complex vector x + iy is
+// (x, y) and multiplication by i is J(x, y) = (-y, x); J commutes with both
+// embeddings.  With the generalised eigenpairs H_sym Y = S Y diag(lam),
+// Y^T S Y = I, taken over the eigen-directions of S above 1e-10 (eigenvectors
+// of S scaled by s^{-1/2}, then rotated by the eigenvectors of the projected
+// H_sym),
+//   a = Y cos(delta lam) Y^T S e_0 - J Y sin(delta lam) Y^T S e_0,
+// i.e. a_re = p_re + q_im, a_im = p_im - q_re for p = Y cos(.) c and
+// q = Y sin(.) c, c = Y^T S e_0.  out[0..m) = scale * a_re,
+// out[m..2m) = scale * a_im; info[0] = the number of kept real directions.
+// One thread; m <= RITZ_MAX / 2.
+__global__ void k_evolve_coeffs(const double *__restrict__ Mr, const double *__restrict__ Mi,
+                                const double *__restrict__ Sr, const double *__restrict__ Si, int m, int ld,
+                                double delta, double scale, double *__restrict__ out, int *__restrict__ info) {
+  constexpr int LD = RITZ_MAX;
+  __shared__ double SR[LD * LD], HR[LD * LD], U[LD * LD], T1[LD * LD], W[LD * LD], X[LD * LD];
+  __shared__ double c[LD], cs[LD], sn[LD];
+  if (threadIdx.x != 0) return;
+  const int m2 = 2 * m;
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) {
+      const double sr = 0.5 * (Sr[i * ld + j] + Sr[j * ld + i]), si = 0.5 * (Si[i * ld + j] - Si[j * ld + i]);
+      const double hr = 0.5 * (Mr[i * ld + j] + Mr[j * ld + i]), hi = 0.5 * (Mi[i * ld + j] - Mi[j * ld + i]);
+      SR[i * LD + j] = sr;
+      SR[i * LD + m + j] = -si;
+      SR[(m + i) * LD + j] = si;
+      SR[(m + i) * LD + m + j] = sr;
+      HR[i * LD + j] = hr;
+      HR[i * LD + m + j] = -hi;
+      HR[(m + i) * LD + j] = hi;
+      HR[(m + i) * LD + m + j] = hr;
+    }
+  // S = U diag(s) U^T; X = U_k s_k^{-1/2} over s_k > 1e-10
+  for (int i = 0; i < m2; ++i)
+    for (int j = 0; j < m2; ++j) T1[i * LD + j] = SR[i * LD + j];
+  jacobi_eig_vectors(T1, U, m2);
+  int r = 0;
+  for (int k = 0; k < m2; ++k) {
+    const double sk = T1[k * LD + k];
+    if (sk > 1e-10) {
+      const double f = 1.0 / sqrt(sk);
+      for (int i = 0; i < m2; ++i) X[i * LD + r] = U[i * LD + k] * f;
+      ++r;
+    }
+  }
+  // T1 = X^T H X (r x r), W = H X as work
+  for (int i = 0; i < m2; ++i)
+    for (int b = 0; b < r; ++b) {
+      double v = 0.0;
+      for (int k = 0; k < m2; ++k) v += HR[i * LD + k] * X[k * LD + b];
+      W[i * LD + b] = v;
+    }
+  for (int a = 0; a < r; ++a)
+    for (int b = 0; b < r; ++b) {
+      double v = 0.0;
+      for (int i = 0; i < m2; ++i) v += X[i * LD + a] * W[i * LD + b];
+      T1[a * LD + b] = v;
+    }
+  jacobi_eig_vectors(T1, W, r);
+  // Y = X W (into U), c = Y^T S e_0
+  for (int i = 0; i < m2; ++i)
+    for (int b = 0; b < r; ++b) {
+      double v = 0.0;
+      for (int a = 0; a < r; ++a) v += X[i * LD + a] * W[a * LD + b];
+      U[i * LD + b] = v;
+    }
+  for (int b = 0; b < r; ++b) {
+    double v = 0.0;
+    for (int i = 0; i < m2; ++i) v += U[i * LD + b] * SR[i * LD];
+    c[b] = v;
+    cs[b] = cos(delta * T1[b * LD + b]) * v;
+    sn[b] = sin(delta * T1[b * LD + b]) * v;
+  }
+  for (int i = 0; i < m; ++i) {
+    double pr = 0.0, pi = 0.0, qr = 0.0, qi = 0.0;
+    for (int b = 0; b < r; ++b) {
+      pr += U[i * LD + b] * cs[b];
+      pi += U[(m + i) * LD + b] * cs[b];
+      qr += U[i * LD + b] * sn[b];
+      qi += U[(m + i) * LD + b] * sn[b];
+    }
+    out[i] = scale * (pr + qi);
+    out[m + i] = scale * (pi - qr);
+  }
+  info[0] = r;
+}
+
 // ---------------------------------------------------------------------------
 // Symmetric eigen path of the SVD step (Gram matrix G = Y Y^T):
 //   sytrd      Householder tridiagonalisation G = Q_H T Q_H^T (lower part)
@@ -3106,6 +3198,11 @@ void launch_grad_final(hipStream_t st, const double *g, int n, int L, int N, con
 void launch_ritz_vector(hipStream_t st, const double *Mm, const double *S, int m, int ld, int a, double *x,
                         int *info) {
   hipLaunchKernelGGL(k_ritz_vector, dim3(1), dim3(64), 0, st, Mm, S, m, ld, a, x, info);
+}
+
+void launch_evolve_coeffs(hipStream_t st, const double *Mr, const double *Mi, const double *Sr, const double *Si,
+                          int m, int ld, double delta, double scale, double *out, int *info) {
+  hipLaunchKernelGGL(k_evolve_coeffs, dim3(1), dim3(64), 0, st, Mr, Mi, Sr, Si, m, ld, delta, scale, out, info);
 }
 
 }  // namespace thck

@@ -94,7 +94,7 @@ EXPORTS = [
     "thc_default_opts", "thc_mps_capacity", "thc_load_factors", "thc_destroy", "mps_apply_thc_H",
     "mps_sum_compress", "mps_overlap", "krylov_create", "krylov_destroy", "krylov_step",
     "krylov_get_vector", "krylov_get_matrices", "mps_compress", "mps_apply_layer", "thc_last_error",
-    "krylov_ritz_vector", "krylov_restart", "thc_energy_gradient", "mps_overlap_noalloc",
+    "krylov_ritz_vector", "krylov_restart", "thc_energy_gradient", "mps_overlap_noalloc", "krylov_evolve",
 ]
 
 _lib = None
@@ -133,12 +133,14 @@ def load_library(path: str = LIB_PATH):
     lib.krylov_restart.argtypes = [vp, C.c_int32, vp]
     lib.mps_overlap_noalloc.argtypes = [P(ThcMps), P(ThcMps), vp, vp]
     lib.thc_energy_gradient.argtypes = [vp, P(ThcMps), C.c_int32, P(C.c_double), P(C.c_double), P(C.c_double), vp]
+    lib.krylov_evolve.argtypes = [C.c_int32, P(vp), P(P(ThcMps)), P(P(ThcMps)), P(ThcOpts), C.c_int32, C.c_double,
+                                  C.c_int32, P(P(ThcMps)), P(P(ThcMps)), P(C.c_int32), P(ThcStats), vp]
     lib.thc_last_error.argtypes = []
     lib.thc_last_error.restype = C.c_char_p
     for name in ("thc_load_factors", "thc_destroy", "mps_apply_thc_H", "mps_sum_compress", "mps_overlap",
                  "krylov_create", "krylov_destroy", "krylov_step", "krylov_get_vector", "krylov_get_matrices",
                  "mps_compress", "mps_apply_layer", "krylov_ritz_vector", "krylov_restart",
-                 "thc_energy_gradient", "mps_overlap_noalloc"):
+                 "thc_energy_gradient", "mps_overlap_noalloc", "krylov_evolve"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -382,6 +384,45 @@ class Krylov:
             self.close()
         except Exception:
             pass
+
+
+def evolve(instances, K: int, delta: float, n_steps: int, stats: ThcStats | None = None):
+    """Krylov time evolution (krylov_evolve) of complex states held as (re, im)
+    pairs of DeviceMPS.  instances: list of (Context, re, im, D, opts kw dict)
+    with re or im None for a zero part.  Returns ([(re, im), ...] as
+    DeviceMPS, krylov basis sizes as an n_inst x n_steps array); a zero part
+    comes back as the bond-1 MPS of zeros."""
+    q = len(instances)
+    lib = load_library()
+    ctxs = (C.c_void_p * q)(*[inst[0].h for inst in instances])
+    keep = []
+
+    def ptr(m):
+        if m is None:
+            return None
+        d = m.desc()
+        keep.append(d)
+        return C.pointer(d)
+
+    re_in = (C.POINTER(ThcMps) * q)(*[ptr(inst[1]) for inst in instances])
+    im_in = (C.POINTER(ThcMps) * q)(*[ptr(inst[2]) for inst in instances])
+    opts = (ThcOpts * q)(*[make_opts(inst[3], **(inst[4] if len(inst) > 4 else {})) for inst in instances])
+    outs = []
+    for inst in instances:
+        ctx, re, im, D = inst[:4]
+        cap = capacity(ctx.n, D)
+        for m in (re, im):
+            if m is not None:
+                cap = max(cap, m.buf.numel())
+        outs.append((DeviceMPS(ctx.n, cap, ctx.device), DeviceMPS(ctx.n, cap, ctx.device)))
+    od = [(a.desc(), b.desc()) for a, b in outs]
+    re_out = (C.POINTER(ThcMps) * q)(*[C.pointer(a) for a, _ in od])
+    im_out = (C.POINTER(ThcMps) * q)(*[C.pointer(b) for _, b in od])
+    dims = (C.c_int32 * max(1, q * n_steps))()
+    _check(lib.krylov_evolve(q, ctxs, re_in, im_in, opts, int(K), float(delta), int(n_steps), re_out, im_out, dims,
+                             C.byref(stats) if stats is not None else None, _stream()))
+    res = [(a._written(da), b._written(db)) for (a, b), (da, db) in zip(outs, od)]
+    return res, np.array(dims[: q * n_steps], dtype=np.int32).reshape(q, n_steps)
 
 
 class ThcEnergy(torch.autograd.Function):
