@@ -60,14 +60,18 @@ def elapsed():
     return time.monotonic() - T_START
 
 
-KERNEL_FN = {"lq": "k_lq2", "sytrd": "k_sy2sb", "tri_eig": "k_tri_eig", "ormtr": "k_ormtr2", "gemm": "k_gemm_mfma",
+KERNEL_FN = {"lq": ("k_lq2", "k_lq_q"), "sytrd": "k_sy2sb", "tri_eig": "k_tri_eig", "ormtr": "k_ormtr2", "gemm": "k_gemm_mfma",
              "sb2st": "k_sb2st", "q2": "k_q2apply"}
 KERNEL_SOURCES = ("kernels.hip", "band.hip")
 
 
-def kernel_digest(fn: str):
-    """SHA-256 of a kernel's source text (from its signature line to its closing brace)."""
+def kernel_digest(fn):
+    """SHA-256 of a kernel's source text (from its signature line to its closing
+    brace); for a class of several kernels, of their texts joined in order."""
     import hashlib
+    if isinstance(fn, tuple):
+        parts = [kernel_digest(f) for f in fn]
+        return None if None in parts else hashlib.sha256("".join(parts).encode()).hexdigest()
     for name in KERNEL_SOURCES:
         src = open(os.path.join(ROOT, "paper_2409_12708_amd", "csrc", name)).read().splitlines()
         try:
@@ -85,7 +89,8 @@ def measured_traffic(kernel: str, workload: str, algorithmic_bytes_per_launch: f
     times this run's algorithmic bytes per launch; None when there are no
     counter runs or the kernel's source has changed since they were taken."""
     fn = KERNEL_FN.get(kernel)
-    path = os.path.join(ROOT, "profiles", f"traffic_{fn}_{workload}.json")
+    first = fn[0] if isinstance(fn, tuple) else fn
+    path = os.path.join(ROOT, "profiles", f"traffic_{first}_{workload}.json")
     if not fn or not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -94,7 +99,7 @@ def measured_traffic(kernel: str, workload: str, algorithmic_bytes_per_launch: f
     return int(rec["measured_over_algorithmic"] * algorithmic_bytes_per_launch)
 
 
-KERNEL_LABEL = {"lq": "k_lq2 (Householder LQ with Q, FP64)",
+KERNEL_LABEL = {"lq": "k_lq2 + k_lq_q (Householder LQ, then Q from its compact-WY blocks, FP64)",
                 "sytrd": "k_sy2sb (tridiagonalisation: band reduction, FP64 MFMA)",
                 "sb2st": "k_sb2st (tridiagonalisation: band chase, FP64)",
                 "q2": "k_q2apply (band-chase back-transformation, FP64)",

@@ -159,3 +159,25 @@ def test_evolve_rejects_bad_arguments(thck):
     with pytest.raises(thck.ThcError) as e:
         thck.evolve([(ctx, zero, None, 4)], K=4, delta=0.1, n_steps=1)
     assert e.value.status == -1
+
+
+def test_complex_start_and_degenerate_calls(thck):
+    # a start with both parts given (a genuinely complex state), K = 1 (a
+    # phase from <H>), and n_steps = 0 (the input comes back unchanged)
+    rng = np.random.default_rng(27)
+    t, chi, zeta = synth.thc_factors(rng, 3, 4)
+    re = _random_start(rng, 6, 8)
+    im = M.scale(_random_start(rng, 6, 8), 0.5)
+    ctx = thck.Context(t, chi, zeta)
+    dre, dim = thck.DeviceMPS.from_sites(re), thck.DeviceMPS.from_sites(im)
+    for K, steps in ((3, 2), (1, 1)):
+        (out,), dims = thck.evolve([(ctx, dre, dim, 8)], K=K, delta=0.07, n_steps=steps)
+        ref, rdims = EV.evolve((re, im), t, chi, zeta, 8, K, 0.07, steps)
+        err = _rel(_dense(out), EV.to_dense_complex(ref))
+        print("K", K, "dims", dims.tolist(), rdims, "err vs oracle", err)
+        assert dims[0].tolist() == rdims
+        assert err < 1e-12
+    (out,), dims = thck.evolve([(ctx, dre, dim, 8)], K=4, delta=0.07, n_steps=0)
+    assert dims.shape == (1, 0)
+    want = M.to_dense(re) + 1j * M.to_dense(im)
+    assert _rel(_dense(out), want) < 1e-15
