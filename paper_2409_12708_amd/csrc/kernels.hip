@@ -2077,16 +2077,37 @@ __device__ __forceinline__ double rcp_nr(double b) {
 }
 __device__ __forceinline__ double qdiv(double a, double b) { return a * rcp_nr(b); }
 
+// reciprocal estimate plus one Newton step for |b| >= 1e-300 (no clamp):
+// the pivots of the counts below are kept at |q| >= pivmin >= 1e-300
+__device__ __forceinline__ double rcp_nr_pivot(double b) {
+  const double r = __builtin_amdgcn_rcp(b);
+  return fma(r, fma(-b, r, 1.0), r);
+}
+
+// Sturm count: number of eigenvalues of the symmetric tridiagonal (d, e)
+// below x, e2 = e^2; pivots of magnitude below pivmin (>= 1e-300) are
+// replaced by -pivmin.  Four steps per round, their d and e2 read from LDS
+// before the dependent chain of the four.
 __device__ __forceinline__ int sturm_count(const double *d, const double *e2, int m, double x, double pivmin) {
   int cnt = 0;
   double q = d[0] - x;
   if (fabs(q) < pivmin) q = -pivmin;
   if (q < 0.0) ++cnt;
-  for (int k = 1; k < m; ++k) {
-    q = (d[k] - x) - qdiv(e2[k - 1], q);
+  auto step = [&](double dk, double ek) {
+    q = (dk - x) - ek * rcp_nr_pivot(q);
     if (fabs(q) < pivmin) q = -pivmin;
     if (q < 0.0) ++cnt;
+  };
+  int k = 1;
+  for (; k + 4 <= m; k += 4) {
+    const double d0 = d[k], d1 = d[k + 1], d2 = d[k + 2], d3 = d[k + 3];
+    const double f0 = e2[k - 1], f1 = e2[k], f2 = e2[k + 1], f3 = e2[k + 2];
+    step(d0, f0);
+    step(d1, f1);
+    step(d2, f2);
+    step(d3, f3);
   }
+  for (; k < m; ++k) step(d[k], e2[k - 1]);
   return cnt;
 }
 
@@ -2100,15 +2121,25 @@ __device__ __forceinline__ int sturm_newton(const double *d, const double *e2, i
   double q = d[0] - x, dq = -1.0, s = 0.0;
   if (fabs(q) < pivmin) q = -pivmin;
   if (q < 0.0) ++cnt;
-  for (int k = 1; k < m; ++k) {
-    const double r = rcp_nr(q);
-    const double t = e2[k - 1] * r;
+  auto step = [&](double dk, double ek) {
+    const double r = rcp_nr_pivot(q);
+    const double t = ek * r;
     s = fma(dq, r, s);
     dq = fma(t * r, dq, -1.0);
-    q = (d[k] - x) - t;
+    q = (dk - x) - t;
     if (fabs(q) < pivmin) q = -pivmin;
     if (q < 0.0) ++cnt;
+  };
+  int k = 1;
+  for (; k + 4 <= m; k += 4) {
+    const double d0 = d[k], d1 = d[k + 1], d2 = d[k + 2], d3 = d[k + 3];
+    const double f0 = e2[k - 1], f1 = e2[k], f2 = e2[k + 1], f3 = e2[k + 2];
+    step(d0, f0);
+    step(d1, f1);
+    step(d2, f2);
+    step(d3, f3);
   }
+  for (; k < m; ++k) step(d[k], e2[k - 1]);
   S = fma(dq, rcp_nr(q), s);
   return cnt;
 }
