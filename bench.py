@@ -344,6 +344,34 @@ def rel_distance(a_sites, b_sites):
     return float((max(aa + bb - 2.0 * ab, 0.0)) ** 0.5 / max(bb, 1e-300) ** 0.5)
 
 
+def evolve_run(args, thck, synth, np, torch):
+    """One Krylov time step (Sec. 2.2) of a batch of instances of uneven size
+    in one krylov_evolve call: the time-evolution configuration's structure
+    (instances of different L, N = 4L and D, Hartree-Fock single-excitation
+    starts, K = 12, delta = 0.05) at sizes one step of which takes seconds."""
+    rng = np.random.default_rng(7)
+    insts, draws = [], []
+    for q in range(args.evolve):
+        L = int(rng.integers(8, 13))
+        D = int(rng.choice([32, 64]))
+        t, chi, zeta = synth.thc_factors(rng, L, 4 * L)
+        n_elec = L if L % 2 == 0 else L - 1
+        psi = thck.DeviceMPS.from_sites(synth.occupation_mps_tensors(synth.single_excitation_occupation(L, n_elec)))
+        insts.append((thck.Context(t, chi, zeta), psi, None, D, {"prec": args.prec}))
+        draws.append({"L": L, "N": 4 * L, "D": D, "electrons": n_elec})
+    torch.cuda.synchronize()
+    st = thck.ThcStats()
+    t0 = time.perf_counter()
+    outs, dims = thck.evolve(insts, K=12, delta=0.05, n_steps=1, stats=st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    norms = [float(np.sqrt(max(inst[0].overlap(a, a) + inst[0].overlap(b, b), 0.0)))
+             for inst, (a, b) in zip(insts, outs)]
+    print(json.dumps({"evolve": True, "instances": draws, "K": 12, "delta": 0.05, "steps": 1,
+                      "krylov_dims": dims.tolist(), "seconds": wall, "compressions": int(st.n_compressions),
+                      "norms_after": norms, "contraction_precision": args.prec}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -359,6 +387,10 @@ def main():
                          "device copy of known size; prints the slice's algorithmic bytes per kernel class")
     ap.add_argument("--prec", default="bf16x3", choices=["f64", "f32", "bf16x3"],
                     help="contraction precision of the absorb products (factorisations stay FP64)")
+    ap.add_argument("--evolve", type=int, default=0, metavar="INSTANCES",
+                    help="instead of the Lanczos step: one Krylov time step (K = 12, delta = 0.05) of this many "
+                         "instances in one call, L drawn from 8..12, N = 4L, D from {32, 64}, each from a "
+                         "Hartree-Fock single excitation; prints the draws and the time")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -372,7 +404,7 @@ def main():
     import synth
 
     pooled = None
-    if not args.no_cpu_baseline and not args.profile_slice:
+    if not args.no_cpu_baseline and not args.profile_slice and not args.evolve:
         # the term-parallel CPU baseline spawns its workers, so it runs first
         w = synth.WORKLOADS[args.workload]
         _, chi_p, _, sites_p = synth.make_workload(args.workload)
@@ -405,6 +437,10 @@ def main():
     torch.cuda.synchronize()
     log(f"[bench] workload {args.workload}: L={L} N={N} D={D}; requested warmup {args.warmup}, steps "
         f"{args.steps}; budget {args.budget:.0f} s; {elapsed():.1f} s since start")
+
+    if args.evolve:
+        evolve_run(args, thck, synth, np, torch)
+        return
 
     if args.profile_slice:
         # a device copy of 64 MiB (read and written once) calibrates the counters
