@@ -305,10 +305,12 @@ def cpu_baseline_pool(chi, sites, D, L, N):
         return None
     n_layer = 2 * 2 * N + 2 * 4 * N * N + 2 * 2 * L
     n_add = 4 * N * N + 2 * L - 1
+    # bounded waits: a pool that cannot start its workers raises instead of hanging
     with mp.get_context("spawn").Pool(cores, initializer=_pool_init) as pool:
-        pool.map(_pool_init_probe, range(cores))  # workers started and imported before the clock
+        pool.map_async(_pool_init_probe, range(cores)).get(timeout=120)  # workers up before the clock
         t0 = time.perf_counter()
-        times = pool.map(_pool_job, [(sites, chi[:, i % chi.shape[1]], D) for i in range(cores)], chunksize=1)
+        times = pool.map_async(_pool_job, [(sites, chi[:, i % chi.shape[1]], D) for i in range(cores)],
+                               chunksize=1).get(timeout=300)
         wall = time.perf_counter() - t0
     t_layer = sum(a for a, _ in times) / len(times) / cores
     t_add = sum(b for _, b in times) / len(times) / cores
