@@ -263,8 +263,13 @@ def cpu_baseline(t, chi, zeta, sites, D, L, N, pooled=None):
 
 
 def _pool_init():
+    # one BLAS thread per worker process: the thread counts are read when
+    # numpy's BLAS loads, which happens after this in a spawned worker
+    for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "BLIS_NUM_THREADS"):
+        os.environ[v] = "1"
+    import numpy  # noqa: F401
     from threadpoolctl import threadpool_limits
-    threadpool_limits(1)  # one BLAS thread per worker process
+    threadpool_limits(1)
 
 
 def _pool_job(args):
@@ -307,10 +312,11 @@ def cpu_baseline_pool(chi, sites, D, L, N):
     n_add = 4 * N * N + 2 * L - 1
     # bounded waits: a pool that cannot start its workers raises instead of hanging
     with mp.get_context("spawn").Pool(cores, initializer=_pool_init) as pool:
-        pool.map_async(_pool_init_probe, range(cores)).get(timeout=120)  # workers up before the clock
+        pool.map_async(_pool_init_probe, range(cores)).get(timeout=60)  # workers up before the clock
+        log(f"[bench] {cores} oracle processes started; {elapsed():.0f} s since start")
         t0 = time.perf_counter()
         times = pool.map_async(_pool_job, [(sites, chi[:, i % chi.shape[1]], D) for i in range(cores)],
-                               chunksize=1).get(timeout=300)
+                               chunksize=1).get(timeout=150)
         wall = time.perf_counter() - t0
     t_layer = sum(a for a, _ in times) / len(times) / cores
     t_add = sum(b for _, b in times) / len(times) / cores
