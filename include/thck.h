@@ -342,6 +342,28 @@ thc_status krylov_evolve(int32_t n_inst, thc_ctx *const *ctxs, const thc_mps *co
                          int32_t n_steps, thc_mps *const *out_re, thc_mps *const *out_im, int32_t *krylov_dims,
                          thc_stats *st, void *hip_stream);
 
+/* Complex states as pairs of real MPS (the representation krylov_evolve
+ * uses): out <- compressed sum_i c_i |term_i> with complex c_i
+ * (coeffs[2i] = Re c_i, coeffs[2i+1] = Im c_i, host) and complex terms
+ * term_i = terms_re[i] + i terms_im[i] (device MPS; a NULL entry, or a NULL
+ * array, is a zero part).  The real part is one mps_sum_compress over the
+ * terms (Re c_i, re_i), (-Im c_i, im_i), the imaginary part one over
+ * (Re c_i, im_i), (Im c_i, re_i), i ascending, leaving out NULL parts and
+ * exactly zero coefficients; a part with no term left is written as the
+ * bond-1 MPS of zeros (canonical = 0).  out_re and out_im follow
+ * mps_sum_compress's rules (capacity, no aliasing of any input) and must be
+ * distinct.  Synchronises. */
+thc_status mps_sum_compress_complex(thc_ctx *ctx, int32_t k, const double *coeffs, const thc_mps *const *terms_re,
+                                    const thc_mps *const *terms_im, thc_mps *out_re, thc_mps *out_im,
+                                    const thc_opts *o, thc_stats *st, void *hip_stream);
+
+/* result[0] + i result[1] <- <a|b> for complex states given as pairs of
+ * real MPS (NULL = zero part): <a_re|b_re> + <a_im|b_im>
+ * + i (<a_re|b_im> - <a_im|b_re>), each by mps_overlap.  result is host.
+ * Synchronises. */
+thc_status mps_overlap_complex(thc_ctx *ctx, const thc_mps *a_re, const thc_mps *a_im, const thc_mps *b_re,
+                               const thc_mps *b_im, double *result, void *hip_stream);
+
 /* Compress one MPS to D (QR sweep then SVD truncation sweep, Fig. 3). */
 thc_status mps_compress(thc_ctx *ctx, const thc_mps *in, thc_mps *out, const thc_opts *o,
                         thc_stats *st, void *hip_stream);

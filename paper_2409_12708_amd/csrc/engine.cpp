@@ -2530,6 +2530,72 @@ thc_status krylov_evolve(int32_t n_inst, thc_ctx *const *ctxs, const thc_mps *co
   });
 }
 
+thc_status mps_sum_compress_complex(thc_ctx *ctx, int32_t k, const double *coeffs, const thc_mps *const *terms_re,
+                                    const thc_mps *const *terms_im, thc_mps *out_re, thc_mps *out_im,
+                                    const thc_opts *o, thc_stats *st, void *hip_stream) {
+  if (!ctx) return fail(THC_EINVAL, "ctx is NULL");
+  if (k < 1 || !coeffs || (!terms_re && !terms_im)) return fail(THC_EINVAL, "need k >= 1 terms");
+  if (!out_re || !out_im || out_re == out_im || out_re->data == out_im->data)
+    return fail(THC_EINVAL, "need two distinct outputs");
+  return run_guarded([&] {
+    const int n = ctx->n;
+    for (int i = 0; i < 2 * k; ++i)
+      if (!std::isfinite(coeffs[i])) raise(THC_ENONFINITE, "non-finite coefficient");
+    // the two term lists, in the order of krylov_evolve's combinations
+    std::vector<double> co[2];
+    std::vector<const thc_mps *> tm[2];
+    for (int i = 0; i < k; ++i) {
+      const double cr = coeffs[2 * i], ci = coeffs[2 * i + 1];
+      const thc_mps *xr = terms_re ? terms_re[i] : nullptr, *xi = terms_im ? terms_im[i] : nullptr;
+      for (const thc_mps *x : {xr, xi})
+        if (x) {
+          check_mps(x, n);
+          if (x->data == out_re->data || x->data == out_im->data) raise(THC_EINVAL, "output aliases an input");
+        }
+      const double c[2][2] = {{cr, -ci}, {cr, ci}};
+      const thc_mps *x[2][2] = {{xr, xi}, {xi, xr}};
+      for (int part = 0; part < 2; ++part)
+        for (int h = 0; h < 2; ++h)
+          if (x[part][h] && c[part][h] != 0.0) {
+            co[part].push_back(c[part][h]);
+            tm[part].push_back(x[part][h]);
+          }
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    thc_stats acc{};
+    for (int part = 0; part < 2; ++part) {
+      thc_mps *dst = part == 0 ? out_re : out_im;
+      if (co[part].empty()) {
+        RPart zero;
+        store_part(zero, dst, n, s);
+        continue;
+      }
+      thc_stats s1{};
+      check(mps_sum_compress(ctx, (int)co[part].size(), co[part].data(), tm[part].data(), dst, o, &s1, s));
+      add_stats(acc, s1);
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    if (st) *st = acc;
+  });
+}
+
+thc_status mps_overlap_complex(thc_ctx *ctx, const thc_mps *a_re, const thc_mps *a_im, const thc_mps *b_re,
+                               const thc_mps *b_im, double *result, void *hip_stream) {
+  if (!ctx || !result) return fail(THC_EINVAL, "NULL argument");
+  return run_guarded([&] {
+    auto ov = [&](const thc_mps *x, const thc_mps *y) {
+      if (!x || !y) return 0.0;
+      double r = 0.0;
+      check(mps_overlap(ctx, x, y, &r, hip_stream));
+      return r;
+    };
+    const double re = ov(a_re, b_re) + ov(a_im, b_im);
+    const double im = ov(a_re, b_im) - ov(a_im, b_re);
+    result[0] = re;
+    result[1] = im;
+  });
+}
+
 }  // extern "C"
 
 // ===========================================================================

@@ -95,6 +95,7 @@ EXPORTS = [
     "mps_sum_compress", "mps_overlap", "krylov_create", "krylov_destroy", "krylov_step",
     "krylov_get_vector", "krylov_get_matrices", "mps_compress", "mps_apply_layer", "thc_last_error",
     "krylov_ritz_vector", "krylov_restart", "thc_energy_gradient", "mps_overlap_noalloc", "krylov_evolve",
+    "mps_sum_compress_complex", "mps_overlap_complex",
 ]
 
 _lib = None
@@ -135,12 +136,16 @@ def load_library(path: str = LIB_PATH):
     lib.thc_energy_gradient.argtypes = [vp, P(ThcMps), C.c_int32, P(C.c_double), P(C.c_double), P(C.c_double), vp]
     lib.krylov_evolve.argtypes = [C.c_int32, P(vp), P(P(ThcMps)), P(P(ThcMps)), P(ThcOpts), C.c_int32, C.c_double,
                                   C.c_int32, P(P(ThcMps)), P(P(ThcMps)), P(C.c_int32), P(ThcStats), vp]
+    lib.mps_sum_compress_complex.argtypes = [vp, C.c_int32, P(C.c_double), P(P(ThcMps)), P(P(ThcMps)), P(ThcMps),
+                                             P(ThcMps), P(ThcOpts), P(ThcStats), vp]
+    lib.mps_overlap_complex.argtypes = [vp, P(ThcMps), P(ThcMps), P(ThcMps), P(ThcMps), P(C.c_double), vp]
     lib.thc_last_error.argtypes = []
     lib.thc_last_error.restype = C.c_char_p
     for name in ("thc_load_factors", "thc_destroy", "mps_apply_thc_H", "mps_sum_compress", "mps_overlap",
                  "krylov_create", "krylov_destroy", "krylov_step", "krylov_get_vector", "krylov_get_matrices",
                  "mps_compress", "mps_apply_layer", "krylov_ritz_vector", "krylov_restart",
-                 "thc_energy_gradient", "mps_overlap_noalloc", "krylov_evolve"):
+                 "thc_energy_gradient", "mps_overlap_noalloc", "krylov_evolve", "mps_sum_compress_complex",
+                 "mps_overlap_complex"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -313,6 +318,37 @@ class Context:
         _check(self.lib.thc_energy_gradient(self.h, C.byref(pd), p, C.byref(e), _dptr(dchi), _dptr(dzeta),
                                             _stream()))
         return float(e.value), dchi, dzeta
+
+    def sum_compress_complex(self, coeffs, terms, D: int, stats: ThcStats | None = None, **kw):
+        """Compressed sum_i c_i |t_i> for complex c_i and complex states given as
+        (re, im) pairs of DeviceMPS (None = zero part); returns an (re, im) pair."""
+        o = make_opts(D, **kw)
+        k = len(terms)
+        keep = []
+
+        def ptr(m):
+            if m is None:
+                return None
+            d = m.desc()
+            keep.append(d)
+            return C.pointer(d)
+
+        re_arr = (C.POINTER(ThcMps) * k)(*[ptr(t[0]) for t in terms])
+        im_arr = (C.POINTER(ThcMps) * k)(*[ptr(t[1]) for t in terms])
+        co = (C.c_double * (2 * k))(*[v for c in coeffs for v in (complex(c).real, complex(c).imag)])
+        out_re, out_im = self.new_mps(D), self.new_mps(D)
+        dr, di = out_re.desc(), out_im.desc()
+        _check(self.lib.mps_sum_compress_complex(self.h, k, co, re_arr, im_arr, C.byref(dr), C.byref(di), C.byref(o),
+                                                 C.byref(stats) if stats is not None else None, _stream()))
+        return out_re._written(dr), out_im._written(di)
+
+    def overlap_complex(self, a, b) -> complex:
+        """<a|b> of complex states given as (re, im) pairs of DeviceMPS (None = zero part)."""
+        r = (C.c_double * 2)()
+        descs = [None if m is None else m.desc() for m in (*a, *b)]
+        ptrs = [None if d is None else C.byref(d) for d in descs]
+        _check(self.lib.mps_overlap_complex(self.h, *ptrs, r, _stream()))
+        return complex(r[0], r[1])
 
     def overlap(self, a: DeviceMPS, b: DeviceMPS) -> float:
         r = C.c_double()

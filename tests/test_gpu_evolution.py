@@ -181,3 +181,29 @@ def test_complex_start_and_degenerate_calls(thck):
     assert dims.shape == (1, 0)
     want = M.to_dense(re) + 1j * M.to_dense(im)
     assert _rel(_dense(out), want) < 1e-15
+
+
+def test_complex_sum_compress_and_overlap_match_oracle(thck):
+    # the complex combination and overlap entry points on (re, im) pairs with
+    # absent parts, untruncated (D = 8 at L = 3) and truncated (D = 4)
+    rng = np.random.default_rng(28)
+    t, chi, zeta = synth.thc_factors(rng, 3, 4)
+    ctx = thck.Context(t, chi, zeta)
+    xs = [(_random_start(rng, 6, 8), _random_start(rng, 6, 8)), (_random_start(rng, 6, 8), None),
+          (None, _random_start(rng, 6, 8))]
+    coeffs = [0.3 - 0.7j, 1.1 + 0.2j, -0.4j]
+    dev = [tuple(None if p is None else thck.DeviceMPS.from_sites(p) for p in x) for x in xs]
+    for D, tol in ((8, 1e-12), (4, 1e-9)):
+        got = ctx.sum_compress_complex(coeffs, dev, D)
+        ref = EV.ccombine(coeffs, xs, D)
+        err = _rel(_dense(got), EV.to_dense_complex(ref))
+        print("D", D, "err vs oracle", err)
+        assert err < tol
+    for a, b in ((0, 2), (0, 1), (1, 2), (2, 0)):
+        got = ctx.overlap_complex(dev[a], dev[b])
+        want = EV.coverlap(xs[a], xs[b])
+        assert abs(got - want) < 1e-13, (a, b, got, want)
+    # a real combination of real states: the imaginary output is the zero MPS
+    re, im = ctx.sum_compress_complex([2.0], [dev[1]], 8)
+    assert im.bond_list() == [1] * 7 and not im.to_sites()[0].any()
+    assert _rel(M.to_dense(re.to_sites()), 2.0 * M.to_dense(xs[1][0])) < 1e-12
