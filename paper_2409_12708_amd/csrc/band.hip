@@ -29,6 +29,13 @@ constexpr int R_ROWS = 512 - 16; // rows of the panel arrays (m <= 512)
 constexpr int NT = 512;         // threads per workgroup
 constexpr int NW = NT / WAVE;   // waves per workgroup
 
+// 1/b from the hardware estimate and two Newton steps, for normal |b|
+__device__ __forceinline__ double rcp2(double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  r = fma(r, fma(-b, r, 1.0), r);
+  return fma(r, fma(-b, r, 1.0), r);
+}
+
 // Householder reflector H = I - tau v v^T, v[0] = 1, H x = beta e_0, from
 // alpha = x[0], amx = max |x[1:]|, s2 = |x[1:]|^2.  Returns false when the
 // squares are out of range and the caller must supply the scaled sum s3 of
@@ -43,8 +50,10 @@ __device__ __forceinline__ bool house_direct(double alpha, double amx, double s2
   }
   if (s2 > 1e-280 && s2 < 1e280 && fabs(alpha) < 1e140) {
     const double bs = -copysign(sqrt(alpha * alpha + s2), alpha);
-    tau = (bs - alpha) / bs;
-    sc = 1.0 / (alpha - bs);
+    // |bs| >= amx > 1e-290 and |alpha - bs| >= |bs|: reciprocal estimates
+    // refined by two Newton steps (a few ulps) instead of full divisions
+    tau = (bs - alpha) * rcp2(bs);
+    sc = rcp2(alpha - bs);
     beta = bs;
     return true;
   }

@@ -159,3 +159,40 @@ def test_compress_degenerate_spectrum(thck, flags):
     half = M.to_dense(ctx.compress(thck.DeviceMPS.from_sites(psi), D=32, flags=flags).to_sites())
     assert abs(np.dot(half, ref) - np.dot(half, half)) < 1e-12
     assert abs(np.dot(half, half) - 0.5) < 1e-12
+
+
+def test_zero_state_compresses_to_zero(thck):
+    # the zero MPS (every site zero, bonds as a random state's): compression
+    # and H application return the zero state, finite, with the oracle's
+    # bond-1 rule (k = max(1, ...) when s_1 = 0)
+    rng = np.random.default_rng(61)
+    n = 8
+    t, chi, zeta = synth.thc_factors(np.random.default_rng(1), n // 2, 3)
+    ctx = thck.Context(t, chi, zeta)
+    zero = [np.zeros_like(a) for a in synth.random_mps_tensors(rng, n, 8)]
+    dz = thck.DeviceMPS.from_sites(zero)
+    out = ctx.compress(dz, D=8)
+    ref = M.compress(zero, 8)
+    got = out.to_sites()
+    assert all(np.isfinite(a).all() for a in got)
+    assert not M.to_dense(got).any()
+    assert out.bond_list() == M.bonds(ref)
+    h = ctx.apply_H(dz, D=8)
+    assert not M.to_dense(h.to_sites()).any()
+
+
+def test_evolve_with_graphs_matches_eager(thck):
+    # the time step's compression batches replayed from captured HIP graphs
+    # give the eager results bit for bit (two steps: the second replays the
+    # graphs the first captured)
+    rng = np.random.default_rng(62)
+    t, chi, zeta = synth.thc_factors(rng, 3, 4)
+    psi = _norm_mps(rng, 6, 4)
+    ctx = thck.Context(t, chi, zeta)
+    res = []
+    for flags in (0, thck.FLAG_GRAPHS):
+        (out,), dims = thck.evolve([(ctx, thck.DeviceMPS.from_sites(psi), None, 4, {"flags": flags})], K=4,
+                                   delta=0.05, n_steps=2)
+        res.append([np.concatenate([a.reshape(-1) for a in p.to_sites()]) for p in out])
+    for a, b in zip(*res):
+        assert a.shape == b.shape and np.array_equal(a, b)
