@@ -1185,85 +1185,105 @@ __global__ void k_scale_range(double *__restrict__ p, int64_t count, double c) {
 }
 
 // ---------------------------------------------------------------------------
-// small dense symmetric eigensolver (cyclic Jacobi), one workgroup, m <= 64.
-// Computes the Ritz values of the Lanczos step:
-//   mode 0: eigenvalues of the tridiagonal (alpha, beta);
-//   mode 1: eigenvalues of C H_sym C^T with C S C^T = I (Cholesky of S), or
-//           of X^T H_sym X with X = U_k s_k^{-1/2} when an eigenvalue of S
-//           is at or below 1e-10 (canonical orthogonalisation keeping the
-//           s_k > 1e-10); the entries past the kept count are NaN.
+// Small dense symmetric eigensolvers (cyclic Jacobi) for the K x K problems
+// of the Krylov step, run by one wavefront: the rotations are taken in the
+// cyclic order, each by all lanes at once (lane k updates entry k of rows
+// p and q, then of columns p and q, then of the eigenvector columns), so
+// the results equal those of the serial loop; m <= RITZ_MAX.  Used for
+//   the Ritz values of the tridiagonal (alpha, beta);
+//   the Ritz values of C H_sym C^T with C S C^T = I (Cholesky of S), or of
+//   X^T H_sym X with X = U_k s_k^{-1/2} when an eigenvalue of S is at or
+//   below 1e-10 (canonical orthogonalisation keeping the s_k > 1e-10); the
+//   entries past the kept count are NaN;
+//   the coefficients of a Krylov time step.
+// Every wave-collective routine below is called by all 64 lanes of the
+// kernel's single wave; LDS written by one lane is read by others after
+// wave_sync().
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// sum over the lanes of the squares of A's entries (tot) and of its
+// off-diagonal entries (off); lane k takes row k
+__device__ __forceinline__ void jacobi_norms(const double *A, int m, int lda, double &off, double &tot) {
+  const int l = threadIdx.x;
+  double o = 0.0, t = 0.0;
+  if (l < m)
+    for (int j = 0; j < m; ++j) {
+      const double x = A[l * lda + j];
+      t += x * x;
+      if (j != l) o += x * x;
+    }
+  off = wave_sum(o);
+  tot = wave_sum(t);
+}
+
+// one rotation (p, q) of the cyclic sweep on A (and V when non-null)
+__device__ __forceinline__ void jacobi_rotate(double *A, int lda, double *V, int ldv, int m, int p, int q) {
+  const int l = threadIdx.x;
+  const double apq = A[p * lda + q];
+  if (apq == 0.0) return;  // uniform: every lane read the same entry
+  const double th = (A[q * lda + q] - A[p * lda + p]) / (2.0 * apq);
+  const double t = copysign(1.0, th) / (fabs(th) + sqrt(1.0 + th * th));
+  const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+  wave_sync();  // every lane has read the pivot entries
+  if (l < m) {
+    const double ap = A[p * lda + l], aq = A[q * lda + l];
+    A[p * lda + l] = c * ap - s * aq;
+    A[q * lda + l] = s * ap + c * aq;
+  }
+  wave_sync();
+  if (l < m) {
+    const double ap = A[l * lda + p], aq = A[l * lda + q];
+    A[l * lda + p] = c * ap - s * aq;
+    A[l * lda + q] = s * ap + c * aq;
+    if (V != nullptr) {
+      const double vp = V[l * ldv + p], vq = V[l * ldv + q];
+      V[l * ldv + p] = c * vp - s * vq;
+      V[l * ldv + q] = s * vp + c * vq;
+    }
+  }
+  wave_sync();
+}
+
+// eigenvalues of the m x m symmetric A (row stride lda), ascending, into w
 __device__ void jacobi_eig_small(double *A, int m, int lda, double *w) {
-  // serial cyclic Jacobi (m tiny), run by one thread
   for (int sweep = 0; sweep < 100; ++sweep) {
-    double off = 0.0, tot = 0.0;
-    for (int i = 0; i < m; ++i)
-      for (int j = 0; j < m; ++j) {
-        tot += A[i * lda + j] * A[i * lda + j];
-        if (i != j) off += A[i * lda + j] * A[i * lda + j];
-      }
+    double off, tot;
+    jacobi_norms(A, m, lda, off, tot);
     if (off <= 1e-30 * tot || off == 0.0) break;
     for (int p = 0; p < m; ++p)
-      for (int q = p + 1; q < m; ++q) {
-        const double apq = A[p * lda + q];
-        if (apq == 0.0) continue;
-        const double th = (A[q * lda + q] - A[p * lda + p]) / (2.0 * apq);
-        const double t = copysign(1.0, th) / (fabs(th) + sqrt(1.0 + th * th));
-        const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
-        for (int k = 0; k < m; ++k) {
-          const double ap = A[p * lda + k], aq = A[q * lda + k];
-          A[p * lda + k] = c * ap - s * aq;
-          A[q * lda + k] = s * ap + c * aq;
-        }
-        for (int k = 0; k < m; ++k) {
-          const double ap = A[k * lda + p], aq = A[k * lda + q];
-          A[k * lda + p] = c * ap - s * aq;
-          A[k * lda + q] = s * ap + c * aq;
-        }
-      }
+      for (int q = p + 1; q < m; ++q) jacobi_rotate(A, lda, nullptr, 0, m, p, q);
   }
-  for (int i = 0; i < m; ++i) w[i] = A[i * lda + i];
-  // ascending insertion sort
-  for (int i = 1; i < m; ++i) {
-    double v = w[i];
-    int j = i - 1;
-    while (j >= 0 && w[j] > v) { w[j + 1] = w[j]; --j; }
-    w[j + 1] = v;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < m; ++i) w[i] = A[i * lda + i];
+    for (int i = 1; i < m; ++i) {  // ascending insertion sort
+      double v = w[i];
+      int j = i - 1;
+      while (j >= 0 && w[j] > v) { w[j + 1] = w[j]; --j; }
+      w[j + 1] = v;
+    }
   }
+  wave_sync();
 }
 
 // Cyclic Jacobi with eigenvectors on the m x m symmetric A (row stride LD):
 // on return the eigenvalues are on the diagonal of A and V (m x m, columns)
-// holds the eigenvectors.  One thread; m <= RITZ_MAX.
+// holds the eigenvectors.
 __device__ void jacobi_eig_vectors(double *A, double *V, int m) {
   constexpr int LD = RITZ_MAX;
-  for (int i = 0; i < m; ++i)
-    for (int j = 0; j < m; ++j) V[i * LD + j] = (i == j) ? 1.0 : 0.0;
+  const int l = threadIdx.x;
+  if (l < m)
+    for (int j = 0; j < m; ++j) V[l * LD + j] = (l == j) ? 1.0 : 0.0;
+  wave_sync();
   for (int sweep = 0; sweep < 100; ++sweep) {
-    double off = 0.0, tot = 0.0;
-    for (int i = 0; i < m; ++i)
-      for (int j = 0; j < m; ++j) { tot += A[i * LD + j] * A[i * LD + j]; if (i != j) off += A[i * LD + j] * A[i * LD + j]; }
+    double off, tot;
+    jacobi_norms(A, m, LD, off, tot);
     if (off <= 1e-30 * tot || off == 0.0) break;
     for (int p = 0; p < m; ++p)
-      for (int q = p + 1; q < m; ++q) {
-        const double apq = A[p * LD + q];
-        if (apq == 0.0) continue;
-        const double th = (A[q * LD + q] - A[p * LD + p]) / (2.0 * apq);
-        const double t = copysign(1.0, th) / (fabs(th) + sqrt(1.0 + th * th));
-        const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
-        for (int k = 0; k < m; ++k) {
-          const double ap = A[p * LD + k], aq = A[q * LD + k];
-          A[p * LD + k] = c * ap - s * aq; A[q * LD + k] = s * ap + c * aq;
-        }
-        for (int k = 0; k < m; ++k) {
-          const double ap = A[k * LD + p], aq = A[k * LD + q];
-          A[k * LD + p] = c * ap - s * aq; A[k * LD + q] = s * ap + c * aq;
-        }
-        for (int k = 0; k < m; ++k) {
-          const double ap = V[k * LD + p], aq = V[k * LD + q];
-          V[k * LD + p] = c * ap - s * aq; V[k * LD + q] = s * ap + c * aq;
-        }
-      }
+      for (int q = p + 1; q < m; ++q) jacobi_rotate(A, LD, V, LD, m, p, q);
   }
 }
 
@@ -1271,69 +1291,84 @@ __device__ void jacobi_eig_vectors(double *A, double *V, int m) {
 // rows c_a of C (mk x m) with C S C^T = I.  S = U diag(s) U^T; when every
 // s exceeds 1e-10, C = L^{-1} with S = L L^T (Cholesky, mk = m); otherwise
 // canonical orthogonalisation keeps the eigenvectors with s > 1e-10:
-// c_k = u_k^T / sqrt(s_k).  Returns mk; ok = Cholesky branch.  Work arrays
-// T1, Sc, U of RITZ_MAX^2.  One thread.
+// c_k = u_k^T / sqrt(s_k).  Returns mk (on every lane); ok = Cholesky
+// branch.  Work arrays T1, Sc, U of RITZ_MAX^2.  Wave-collective: the
+// eigen-decomposition by all lanes, the rest by lane 0.
 __device__ int ritz_transform(const double *S, int ld, int m, double *C, double *T1, double *Sc, double *U, bool &ok) {
   constexpr int LD = RITZ_MAX;
-  for (int i = 0; i < m; ++i)
-    for (int j = 0; j < m; ++j) T1[i * LD + j] = S[i * ld + j];
+  __shared__ int s_mk, s_ok;
+  const int l = threadIdx.x;
+  if (l < m)
+    for (int j = 0; j < m; ++j) T1[l * LD + j] = S[l * ld + j];
+  wave_sync();
   jacobi_eig_vectors(T1, U, m);
-  ok = true;
-  for (int k = 0; k < m; ++k) ok = ok && (T1[k * LD + k] > 1e-10);
-  int mk = m;
-  if (ok) {
-    // Cholesky S = L L^T (in Sc, lower), then C = L^{-1} by forward
-    // substitution on the identity
-    for (int i = 0; i < m; ++i)
-      for (int j = 0; j < m; ++j) Sc[i * LD + j] = S[i * ld + j];
-    for (int j = 0; j < m; ++j) {
-      double d = Sc[j * LD + j];
-      for (int k = 0; k < j; ++k) d -= Sc[j * LD + k] * Sc[j * LD + k];
-      d = sqrt(d > 0.0 ? d : 0.0);
-      Sc[j * LD + j] = d;
-      for (int i = j + 1; i < m; ++i) {
-        double v = Sc[i * LD + j];
-        for (int k = 0; k < j; ++k) v -= Sc[i * LD + k] * Sc[j * LD + k];
-        Sc[i * LD + j] = v / d;
+  if (l == 0) {
+    bool okl = true;
+    for (int k = 0; k < m; ++k) okl = okl && (T1[k * LD + k] > 1e-10);
+    int mk = m;
+    if (okl) {
+      // Cholesky S = L L^T (in Sc, lower), then C = L^{-1} by forward
+      // substitution on the identity
+      for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) Sc[i * LD + j] = S[i * ld + j];
+      for (int j = 0; j < m; ++j) {
+        double d = Sc[j * LD + j];
+        for (int k = 0; k < j; ++k) d -= Sc[j * LD + k] * Sc[j * LD + k];
+        d = sqrt(d > 0.0 ? d : 0.0);
+        Sc[j * LD + j] = d;
+        for (int i = j + 1; i < m; ++i) {
+          double v = Sc[i * LD + j];
+          for (int k = 0; k < j; ++k) v -= Sc[i * LD + k] * Sc[j * LD + k];
+          Sc[i * LD + j] = v / d;
+        }
+      }
+      for (int col = 0; col < m; ++col)
+        for (int i = 0; i < m; ++i) {
+          double v = (i == col) ? 1.0 : 0.0;
+          for (int k = 0; k < i; ++k) v -= Sc[i * LD + k] * C[k * LD + col];
+          C[i * LD + col] = (i < col) ? 0.0 : v / Sc[i * LD + i];
+        }
+    } else {
+      mk = 0;
+      for (int k = 0; k < m; ++k) {
+        const double sk = T1[k * LD + k];
+        if (sk > 1e-10) {
+          for (int i = 0; i < m; ++i) C[mk * LD + i] = U[i * LD + k] / sqrt(sk);
+          ++mk;
+        }
       }
     }
-    for (int col = 0; col < m; ++col)
-      for (int i = 0; i < m; ++i) {
-        double v = (i == col) ? 1.0 : 0.0;
-        for (int k = 0; k < i; ++k) v -= Sc[i * LD + k] * C[k * LD + col];
-        C[i * LD + col] = (i < col) ? 0.0 : v / Sc[i * LD + i];
-      }
-  } else {
-    mk = 0;
-    for (int k = 0; k < m; ++k) {
-      const double sk = T1[k * LD + k];
-      if (sk > 1e-10) {
-        for (int i = 0; i < m; ++i) C[mk * LD + i] = U[i * LD + k] / sqrt(sk);
-        ++mk;
-      }
-    }
+    s_mk = mk;
+    s_ok = okl ? 1 : 0;
   }
-  return mk;
+  wave_sync();
+  ok = s_ok != 0;
+  return s_mk;
 }
 
 // T1 = C H_sym C^T (mk x mk) with H_sym = (M + M^T)/2; Sc is work.
+// Wave-collective: lane k computes row k of each product.
 __device__ void ritz_projected(const double *Mm, int ld, int m, int mk, const double *C, double *T1, double *H,
                                double *Sc) {
   constexpr int LD = RITZ_MAX;
-  for (int i = 0; i < m; ++i)
-    for (int j = 0; j < m; ++j) H[i * LD + j] = 0.5 * (Mm[i * ld + j] + Mm[j * ld + i]);
-  for (int i = 0; i < mk; ++i)
+  const int l = threadIdx.x;
+  if (l < m)
+    for (int j = 0; j < m; ++j) H[l * LD + j] = 0.5 * (Mm[l * ld + j] + Mm[j * ld + l]);
+  wave_sync();
+  if (l < mk)
     for (int j = 0; j < m; ++j) {
       double v = 0.0;
-      for (int k = 0; k < m; ++k) v += C[i * LD + k] * H[k * LD + j];
-      Sc[i * LD + j] = v;
+      for (int k = 0; k < m; ++k) v += C[l * LD + k] * H[k * LD + j];
+      Sc[l * LD + j] = v;
     }
-  for (int i = 0; i < mk; ++i)
+  wave_sync();
+  if (l < mk)
     for (int j = 0; j < mk; ++j) {
       double v = 0.0;
-      for (int k = 0; k < m; ++k) v += Sc[i * LD + k] * C[j * LD + k];
-      T1[i * LD + j] = v;
+      for (int k = 0; k < m; ++k) v += Sc[l * LD + k] * C[j * LD + k];
+      T1[l * LD + j] = v;
     }
+  wave_sync();
 }
 
 __global__ void k_ritz(const double *__restrict__ Mm, const double *__restrict__ S, int m, int ld,
@@ -1341,58 +1376,66 @@ __global__ void k_ritz(const double *__restrict__ Mm, const double *__restrict__
                        double *__restrict__ out_gen, double *__restrict__ out_tri, int *__restrict__ info) {
   constexpr int LD = RITZ_MAX;
   __shared__ double H[LD * LD], Sc[LD * LD], C[LD * LD], T1[LD * LD], U[LD * LD], wv[LD];
-  if (threadIdx.x != 0) return;
+  const int l = threadIdx.x;  // one wave
   // tridiagonal
-  for (int i = 0; i < m; ++i)
-    for (int j = 0; j < m; ++j) T1[i * LD + j] = 0.0;
-  for (int i = 0; i < m; ++i) T1[i * LD + i] = alpha[i];
-  for (int i = 0; i + 1 < m; ++i) { T1[i * LD + i + 1] = beta[i]; T1[(i + 1) * LD + i] = beta[i]; }
+  if (l < m)
+    for (int j = 0; j < m; ++j)
+      T1[l * LD + j] = (j == l) ? alpha[l] : ((j == l + 1) ? beta[l] : ((j + 1 == l) ? beta[j] : 0.0));
+  wave_sync();
   jacobi_eig_small(T1, m, LD, wv);
-  for (int i = 0; i < m; ++i) out_tri[i] = wv[i];
+  if (l < m) out_tri[l] = wv[l];
+  wave_sync();
   // generalised
   bool ok = true;
   const int mk = ritz_transform(S, ld, m, C, T1, Sc, U, ok);
   ritz_projected(Mm, ld, m, mk, C, T1, H, Sc);
   jacobi_eig_small(T1, mk, LD, wv);
   // values of dropped basis directions are reported as NaN
-  for (int i = 0; i < m; ++i) out_gen[i] = (i < mk) ? wv[i] : __longlong_as_double(0x7ff8000000000000LL);
-  info[0] = ok ? 0 : 1;
-  info[1] = mk;
+  if (l < m) out_gen[l] = (l < mk) ? wv[l] : __longlong_as_double(0x7ff8000000000000LL);
+  if (l == 0) {
+    info[0] = ok ? 0 : 1;
+    info[1] = mk;
+  }
 }
 
 // Coefficients x (m) of the a-th Ritz vector (ascending Ritz values) over
 // the basis v_0..v_{m-1}: x = C^T y_a with y_a the eigenvector of C H_sym C^T
 // (eq. reortho, eq. eff_H); the Ritz vector sum_i x_i v_i has unit norm in
-// the metric S.  info[0] = 0 on success, 1 when a >= the kept count.
+// the metric S.  info[0] = 0 on success, 1 when a >= the kept count.  One wave.
 __global__ void k_ritz_vector(const double *__restrict__ Mm, const double *__restrict__ S, int m, int ld, int a,
                               double *__restrict__ x, int *__restrict__ info) {
   constexpr int LD = RITZ_MAX;
   __shared__ double H[LD * LD], Sc[LD * LD], C[LD * LD], T1[LD * LD], U[LD * LD];
-  if (threadIdx.x != 0) return;
+  __shared__ int s_col;
+  const int l = threadIdx.x;
   bool ok = true;
   const int mk = ritz_transform(S, ld, m, C, T1, Sc, U, ok);
-  if (a < 0 || a >= mk) {
-    info[0] = 1;
+  if (a < 0 || a >= mk) {  // uniform
+    if (l == 0) info[0] = 1;
     return;
   }
   ritz_projected(Mm, ld, m, mk, C, T1, H, Sc);
   jacobi_eig_vectors(T1, U, mk);
-  // the a-th smallest eigenvalue's column
-  int order[LD];
-  for (int i = 0; i < mk; ++i) order[i] = i;
-  for (int i = 1; i < mk; ++i) {
-    const int v = order[i];
-    int j = i - 1;
-    while (j >= 0 && T1[order[j] * LD + order[j]] > T1[v * LD + v]) { order[j + 1] = order[j]; --j; }
-    order[j + 1] = v;
+  if (l == 0) {
+    // the a-th smallest eigenvalue's column
+    int order[LD];
+    for (int i = 0; i < mk; ++i) order[i] = i;
+    for (int i = 1; i < mk; ++i) {
+      const int v = order[i];
+      int j = i - 1;
+      while (j >= 0 && T1[order[j] * LD + order[j]] > T1[v * LD + v]) { order[j + 1] = order[j]; --j; }
+      order[j + 1] = v;
+    }
+    s_col = order[a];
   }
-  const int col = order[a];
-  for (int i = 0; i < m; ++i) {
+  wave_sync();
+  const int col = s_col;
+  if (l < m) {
     double v = 0.0;
-    for (int k = 0; k < mk; ++k) v += C[k * LD + i] * U[k * LD + col];
-    x[i] = v;
+    for (int k = 0; k < mk; ++k) v += C[k * LD + l] * U[k * LD + col];
+    x[l] = v;
   }
-  info[0] = 0;
+  if (l == 0) info[0] = 0;
 }
 
 // Krylov time step (Sec. 2.2): the coefficients a over the complex basis
@@ -1410,17 +1453,19 @@ __global__ void k_ritz_vector(const double *__restrict__ Mm, const double *__res
 // i.e. a_re = p_re + q_im, a_im = p_im - q_re for p = Y cos(.) c and
 // q = Y sin(.) c, c = Y^T S e_0.  out[0..m) = scale * a_re,
 // out[m..2m) = scale * a_im; info[0] = the number of kept real directions.
-// One thread; m <= RITZ_MAX / 2.
+// One wave; m <= RITZ_MAX / 2.
 __global__ void k_evolve_coeffs(const double *__restrict__ Mr, const double *__restrict__ Mi,
                                 const double *__restrict__ Sr, const double *__restrict__ Si, int m, int ld,
                                 double delta, double scale, double *__restrict__ out, int *__restrict__ info) {
   constexpr int LD = RITZ_MAX;
   __shared__ double SR[LD * LD], HR[LD * LD], U[LD * LD], T1[LD * LD], W[LD * LD], X[LD * LD];
-  __shared__ double c[LD], cs[LD], sn[LD];
-  if (threadIdx.x != 0) return;
+  __shared__ double cs[LD], sn[LD];
+  __shared__ int s_r;
+  const int l = threadIdx.x;  // one wave: lane l owns row l of the embeddings and products
   const int m2 = 2 * m;
-  for (int i = 0; i < m; ++i)
+  if (l < m)
     for (int j = 0; j < m; ++j) {
+      const int i = l;
       const double sr = 0.5 * (Sr[i * ld + j] + Sr[j * ld + i]), si = 0.5 * (Si[i * ld + j] - Si[j * ld + i]);
       const double hr = 0.5 * (Mr[i * ld + j] + Mr[j * ld + i]), hi = 0.5 * (Mi[i * ld + j] - Mi[j * ld + i]);
       SR[i * LD + j] = sr;
@@ -1432,59 +1477,69 @@ __global__ void k_evolve_coeffs(const double *__restrict__ Mr, const double *__r
       HR[(m + i) * LD + j] = hi;
       HR[(m + i) * LD + m + j] = hr;
     }
+  wave_sync();
   // S = U diag(s) U^T; X = U_k s_k^{-1/2} over s_k > 1e-10
-  for (int i = 0; i < m2; ++i)
-    for (int j = 0; j < m2; ++j) T1[i * LD + j] = SR[i * LD + j];
+  if (l < m2)
+    for (int j = 0; j < m2; ++j) T1[l * LD + j] = SR[l * LD + j];
+  wave_sync();
   jacobi_eig_vectors(T1, U, m2);
-  int r = 0;
-  for (int k = 0; k < m2; ++k) {
-    const double sk = T1[k * LD + k];
-    if (sk > 1e-10) {
-      const double f = 1.0 / sqrt(sk);
-      for (int i = 0; i < m2; ++i) X[i * LD + r] = U[i * LD + k] * f;
-      ++r;
+  if (l == 0) {
+    int r = 0;
+    for (int k = 0; k < m2; ++k) {
+      const double sk = T1[k * LD + k];
+      if (sk > 1e-10) {
+        const double f = 1.0 / sqrt(sk);
+        for (int i = 0; i < m2; ++i) X[i * LD + r] = U[i * LD + k] * f;
+        ++r;
+      }
     }
+    s_r = r;
   }
+  wave_sync();
+  const int r = s_r;
   // T1 = X^T H X (r x r), W = H X as work
-  for (int i = 0; i < m2; ++i)
+  if (l < m2)
     for (int b = 0; b < r; ++b) {
       double v = 0.0;
-      for (int k = 0; k < m2; ++k) v += HR[i * LD + k] * X[k * LD + b];
-      W[i * LD + b] = v;
+      for (int k = 0; k < m2; ++k) v += HR[l * LD + k] * X[k * LD + b];
+      W[l * LD + b] = v;
     }
-  for (int a = 0; a < r; ++a)
+  wave_sync();
+  if (l < r)
     for (int b = 0; b < r; ++b) {
       double v = 0.0;
-      for (int i = 0; i < m2; ++i) v += X[i * LD + a] * W[i * LD + b];
-      T1[a * LD + b] = v;
+      for (int i = 0; i < m2; ++i) v += X[i * LD + l] * W[i * LD + b];
+      T1[l * LD + b] = v;
     }
+  wave_sync();
   jacobi_eig_vectors(T1, W, r);
   // Y = X W (into U), c = Y^T S e_0
-  for (int i = 0; i < m2; ++i)
+  if (l < m2)
     for (int b = 0; b < r; ++b) {
       double v = 0.0;
-      for (int a = 0; a < r; ++a) v += X[i * LD + a] * W[a * LD + b];
-      U[i * LD + b] = v;
+      for (int a = 0; a < r; ++a) v += X[l * LD + a] * W[a * LD + b];
+      U[l * LD + b] = v;
     }
-  for (int b = 0; b < r; ++b) {
+  wave_sync();
+  if (l < r) {
     double v = 0.0;
-    for (int i = 0; i < m2; ++i) v += U[i * LD + b] * SR[i * LD];
-    c[b] = v;
-    cs[b] = cos(delta * T1[b * LD + b]) * v;
-    sn[b] = sin(delta * T1[b * LD + b]) * v;
+    for (int i = 0; i < m2; ++i) v += U[i * LD + l] * SR[i * LD];
+    cs[l] = cos(delta * T1[l * LD + l]) * v;
+    sn[l] = sin(delta * T1[l * LD + l]) * v;
   }
-  for (int i = 0; i < m; ++i) {
+  wave_sync();
+  if (l < m) {
     double pr = 0.0, pi = 0.0, qr = 0.0, qi = 0.0;
     for (int b = 0; b < r; ++b) {
-      pr += U[i * LD + b] * cs[b];
-      pi += U[(m + i) * LD + b] * cs[b];
-      qr += U[i * LD + b] * sn[b];
-      qi += U[(m + i) * LD + b] * sn[b];
+      pr += U[l * LD + b] * cs[b];
+      pi += U[(m + l) * LD + b] * cs[b];
+      qr += U[l * LD + b] * sn[b];
+      qi += U[(m + l) * LD + b] * sn[b];
     }
-    out[i] = scale * (pr + qi);
-    out[m + i] = scale * (pi - qr);
+    out[l] = scale * (pr + qi);
+    out[m + l] = scale * (pi - qr);
   }
-  info[0] = r;
+  if (l == 0) info[0] = r;
 }
 
 // ---------------------------------------------------------------------------
