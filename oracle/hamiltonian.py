@@ -90,12 +90,30 @@ def sum_tree(leaves, D, eps=M.CUTOFF, D_sum=None, D_final=None):
 
 
 def apply_H(psi, t, chi, zeta, D, mode="tree", eps=M.CUTOFF, include_T=True, include_V=True):
-    """Compressed H|psi> with H = T + V (eq. 1, THC form eq. sum_of_H)."""
+    """Compressed H|psi> with H = T + V (eq. 1, THC form eq. sum_of_H).
+
+    mode "sequential": Algorithm 1's running sum; "tree": the pairwise tree
+    of Fig. 11 over all terms; "two_trees": the terms split by nu into the V
+    terms with nu < N/2 and the rest (V terms with nu >= N/2, then T), each
+    part summed by its own tree and the two sums added (reading R13, the
+    order of the GPU's two-stream application)."""
     leaves = leaf_terms(psi, t, chi, zeta, D, eps, include_T, include_V)
     if mode == "sequential":
         return sum_sequential(leaves, D, eps)
     if mode == "tree":
         return sum_tree(list(leaves), D, eps)
+    if mode == "two_trees":
+        leaves = list(leaves)
+        N = chi.shape[1]
+        n_v = [0, 0]  # V terms with nu < N/2, with nu >= N/2
+        if include_V:
+            for nu, sp_, mu, s in v_terms(N):
+                if zeta[mu, nu] != 0.0:
+                    n_v[nu >= N // 2] += 1
+        n_first = n_v[0]
+        if n_v[0] == 0 or n_v[1] == 0:  # one part without V terms: the single tree
+            return sum_tree(leaves, D, eps)
+        return add_compress(sum_tree(leaves[:n_first], D, eps), sum_tree(leaves[n_first:], D, eps), D, eps)
     raise ValueError(mode)
 
 

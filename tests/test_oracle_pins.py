@@ -335,3 +335,21 @@ def test_mps_lanczos_matches_dense_lanczos():
     sec = np.where((nn == 2) & (sz == 0))[0]
     e0 = np.linalg.eigvalsh(H.toarray()[np.ix_(sec, sec)])[0]
     assert abs(ritz_mps[-1][0] - e0) < 1e-8
+
+
+def test_two_trees_order_is_exact_untruncated():
+    # the two-part summation order (reading R13) changes only the order of the
+    # compressed additions: untruncated it is eq. (1) applied densely
+    rng = np.random.default_rng(31)
+    L, N = 3, 4
+    t, chi, zeta = synth.thc_factors(rng, L, N)
+    psi = synth.random_mps_tensors(rng, 2 * L, 8)
+    got = M.to_dense(OH.apply_H(psi, t, chi, zeta, 8, mode="two_trees"))
+    want = F.apply_H_dense(M.to_dense(psi), t, TH.thc_v(chi, zeta))
+    assert np.linalg.norm(got - want) < 1e-12 * np.linalg.norm(want)
+    # with every V term in the first half the order falls back to the single tree
+    z1 = zeta.copy()
+    z1[:, N // 2:] = 0.0
+    a = M.to_dense(OH.apply_H(psi, t, chi, z1, 4, mode="two_trees"))
+    b = M.to_dense(OH.apply_H(psi, t, chi, z1, 4, mode="tree"))
+    assert np.array_equal(a, b)
