@@ -148,6 +148,20 @@ typedef struct {
  * eigenpairs to rounding. */
 #define THC_FLAG_SYTRD_ONE_STAGE 8ull
 
+/* opts.flags: mps_apply_thc_H (and the H applications of krylov_step and
+ * krylov_evolve) splits the V terms by nu into [0, N/2) and [N/2, N), the
+ * kinetic terms going with the second half, and sums each half by its own
+ * pairwise tree in its own engine, on its own stream and host thread (a
+ * second context on the same factors, created on first use and freed with
+ * the context), so that the kernels of the two halves overlap on the GPU;
+ * the two partial sums are then added and compressed.  Each half's batches
+ * take half of the workspace budget.  The summation order differs from the
+ * single tree (the same terms, a different tree), so truncated results
+ * differ from the single-stream ones within the truncation error;
+ * untruncated results agree to rounding.  Ignored when either half has no
+ * V term. */
+#define THC_FLAG_TWO_STREAMS 16ull
+
 enum {
   THC_K_LQ = 0,      /* Householder LQ with Q formation (canonical sweep and re-orthonormalisation) */
   THC_K_SYTRD = 1,   /* tridiagonalisation of the Gram matrix (two-stage route: its band reduction) */

@@ -5,8 +5,8 @@ include/thck.h); ``thck`` is the ctypes binding.
 """
 from .thck import (Context, DeviceMPS, Krylov, ThcEnergy, ThcError, ThcStats, capacity,  # noqa: F401
                    evolve, load_library, make_opts, thc_energy, EXPORTS, FLAG_GRAPHS, FLAG_SVD_JACOBI, FLAG_SYTRD_ONE_STAGE,
-                   FLAG_TIME_KERNELS)
+                   FLAG_TIME_KERNELS, FLAG_TWO_STREAMS)
 
 __all__ = ["Context", "DeviceMPS", "Krylov", "ThcEnergy", "ThcError", "ThcStats", "capacity", "evolve", "load_library",
            "make_opts", "thc_energy", "EXPORTS", "FLAG_GRAPHS", "FLAG_SVD_JACOBI", "FLAG_SYTRD_ONE_STAGE",
-           "FLAG_TIME_KERNELS"]
+           "FLAG_TIME_KERNELS", "FLAG_TWO_STREAMS"]

@@ -766,11 +766,12 @@ int launch_sy2sb(hipStream_t st, int nb, double *A, int64_t sA, int m, double *t
   if (nb <= 0 || m < BW + 2) return 0;  // already within the band
   constexpr int R = MMAX - BW;
   const size_t lds = (size_t)(2 * R * VLD + NW * 16 * VLD + 256 + 256 + 4 * NW + 1 + NW * BW + BW) * sizeof(double);
-  static bool attr = false;
-  if (!attr) {
+  // kernel attributes set once per process (thread-safe static initialisation)
+  static const bool attr = [&] {
     set_lds_band(k_sy2sb<MMAX>, lds);
-    attr = true;
-  }
+    return true;
+  }();
+  (void)attr;
   hipLaunchKernelGGL(k_sy2sb<MMAX>, dim3(nb), dim3(NT), lds, st, A, sA, m, tau, sv, only);
   return 0;
 }
@@ -782,11 +783,12 @@ int launch_sb2st(hipStream_t st, int nb, const double *A, int64_t sA, int m, dou
   if (nb <= 0) return 0;
   constexpr int CNT = 768, CLAG = 3;  // 12 waves, sweeps 3 phases apart
   const size_t lds = ((size_t)MMAX * 2 * BW + WAVE + 1 + (CNT / WAVE) * 2 * BW) * sizeof(double);  // band, pad, zero, scratch
-  static bool attr = false;
-  if (!attr) {
+  // kernel attributes set once per process (thread-safe static initialisation)
+  static const bool attr = [&] {
     set_lds_band(k_sb2st<MMAX, CNT, CLAG>, lds);
-    attr = true;
-  }
+    return true;
+  }();
+  (void)attr;
   hipLaunchKernelGGL((k_sb2st<MMAX, CNT, CLAG>), dim3(nb), dim3(CNT), lds, st, A, sA, m, d, e, sv, V2, sV2, only);
   return 0;
 }

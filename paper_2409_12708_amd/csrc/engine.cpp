@@ -21,6 +21,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/thck.h"
@@ -198,9 +199,14 @@ struct thc_ctx {
     batch_cap = nb;
   }
   hipStream_t cap_stream = nullptr;  // stream the graphs are captured on
+  // THC_FLAG_TWO_STREAMS: a second context on the same factors (its own
+  // workspace and slot pool) and its own stream, created on first use
+  std::unique_ptr<thc_ctx> twin;
+  hipStream_t twin_stream = nullptr;
   ~thc_ctx() {
     drop_graphs();
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (twin_stream) (void)hipStreamDestroy(twin_stream);
   }
 };
 
@@ -531,6 +537,8 @@ struct KernelTimer {
       cs.kbytes[r.cls] += r.bytes;
       cs.kn[r.cls] += 1;
       if (shape_stats_on()) {
+        static std::mutex mu;  // engines on several host threads share the table
+        std::lock_guard<std::mutex> lock(mu);
         ShapeStat &s = shape_stats()[r.key];
         s.calls += 1;
         s.ms += ms;
@@ -557,6 +565,8 @@ struct Engine {
   // precision of the contractions that absorb a factor into a site (the
   // factorisations, their projections, Gram matrices and overlaps are FP64)
   int cprec = GEMM_F64;
+  // share of the ~96 GiB batch-workspace budget (two engines at once each take half)
+  double budget_scale = 1.0;
   Engine(thc_ctx *c_, hipStream_t s_, const thc_opts &o_)
       : c(c_), st(s_), o(o_), timing((o_.flags & THC_FLAG_TIME_KERNELS) != 0),
         cprec(o_.prec == THC_PREC_F32 ? GEMM_F32 : (o_.prec == THC_PREC_BF16X3 ? GEMM_BF16X3 : GEMM_F64)) {}
@@ -1066,6 +1076,8 @@ struct Engine {
     }();
     if (!on) return;
     using clk = std::chrono::steady_clock;
+    static std::mutex mu;  // engines on several host threads report here
+    std::lock_guard<std::mutex> lock(mu);
     static clk::time_point t0 = clk::now(), last = t0;
     static int64_t done = 0;
     done += nb;
@@ -1122,8 +1134,8 @@ struct Engine {
     // keep the batch workspace under ~96 GiB; the big kernels run one
     // workgroup per job on one CU each, so a batch of 256 or 512 fills the
     // 256 CUs evenly, while e.g. 300 would leave a nearly empty second round
-    const double budget = 96.0 * (1ull << 30);
-    int b = (int)std::max(1.0, std::min(512.0, budget / (P.per_job * 8.0)));
+    const double budget = 96.0 * (1ull << 30) * budget_scale;
+    int b = (int)std::max(1.0, std::min(512.0 * budget_scale, budget / (P.per_job * 8.0)));
     if (b >= 256) b = b / 256 * 256;
     return b;
   }
@@ -1470,22 +1482,25 @@ Node compress_node(Engine &E, Node x, int D) {
 }
 
 // H|psi> (Algorithm 1 terms with prefix reuse + T terms, reduced by the tree)
-Node apply_H_nodes(Engine &E, const Node &psi, int D, int D_sum) {
+// The terms with nu in [nu0, nu1) (and the kinetic terms when with_T),
+// summed by one pairwise tree; the whole H is nu0 = 0, nu1 = N, with_T.
+Node apply_H_nodes(Engine &E, const Node &psi, int D, int D_sum, int nu0 = 0, int nu1 = -1, bool with_T = true) {
   thc_ctx *c = E.c;
   const int N = c->N, L = c->L;
+  if (nu1 < 0) nu1 = N;
   const thc_opts &o = E.o;
   Reducer red(E, D_sum);
   // leaves in order: V (nu, s', mu, s) then T (i, s)
-  // prefix states
+  // prefix states (prefix[2 (nu - nu0) + s'])
   std::vector<Node> prefix;
-  if (o.include_V) {
+  if (o.include_V && nu1 > nu0) {
     std::vector<JobSpec> s1;
-    for (int nu = 0; nu < N; ++nu)
+    for (int nu = nu0; nu < nu1; ++nu)
       for (int sp = 0; sp < 2; ++sp) s1.push_back(JobSpec{0, &psi, nullptr, c->coef_ptr(2 * nu + sp), 0, 1.0});
     std::vector<Node> a1 = run_jobs(E, s1, D);
     std::vector<JobSpec> s2;
     for (size_t i = 0; i < a1.size(); ++i) {
-      int nu = (int)i / 2, sp = (int)i % 2;
+      int nu = nu0 + (int)i / 2, sp = (int)i % 2;
       s2.push_back(JobSpec{0, &a1[i], nullptr, c->coef_ptr(2 * nu + sp), 1, 1.0});
     }
     prefix = run_jobs(E, s2, D);
@@ -1498,16 +1513,16 @@ Node apply_H_nodes(Engine &E, const Node &psi, int D, int D_sum) {
   };
   std::vector<Leaf> leaves;
   if (o.include_V) {
-    for (int nu = 0; nu < N; ++nu)
+    for (int nu = nu0; nu < nu1; ++nu)
       for (int sp = 0; sp < 2; ++sp)
         for (int mu = 0; mu < N; ++mu)
           for (int s = 0; s < 2; ++s) {
             double z = 0.5 * c->zeta[(size_t)mu * N + nu];
             if (z == 0.0) continue;
-            leaves.push_back(Leaf{&prefix[2 * nu + sp], c->coef_ptr(2 * mu + s), z});
+            leaves.push_back(Leaf{&prefix[2 * (nu - nu0) + sp], c->coef_ptr(2 * mu + s), z});
           }
   }
-  if (o.include_T) {
+  if (o.include_T && with_T) {
     for (int i = 0; i < L; ++i) {
       if (c->lam[i] == 0.0) continue;
       for (int s = 0; s < 2; ++s) leaves.push_back(Leaf{&psi, c->coef_ptr(2 * N + 2 * i + s), c->lam[i]});
@@ -1671,6 +1686,101 @@ thc_status thc_destroy(thc_ctx *ctx) {
   return THC_OK;
 }
 
+namespace {
+
+// both halves of the nu split hold at least one V term (zeta not all zero there)
+bool two_halves_have_terms(const thc_ctx *c) {
+  const int N = c->N, N0 = N / 2;
+  bool a = false, b = false;
+  for (int nu = 0; nu < N; ++nu)
+    for (int mu = 0; mu < N; ++mu)
+      if (c->zeta[(size_t)mu * N + nu] != 0.0) (nu < N0 ? a : b) = true;
+  return a && b;
+}
+
+void add_call_stats(CallStats &a, const CallStats &b) {
+  a.disc_max = std::max(a.disc_max, b.disc_max);
+  a.max_bond = std::max(a.max_bond, b.max_bond);
+  a.sweeps_max = std::max(a.sweeps_max, b.sweeps_max);
+  a.nonconv += b.nonconv;
+  a.fallbacks += b.fallbacks;
+  a.graph_captures += b.graph_captures;
+  a.graph_replays += b.graph_replays;
+  a.compressions += b.compressions;
+  a.launches += b.launches;
+  a.flops += b.flops;
+  for (int q = 0; q < THC_NK; ++q) {
+    a.kms[q] += b.kms[q];
+    a.kflops[q] += b.kflops[q];
+    a.kbytes[q] += b.kbytes[q];
+    a.kn[q] += b.kn[q];
+  }
+}
+
+// the second context of THC_FLAG_TWO_STREAMS: same factors, own workspace,
+// own non-blocking stream (default priority)
+thc_ctx *ensure_twin(thc_ctx *c, hipStream_t st) {
+  if (c->twin) return c->twin.get();
+  thc_ctx *tw = nullptr;
+  thc_status r = thc_load_factors(&tw, c->L, c->N, c->t.data(), c->chi.data(), c->zeta.data(), 0, st);
+  if (r != THC_OK) raise(r, thc_last_error());
+  c->twin.reset(tw);
+  HIPCHK(hipStreamCreateWithFlags(&c->twin_stream, hipStreamNonBlocking));
+  return tw;
+}
+
+// H|psi> with the V terms split by nu into [0, N/2) and [N/2, N) (the
+// kinetic terms with the second half), each half summed by its own tree in
+// its own engine, context and stream, the second on a host thread of its
+// own, so that the kernels of the two halves overlap on the GPU; the two
+// roots are then added and compressed.  Returns the root (context c).
+Node apply_H_two_streams(thc_ctx *c, hipStream_t s, const thc_opts &oo, const Node &in, int D, CallStats &cs) {
+  thc_ctx *tw = ensure_twin(c, s);
+  hipStream_t s1 = c->twin_stream;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  // the second stream starts after the caller's stream has produced psi
+  hipEvent_t ev;
+  HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(ev, s));
+  HIPCHK(hipStreamWaitEvent(s1, ev, 0));
+  HIPCHK(hipEventDestroy(ev));
+  const int N0 = c->N / 2;
+  Engine E0(c, s, oo), E1(tw, s1, oo);
+  E0.budget_scale = E1.budget_scale = 0.5;
+  c->jobs_host_used = 0;
+  tw->jobs_host_used = 0;
+  Node r0, r1;
+  thc_status st1 = THC_OK;
+  std::string msg1;
+  std::thread worker([&] {
+    (void)hipSetDevice(dev);
+    st1 = run_guarded([&] {
+      r1 = apply_H_nodes(E1, in, D, oo.D_sum, N0, c->N, true);
+      HIPCHK(hipStreamSynchronize(s1));
+    });
+    if (st1 != THC_OK) msg1 = thc_last_error();
+  });
+  thc_status st0 = run_guarded([&] { r0 = apply_H_nodes(E0, in, D, oo.D_sum, 0, N0, false); });
+  std::string msg0 = st0 != THC_OK ? std::string(thc_last_error()) : std::string();
+  worker.join();
+  if (st0 != THC_OK || st1 != THC_OK) {
+    if (st0 == THC_OK) release(c, r0);
+    if (st1 == THC_OK) release(tw, r1);
+    raise(st0 != THC_OK ? st0 : st1, st0 != THC_OK ? msg0 : msg1);
+  }
+  std::vector<JobSpec> sp{JobSpec{1, &r0, &r1, nullptr, 0, 1.0}};
+  Node root = run_jobs(E0, sp, oo.D_sum)[0];
+  HIPCHK(hipStreamSynchronize(s));
+  release(c, r0);
+  release(tw, r1);
+  cs = E0.cs;
+  add_call_stats(cs, E1.cs);
+  return root;
+}
+
+}  // namespace
+
 thc_status mps_apply_thc_H(thc_ctx *ctx, const thc_mps *psi, thc_mps *out, const thc_opts *o, thc_stats *st,
                            void *hip_stream) {
   if (!ctx) return fail(THC_EINVAL, "ctx is NULL");
@@ -1683,6 +1793,19 @@ thc_status mps_apply_thc_H(thc_ctx *ctx, const thc_mps *psi, thc_mps *out, const
     if (out->data == psi->data) raise(THC_EINVAL, "psi and out alias");
     if (out->capacity < thc_mps_capacity(ctx->n, D)) raise(THC_ECAPACITY, "output capacity below thc_mps_capacity");
     hipStream_t s = (hipStream_t)hip_stream;
+    if ((oo.flags & THC_FLAG_TWO_STREAMS) && oo.include_V && ctx->N >= 2 && two_halves_have_terms(ctx)) {
+      CallStats cs;
+      Node root = apply_H_two_streams(ctx, s, oo, caller_node(psi), D, cs);
+      Engine E(ctx, s, oo);
+      ctx->jobs_host_used = 0;
+      if (oo.D_sum != D) root = compress_node(E, root, D);
+      emit(E, root, out);
+      HIPCHK(hipStreamSynchronize(s));
+      release(ctx, root);
+      add_call_stats(cs, E.cs);
+      fill_stats(st, cs);
+      return;
+    }
     Engine E(ctx, s, oo);
     ctx->jobs_host_used = 0;
     Node in = caller_node(psi);

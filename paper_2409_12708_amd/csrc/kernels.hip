@@ -18,6 +18,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <stdint.h>
 #include <type_traits>
@@ -2927,6 +2928,10 @@ static std::map<TuneKey, TuneRec> &tune_table() {
   static auto *t = new std::map<TuneKey, TuneRec>();  // read by the exit report
   return *t;
 }
+static std::mutex &tune_mutex() {
+  static std::mutex mu;
+  return mu;
+}
 static bool autotune_on() {
   static const bool on = [] {
     const char *e = getenv("THCK_AUTOTUNE");
@@ -2943,6 +2948,9 @@ static void gemm_mode(hipStream_t st, int nb, const double *A, int64_t sA, int l
   while (nbc * 2 <= nb) nbc *= 2;
   const TuneKey key{MODE, PREC, M, N, K, nbc};
   auto &tab = tune_table();
+  // callers on several host threads (the two-stream H application) share
+  // the table: lookups and the tuning of a new class hold its lock
+  std::lock_guard<std::mutex> lock(tune_mutex());
   auto it = tab.find(key);
   int tile = (PREC != GEMM_F64 && M > 64 && N > 64) ? 128 : 64;
   if (it != tab.end()) {
@@ -3041,12 +3049,13 @@ static void lq_variant(hipStream_t st, int nb, double *X, int64_t sX, int m, int
   constexpr int NWV = 8;
   constexpr size_t lds = (16 * (NMAX + 1) + 256 + 256 + (NWV + 1) * 256 + 256 + 16 + 256) * sizeof(double);
   constexpr size_t lds_q = (16 * (NMAX + 1) + NWV * 256 + 3 * 256) * sizeof(double);
-  static bool attr = false;
-  if (!attr) {
+  // kernel attributes set once per process (thread-safe static initialisation)
+  static const bool attr = [&] {
     set_lds(k_lq2<NMAX, TR>, lds);
     set_lds(k_lq_q<NMAX, TR>, lds_q);
-    attr = true;
-  }
+    return true;
+  }();
+  (void)attr;
   hipLaunchKernelGGL((k_lq2<NMAX, TR>), dim3(nb), dim3(512), lds, st, X, sX, m, n, L, sL, Tw, sT, ldl, only);
   const int k = m < n ? m : n, nslab = (k + 15) / 16;
   if (nslab > 0)
@@ -3076,12 +3085,13 @@ int launch_jacobi(hipStream_t st, int nb, double *Y, int64_t sY, int m, int n, d
   if (n <= 512) {
     constexpr int BS = 16, NMAX = 512;
     size_t lds = (2 * (2 * BS) * (2 * BS) + 2 * BS + 8 + 2 * BS * NMAX) * sizeof(double);
-    static bool attr = false;
-    if (!attr) {
+    // kernel attributes set once per process (thread-safe static initialisation)
+    static const bool attr = [&] {
       (void)hipFuncSetAttribute((const void *)k_jacobi_rows<BS, NMAX>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds);
-      attr = true;
-    }
+      return true;
+    }();
+    (void)attr;
     hipLaunchKernelGGL((k_jacobi_rows<BS, NMAX>), dim3(nb), dim3(256), lds, st, Y, sY, m, n, s, ss, sweeps,
                        max_sweeps, only);
     return 0;
@@ -3089,12 +3099,13 @@ int launch_jacobi(hipStream_t st, int nb, double *Y, int64_t sY, int m, int n, d
   if (n <= 1024) {
     constexpr int BS = 8, NMAX = 1024;
     size_t lds = (2 * (2 * BS) * (2 * BS) + 2 * BS + 8 + 2 * BS * NMAX) * sizeof(double);
-    static bool attr = false;
-    if (!attr) {
+    // kernel attributes set once per process (thread-safe static initialisation)
+    static const bool attr = [&] {
       (void)hipFuncSetAttribute((const void *)k_jacobi_rows<BS, NMAX>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds);
-      attr = true;
-    }
+      return true;
+    }();
+    (void)attr;
     hipLaunchKernelGGL((k_jacobi_rows<BS, NMAX>), dim3(nb), dim3(256), lds, st, Y, sY, m, n, s, ss, sweeps,
                        max_sweeps, only);
     return 0;
@@ -3198,8 +3209,8 @@ int launch_sytrd(hipStream_t st, int nb, double *A, int64_t sA, int m, double *d
   // V, W (NB x MMAX each), x, kept row, 4 group row sums, NW column partials,
   // trailing diagonal (MMAX each), reductions
   const size_t lds = (2 * NB * MMAX + 2 * MMAX + 4 * MMAX + NW * MMAX + MMAX + 2 * NW + 2 * NB + NW) * sizeof(double);
-  static bool attr = false;
-  if (!attr) { set_lds(k_sytrd<MMAX>, lds); attr = true; }
+  static const bool attr = [&] { set_lds(k_sytrd<MMAX>, lds); return true; }();  // once per process, thread-safe
+  (void)attr;
   hipLaunchKernelGGL(k_sytrd<MMAX>, dim3(nb), dim3(512), lds, st, A, sA, m, d, e, tau, sv, only);
   return 0;
 }
@@ -3228,8 +3239,8 @@ int launch_ormtr(hipStream_t st, int nb, const double *A, int64_t sA, int m, con
   if (nblk > 0)
     hipLaunchKernelGGL(k_ormtr_tfac, dim3(nblk, nb), dim3(256), 0, st, A, sA, m, tau, sv, Tf, sTf, only, off);
   const size_t lds = (16 * 516 + 8 * 16 * 64 + 2 * 16 * 64 + 256) * sizeof(double);
-  static bool attr = false;
-  if (!attr) { set_lds(k_ormtr2, lds); attr = true; }
+  static const bool attr = [&] { set_lds(k_ormtr2, lds); return true; }();  // once per process, thread-safe
+  (void)attr;
   hipLaunchKernelGGL(k_ormtr2, dim3(nb * nslab), dim3(512), lds, st, A, sA, m, Tf, sTf, Z, sZ, kk, Ut, sU, nslab,
                      zout ? 1 : 0, only, off);
   return 0;

@@ -89,6 +89,7 @@ FLAG_SVD_JACOBI = 1      # one-sided Jacobi SVD in the truncation step
 FLAG_TIME_KERNELS = 2    # per-kernel-class device times / flops in ThcStats.kernels()
 FLAG_GRAPHS = 4          # compression batches captured into HIP graphs and replayed
 FLAG_SYTRD_ONE_STAGE = 8  # one-stage tridiagonalisation in the SVD step (default: two stages)
+FLAG_TWO_STREAMS = 16    # H applied as two halves (split by nu) on two streams, then added
 
 EXPORTS = [
     "thc_default_opts", "thc_mps_capacity", "thc_load_factors", "thc_destroy", "mps_apply_thc_H",
