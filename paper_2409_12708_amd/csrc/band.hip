@@ -492,15 +492,15 @@ __device__ __forceinline__ double row_max16(double v) {
 // row 1 the rows of the two-sided block (lane = row), row 2 the rows below
 // it for the right application (lane = row); row 3 only pads.  Every lane
 // loads its 16 entries (and lanes of rows 0 and 1 the entry x of the column
-// being annihilated) at once; masked entries read a slot that holds zero and
-// write to a per-lane pad after the band.  v and w reach every lane through
+// being annihilated) at once; lanes without work read a slot that holds zero
+// and write zero back to it.  v and w reach every lane through
 // the wave's 32-double LDS scratch (uniform-address reads).  Band entry
 // (i, c), i >= c, sits at S[c CW + i - c]: lanes along a row step by
 // CW - 1 = 31 doubles, lanes along a column by 1, both free of bank
 // conflicts.
 template <int CW>
-__device__ __forceinline__ void chase_step(double *S, int m, int j, int k, int NS, double *V2, int lane, int zslot,
-                                           int padbase, double *wsc) {
+__device__ __forceinline__ void chase_step(double *S, int m, int j, int k, int NS, double *V2, int lane, int qmax,
+                                           int zpad, int padbase, double *wsc) {
   constexpr int CS = CW - 1;  // band entry (i, c) at S[CS c + i]
   const int r0 = j + 1 + k * BW;
   const int r1 = min(r0 + BW - 1, m - 1);
@@ -525,22 +525,35 @@ __device__ __forceinline__ void chase_step(double *S, int m, int j, int k, int N
     a1 = CS;
     lok = part == 2 && li < nr;
   }
-  const int b0 = (part == 1) ? CW * r0 + CS * li : a0, b1 = (part == 1) ? 1 : a1;
-  // ad[q]: where entry q is written back (the pad where it is masked or, in
-  // the two-sided block, above the diagonal)
-  const int pad = padbase + lane, nmask = lok ? n : 0;
-  const int wlim = (part == 1) ? min(nmask, li + 1) : nmask;
+  int b0 = (part == 1) ? CW * r0 + CS * li : a0, b1 = (part == 1) ? 1 : a1;
+  // Masks are per lane, not per entry: a lane without work reads its zero
+  // slot for every q and writes back the zero its update leaves there (its
+  // a, v and w are zero; the slots are per lane, so that these writes do
+  // not collide).  Slots are shared by the waves, which all write zero.  Entries q >= n of a working lane (the last step
+  // of a sweep, r1 = m - 1) are rows >= m: band slots of columns < m that
+  // hold zero and get zero written back (v_q = w_q = 0).  In the two-sided
+  // block the entries above the diagonal (q > li) are read from the mirror
+  // and written to the lane's pad, their owner writing the lower copy; the
+  // other rows write all q (qmax = 15).
+  if (!lok) {
+    a0 = b0 = zpad + lane;
+    a1 = b1 = 0;
+  }
+  // (byte offsets, stepped from entry to entry: a1 up to qmax, b1 after it)
+  const int sa = 8 * a1, sb = 8 * b1, pado = 8 * (padbase + lane);
+  char *Sb = reinterpret_cast<char *>(S);
+  int off = 8 * a0;
   int ad[BW];
   double a[BW];
 #pragma unroll
   for (int q = 0; q < BW; ++q) {
-    const int adr = (q <= li) ? a0 + a1 * q : b0 + b1 * q;
-    a[q] = S[q < nmask ? adr : zslot];
-    ad[q] = q < wlim ? adr : pad;
+    if (q > 0) off += (q <= qmax) ? sa : sb;
+    a[q] = *reinterpret_cast<const double *>(Sb + off);
+    ad[q] = (q <= qmax) ? off : pado;
   }
   const bool xin = part <= 1 && li < n;
   const int xad = CS * col + r0 + li;  // (r0 + li, col)
-  const double xl = S[xin ? xad : zslot];
+  const double xl = S[xin ? xad : zpad + lane];
   // (a) reflector of column col over rows r0..r1 (row 0 holds x_i in lane i)
   const double xb = (part == 0 && li >= 1) ? xl : 0.0;
   const double amx = read_lane(row_max16(fabs(xb)), 15);
@@ -583,8 +596,11 @@ __device__ __forceinline__ void chase_step(double *S, int m, int j, int k, int N
   __builtin_amdgcn_wave_barrier();
   const double al = (part == 1) ? vi : 0.0;
   const double be = (part == 1) ? w : p;
+  double ws[BW];
 #pragma unroll
-  for (int q = 0; q < BW; ++q) S[ad[q]] = a[q] - (al * wsc[BW + q] + be * vs[q]);
+  for (int q = 0; q < BW; ++q) ws[q] = wsc[BW + q];  // all read before the band stores (same LDS array)
+#pragma unroll
+  for (int q = 0; q < BW; ++q) *reinterpret_cast<double *>(Sb + ad[q]) = fma(-be, vs[q], fma(-al, ws[q], a[q]));
 }
 }  // namespace
 
@@ -602,10 +618,11 @@ __global__ __launch_bounds__(CNT) void k_sb2st(const double *__restrict__ Ab, in
   constexpr int CW = 2 * BW;     // entries kept per band column
   constexpr int CNW = CNT / WAVE;
   static_assert((MMAX - 3) / BW + 1 <= CLAG * CNW, "more sweeps in flight than waves");
-  // MMAX x CW band, then WAVE pad entries (masked writes), one zero (masked
-  // reads), CNW x 32 scratch (each wave's v and w broadcasts)
+  // MMAX x CW band, then WAVE pad entries (writes of the two-sided block
+  // above its diagonal), WAVE zero slots (lanes without work), CNW x 32
+  // scratch (each wave's v and w broadcasts)
   extern __shared__ double S[];
-  constexpr int PADB = MMAX * CW, ZSLOT = PADB + WAVE, WSC = ZSLOT + 1;
+  constexpr int PADB = MMAX * CW, ZPAD = PADB + WAVE, WSC = ZPAD + WAVE;
   const double *A = Ab + (int64_t)blockIdx.x * sA;
   double *d = db + (int64_t)blockIdx.x * sv;
   double *e = eb + (int64_t)blockIdx.x * sv;
@@ -625,12 +642,15 @@ __global__ __launch_bounds__(CNT) void k_sb2st(const double *__restrict__ Ab, in
   if (m >= 3) {
     const int NS = (m - 3) / BW + 1;
     const int nph = CLAG * (m - 3) + 1;
+    // the last entry a lane writes back (the two-sided block's rows stop at
+    // their diagonal)
+    const int qmax = ((lane >> 4) == 1) ? (lane & 15) : BW - 1;
     for (int P = 0; P < nph; ++P) {
       const int jhi = min(P / CLAG, m - 3);
       const int j = jhi - (((jhi - wvs) % CNW) + CNW) % CNW;  // largest j <= jhi run by this wave
       if (j >= 0) {
         const int k = P - CLAG * j;
-        if (k < (m - 3 - j) / BW + 1) chase_step<CW>(S, m, j, k, NS, V2, lane, ZSLOT, PADB, S + WSC + 2 * BW * wvs);
+        if (k < (m - 3 - j) / BW + 1) chase_step<CW>(S, m, j, k, NS, V2, lane, qmax, ZPAD, PADB, S + WSC + 2 * BW * wvs);
       }
       lds_barrier();
     }
@@ -782,7 +802,7 @@ int launch_sb2st(hipStream_t st, int nb, const double *A, int64_t sA, int m, dou
   if (m > MMAX) return -1;
   if (nb <= 0) return 0;
   constexpr int CNT = 768, CLAG = 3;  // 12 waves, sweeps 3 phases apart
-  const size_t lds = ((size_t)MMAX * 2 * BW + WAVE + 1 + (CNT / WAVE) * 2 * BW) * sizeof(double);  // band, pad, zero, scratch
+  const size_t lds = ((size_t)MMAX * 2 * BW + 2 * WAVE + (CNT / WAVE) * 2 * BW) * sizeof(double);  // band, pads, zeros, scratch
   // kernel attributes set once per process (thread-safe static initialisation)
   static const bool attr = [&] {
     set_lds_band(k_sb2st<MMAX, CNT, CLAG>, lds);

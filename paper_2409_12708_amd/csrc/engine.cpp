@@ -1721,11 +1721,12 @@ void add_call_stats(CallStats &a, const CallStats &b) {
 // own non-blocking stream (default priority)
 thc_ctx *ensure_twin(thc_ctx *c, hipStream_t st) {
   if (c->twin) return c->twin.get();
+  // the stream first: a twin is only kept together with its stream
+  if (!c->twin_stream) HIPCHK(hipStreamCreateWithFlags(&c->twin_stream, hipStreamNonBlocking));
   thc_ctx *tw = nullptr;
   thc_status r = thc_load_factors(&tw, c->L, c->N, c->t.data(), c->chi.data(), c->zeta.data(), 0, st);
   if (r != THC_OK) raise(r, thc_last_error());
   c->twin.reset(tw);
-  HIPCHK(hipStreamCreateWithFlags(&c->twin_stream, hipStreamNonBlocking));
   return tw;
 }
 
