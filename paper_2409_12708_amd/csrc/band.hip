@@ -681,7 +681,9 @@ __global__ __launch_bounds__(CNT) void k_sb2st(const double *__restrict__ Ab, in
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_q2apply(const double *__restrict__ V2b, int64_t sV2, int m,
                                                  double *__restrict__ Zb, int64_t sZ, int kk, int nslab,
                                                  const int *__restrict__ only) {
-  const int job = blockIdx.x / nslab, slab = blockIdx.x % nslab;
+  // (integer division runs on the vector unit: take the uniform result back
+  // to a scalar register, so that the job's pointers stay scalar)
+  const int job = __builtin_amdgcn_readfirstlane(blockIdx.x / nslab), slab = blockIdx.x - job * nslab;
   if (only != nullptr && only[job] == 0) return;  // job not selected
   if (m < 3) return;                              // no reflectors
   constexpr int RB = 32 * BW;                     // largest reflector block (NS <= 32)
@@ -700,6 +702,17 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
   auto ldblk = [&](int i) -> double {
     return (i >= 0 && i < nsw && tid < blk) ? V2[(int64_t)(m - 3 - i) * blk + tid] : 0.0;
   };
+  // The prefetched loads are unconditional (clamped into the arrays) and
+  // their masks are applied where the values are used: a load under a
+  // branch makes every later wait count wait for all loads in flight,
+  // the prefetch included.
+  auto zrow_raw = [&](int r) -> double {
+    return Z[(int64_t)min(max(r, 0), m - 1) * kk + min(col, kk - 1)];
+  };
+  auto zrow_ok = [&](int r) { return cok && r >= 0 && r < m; };
+  auto ldblk_raw = [&](int i) -> double {
+    return V2[(int64_t)(m - 3 - min(max(i, 0), nsw - 1)) * blk + min(tid, blk - 1)];
+  };
   // virtual sweep v covers rows j_v + 1 + 16 kq + q, j_v = m - 3 + pad - v
   constexpr int PF = 8;  // sweeps of prefetch (reflector blocks, thread 0's rows of Z)
   double w[16], stg[PF], zin[PF];
@@ -712,8 +725,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
   // zin[v mod PF]: row j_v of Z for thread 0's move after sweep v
 #pragma unroll
   for (int u = 0; u < PF; ++u) {
-    stg[u] = ldblk(u - pad + 1);
-    zin[u] = (kq == 0) ? zrow(m - 3 + pad - u) : 0.0;
+    stg[u] = ldblk_raw(u - pad + 1);
+    zin[u] = zrow_raw(m - 3 + pad - u);
   }
   if (tid < RB) ring[tid] = ldblk(0);  // real sweep 0
   lds_barrier();
@@ -740,12 +753,13 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     constexpr int bot = (15 - u + 16) & 15;  // slot of window row 15 (becomes row 0)
     const int i1 = v - pad + 1;               // real sweep that comes next
     constexpr int sl = u % PF;
-    if (i1 >= 0 && i1 < nsw && tid < RB) ring[(i1 & 1) * RB + tid] = stg[sl];
-    stg[sl] = ldblk(i1 + PF);
+    if (i1 >= 0 && i1 < nsw && tid < RB) ring[(i1 & 1) * RB + tid] = (tid < blk) ? stg[sl] : 0.0;
+    stg[sl] = ldblk_raw(i1 + PF);
     xfer[(u & 1) * NT + tid] = w[bot];
     lds_barrier();
-    const double in = (kq == 0) ? zin[sl] : xfer[(u & 1) * NT + tid - 16];
-    zin[sl] = (kq == 0) ? zrow(m - 3 + pad - (v + PF)) : 0.0;
+    const int rz = m - 3 + pad - v;  // the row zin[sl] holds
+    const double in = (kq == 0) ? (zrow_ok(rz) ? zin[sl] : 0.0) : xfer[(u & 1) * NT + tid - 16];
+    zin[sl] = zrow_raw(rz - PF);
     w[bot] = in;
   };
   for (int v0 = 0; v0 + 1 < nv; v0 += 16) {

@@ -46,6 +46,19 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// A wave-uniform pointer in scalar registers.  A pointer offset by a job
+// index that came out of an integer division (done on the vector unit) can
+// stay in vector registers, and a buffer resource built from it then gets a
+// loop around every buffer access; reading lane 0 into scalar registers
+// explicitly keeps the resource scalar.  Only for values that are uniform.
+__device__ __forceinline__ const double *scalar_ptr(const double *p) {
+  const unsigned long long v = reinterpret_cast<unsigned long long>(p);
+  unsigned lo, hi;
+  asm volatile("v_readfirstlane_b32 %0, %1" : "=s"(lo) : "v"((unsigned)v));
+  asm volatile("v_readfirstlane_b32 %0, %1" : "=s"(hi) : "v"((unsigned)(v >> 32)));
+  return reinterpret_cast<const double *>(((unsigned long long)hi << 32) | lo);
+}
+
 // FP64 MFMA 16x16x4: lane l supplies A[l%16][l/16] and B[l/16][l%16]; the
 // accumulator holds D[l/16 + 4r][l%16] in register r.
 typedef double d4_t __attribute__((ext_vector_type(4)));

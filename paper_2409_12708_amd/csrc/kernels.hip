@@ -343,7 +343,9 @@ __device__ __forceinline__ void block_reflect_rows(double *__restrict__ X, int l
   // offset, accesses past xbytes read 0 and are dropped
   const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(X, 0, (int)xbytes, 0x00020000);
   constexpr int SMAX = 32;  // k-steps of 4 columns per wave (w <= 4 * SMAX * NWV)
-  const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
+  // (the wave index, and with it the column chunk and step count, is
+  // wave-uniform: scalar branches, no per-step exec masking)
+  const int tid = threadIdx.x, lane = tid % WAVE, wv = __builtin_amdgcn_readfirstlane(tid / WAVE);
   const int chunk = ((w + NWV - 1) / NWV + 15) / 16 * 16;  // columns per wave, multiple of 16
   const int cb = wv * chunk;
   const int ce = min(w, cb + chunk);
@@ -353,18 +355,18 @@ __device__ __forceinline__ void block_reflect_rows(double *__restrict__ X, int l
   // element (row, c0 + kc): row-major X[row * ldx + c0 + kc], or with TR
   // (X stored transposed) X[(c0 + kc) * ldx + row]; 16 lanes then read 16
   // consecutive doubles.  The next tile is loaded while this one is
-  // updated and stored.
+  // updated and stored: its loads are raw, and the masks (rows past r_end,
+  // columns past ce) are applied when it becomes the current tile, so that
+  // nothing waits for them before then.
   const int so = 8 * (TR ? 4 * ldx : 4);
   auto load_tile = [&](int rt, double (&dst)[SMAX]) {
     const int row = rt + li;
-    const bool rok = row < r_end;
     const int vo = 8 * (TR ? (c0 + cb + lk) * ldx + row : row * ldx + c0 + cb + lk);
 #pragma unroll
     for (int s = 0; s < SMAX; ++s) {
-      const int kc = cb + 4 * s + lk;
       double x = 0.0;
       if (s < S) x = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, vo, s * so, 0));
-      dst[s] = (rok && kc < ce) ? x : 0.0;
+      dst[s] = x;
     }
   };
   double xa[SMAX], xn[SMAX];
@@ -374,15 +376,20 @@ __device__ __forceinline__ void block_reflect_rows(double *__restrict__ X, int l
     const bool rok = row < r_end;
     const int vo = 8 * (TR ? (c0 + cb + lk) * ldx + row : row * ldx + c0 + cb + lk);
 #pragma unroll
-    for (int s = 0; s < SMAX; ++s) xa[s] = xn[s];
-    // partial W = X V^T over this wave's columns
+    for (int s = 0; s < SMAX; ++s) xa[s] = (rok && cb + 4 * s + lk < ce) ? xn[s] : 0.0;
+    // partial W = X V^T over this wave's columns, four k-steps (16 columns,
+    // the chunk's granularity) at a time, their V reads unmasked so that
+    // they go out together: the columns read lie below cb + chunk <= w
+    // rounded up to 128 (<= NMAX < vld), and V is zero from w on
     d4_t acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int s = 0; s < SMAX; ++s) {
-      if (s < S) {
-        const int kc = cb + 4 * s + lk;
-        const double bv = (kc < ce) ? V[li * vld + kc] : 0.0;
-        acc = mfma16(xa[s], bv, acc);
+    for (int g = 0; g < SMAX / 4; ++g) {
+      if (4 * g < S) {
+        double bv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) bv[u] = V[li * vld + cb + 16 * g + 4 * u + lk];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc = mfma16(xa[4 * g + u], bv[u], acc);
       }
     }
 #pragma unroll
@@ -417,12 +424,11 @@ __device__ __forceinline__ void block_reflect_rows(double *__restrict__ X, int l
       if (4 * b4 < S) {
         const int c16 = cb + 16 * b4;
         d4_t d = {0.0, 0.0, 0.0, 0.0};
+        double av[4];  // A[c][p] = V[p][c] (unmasked, as above)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int cc = c16 + li;
-          const double av = (cc < ce) ? V[(4 * q + lk) * vld + cc] : 0.0;  // A[c][p] = V[p][c]
-          d = mfma16(av, bw[q], d);
-        }
+        for (int q = 0; q < 4; ++q) av[q] = V[(4 * q + lk) * vld + c16 + li];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) d = mfma16(av[q], bw[q], d);
 #pragma unroll
         for (int r = 0; r < 4; ++r) xa[4 * b4 + r] -= d[r];
       }
@@ -564,9 +570,12 @@ __global__ __launch_bounds__(512) void k_lq2(double *__restrict__ Xb, int64_t sX
       X[XI(i0 + p, i0 + c)] = P[p * VLD + c];
     }
     __syncthreads();
-    for (int e = tid; e < NB * w; e += blockDim.x) {
-      const int p = e / w, c = e % w;
-      if (p >= pb || c < p) P[p * VLD + c] = 0.0;
+    // (zero also from w up to the 128-column round-up, the columns that the
+    // trailing update's waves read without masks)
+    const int wz = (w + 127) / 128 * 128;
+    for (int e = tid; e < NB * wz; e += blockDim.x) {
+      const int p = e / wz, c = e % wz;
+      if (c >= w || p >= pb || c < p) P[p * VLD + c] = 0.0;
       else if (c == p) P[p * VLD + c] = 1.0;
     }
     __syncthreads();
@@ -656,7 +665,8 @@ __global__ __launch_bounds__(512) void k_lq_q(const double *__restrict__ Xb, int
   const double *X = Xb + (int64_t)job * sX;
   double *Q = Qb + (int64_t)job * sQ;
   const double *Ts = Tb + (int64_t)job * sT;
-  const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
+  // (wave-uniform wave index: the tile skips below are scalar branches)
+  const int tid = threadIdx.x, lane = tid % WAVE, wv = __builtin_amdgcn_readfirstlane(tid / WAVE);
   const int li = lane % 16, lk = lane / 16;
   const int k = m < n ? m : n;
   const int r0 = 16 * s, cb = wv * CW;
@@ -691,7 +701,8 @@ __global__ __launch_bounds__(512) void k_lq_q(const double *__restrict__ Xb, int
         });
     if (tid < 256) Tt[tid] = Ts[(int64_t)pi * 256 + (tid % 16) * 16 + tid / 16];
     __syncthreads();
-    // partial W = Q V^T over this wave's columns
+    // partial W = Q V^T over this wave's columns (P reads unmasked: the
+    // columns lie below NMAX < VLD, and P is zero from n on)
     {
       d4_t acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -700,7 +711,7 @@ __global__ __launch_bounds__(512) void k_lq_q(const double *__restrict__ Xb, int
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int c = cb + 16 * t + 4 * r + lk;
-            acc = mfma16(q[t][r], (c < n) ? P[li * VLD + c] : 0.0, acc);
+            acc = mfma16(q[t][r], P[li * VLD + c], acc);
           }
 #pragma unroll
       for (int r = 0; r < 4; ++r) Wp[wv * 256 + (lk + 4 * r) * 16 + li] = acc[r];
@@ -733,7 +744,7 @@ __global__ __launch_bounds__(512) void k_lq_q(const double *__restrict__ Xb, int
         const int c = cb + 16 * t + li;
 #pragma unroll
         for (int k4 = 0; k4 < 4; ++k4) {
-          const double a = (c < n) ? -P[(4 * k4 + lk) * VLD + c] : 0.0;
+          const double a = -P[(4 * k4 + lk) * VLD + c];
           q[t] = mfma16(a, bx4[k4], q[t]);
         }
       }
@@ -1586,7 +1597,7 @@ __global__ __launch_bounds__(256) void k_ormtr_tfac(const double *__restrict__ A
   {
     // G = V V^T on MFMA (A and B take the same lane value): wave w over rows
     // 128 w .. 128 w + 127 of the reflectors, the four partials summed in LDS
-    const int lane = tid % WAVE, wv = tid / WAVE, li = lane % 16, lk = lane / 16;
+    const int lane = tid % WAVE, wv = __builtin_amdgcn_readfirstlane(tid / WAVE), li = lane % 16, lk = lane / 16;
     d4_t g = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 8
     for (int k0 = 128 * wv; k0 < 128 * wv + 128; k0 += 4) {
@@ -1642,12 +1653,15 @@ __global__ __launch_bounds__(512) void k_ormtr2(const double *__restrict__ Ab, i
   double *Ws = Wp + NWV * NB * CS;   // NB x CS
   double *Xs = Ws + NB * CS;         // NB x CS
   double *T = Xs + NB * CS;          // NB x NB
-  const int job = blockIdx.x / nslab, slab = blockIdx.x % nslab;
+  // (integer division runs on the vector unit: take the uniform result back
+  // to a scalar register, so that the job's pointers stay scalar)
+  const int job = __builtin_amdgcn_readfirstlane(blockIdx.x / nslab), slab = blockIdx.x - job * nslab;
   const double *A = Ab + (int64_t)job * sA;
   const double *Tf = Tfb + (int64_t)job * sTf;
   const double *Z = Zb + (int64_t)job * sZ;
   double *Ut = Utb + (int64_t)job * sU;
-  const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
+  // (wave-uniform wave index: the row-tile skips are scalar branches)
+  const int tid = threadIdx.x, lane = tid % WAVE, wv = __builtin_amdgcn_readfirstlane(tid / WAVE);
   const int li = lane % 16, lk = lane / 16;
   const int c0 = slab * CS;
 
@@ -1670,13 +1684,20 @@ __global__ __launch_bounds__(512) void k_ormtr2(const double *__restrict__ Ab, i
   // raw rows i0 .. i0 + 15 of A at column tid (a buffer load per row: one
   // lane offset, the row as a scalar offset; masked when written to LDS)
   const __amdgpu_buffer_rsrc_t ars =
-      __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(A), 0, (int)((int64_t)m * m * 8), 0x00020000);
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(scalar_ptr(A)), 0, (int)((int64_t)m * m * 8), 0x00020000);
+  const __amdgpu_buffer_rsrc_t trs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(scalar_ptr(Tf)), 0, nblk * NB * NB * 8, 0x00020000);
   auto load_block = [&](int bi) {
     const int i0 = bi * NB;
 #pragma unroll
     for (int q = 0; q < NB; ++q)
       vn[q] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(ars, 8 * tid, 8 * (i0 + q) * m, 0));
-    if (tid < NB * NB) tn = Tf[(int64_t)bi * NB * NB + tid];
+    // (a buffer load by every thread, the first 256 using it: no branch,
+    // and a lane offset that lives through the loop, so that no register
+    // the products overwrite is the address of a load still in flight,
+    // which would make the products wait for these loads)
+    tn = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(trs, 8 * (tid & (NB * NB - 1)),
+                                                                          8 * NB * NB * bi, 0));
   };
   if (nblk > 0) load_block(nblk - 1);
   // every barrier below orders LDS only: the global data of a thread
@@ -1695,7 +1716,7 @@ __global__ __launch_bounds__(512) void k_ormtr2(const double *__restrict__ Ab, i
     }
     if (tid < NB * NB) T[tid] = tn;
     lds_barrier();
-    if (bi > 0) load_block(bi - 1);
+    load_block(bi > 0 ? bi - 1 : 0);  // (unconditional: no branch around the loads; the last one is unused)
     // partial W = V Z over this wave's rows
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
