@@ -2302,6 +2302,10 @@ __device__ void inv_iter_one(const double *sd, const double *se, int m, int kk, 
   }
   const int nc = (m + IIC - 1) / IIC;
   double rs = 1.0;  // scale of the right-hand side held in X
+  // (unrolled, so that each pass's right-hand side is a load or a formula
+  // without a branch; the loads ahead are unconditional, their rows clamped,
+  // so that the wait counts leave them in flight)
+#pragma unroll
   for (int iter = 0; iter < 2; ++iter) {
     const double *R = X;              // right-hand side of step 1
     double *O = (iter == 0) ? X : Z;  // this step's solution
@@ -2310,7 +2314,7 @@ __device__ void inv_iter_one(const double *sd, const double *se, int m, int kk, 
 #pragma unroll
       for (int i = 0; i < IIC; ++i) {
         const int k = c * IIC + 1 + i;
-        v[i] = (k < m) ? ((iter == 0) ? inv_iter_start(k, t) : R[(int64_t)k * kk + t] * rs) : 0.0;
+        v[i] = (iter == 0) ? inv_iter_start(k, t) : R[(int64_t)min(k, m - 1) * kk + t] * rs;
       }
     };
     // forward elimination, keeping the state at the start of every chunk;
@@ -2323,7 +2327,7 @@ __device__ void inv_iter_one(const double *sd, const double *se, int m, int kk, 
         double cur[IIC];
 #pragma unroll
         for (int i = 0; i < IIC; ++i) cur[i] = nx[i];
-        if (c + 1 < nc) load_rhs(c + 1, nx);
+        load_rhs(min(c + 1, nc - 1), nx);  // (the last chunk again at the end: unused)
         const int k0 = c * IIC, k1 = min(k0 + IIC, m - 1);
         double *ck = CK + (int64_t)c * 3 * kk + t;
         ck[0] = s.r0;
@@ -2359,10 +2363,8 @@ __device__ void inv_iter_one(const double *sd, const double *se, int m, int kk, 
       double cur[IIC];
 #pragma unroll
       for (int i = 0; i < IIC; ++i) cur[i] = nx[i];
-      if (c > 0) {
-        load_rhs(c - 1, nx);
-        load_ck(c - 1);
-      }
+      load_rhs(max(c - 1, 0), nx);  // (chunk 0 again at the end: unused)
+      load_ck(max(c - 1, 0));
       double U0[IIC], U1[IIC], U2[IIC], Zr[IIC];
 #pragma unroll
       for (int i = 0; i < IIC; ++i) {
