@@ -28,6 +28,7 @@ from __future__ import annotations
 import numpy as np
 
 from . import mps as M
+from .fermion import C as C_, Z as Z_  # a = |0><1| on one site, and the Jordan-Wigner sign
 
 CUTOFF = M.CUTOFF
 
@@ -192,6 +193,79 @@ def direct_sum(terms) -> BSMPS:
                     ro[q] += d
         sites.append(s)
     return BSMPS(sites, bonds)
+
+
+# ---------------------------------------------------------------------------
+# Elementary layer (eq. elementary_MPO, App. C), block by block
+# ---------------------------------------------------------------------------
+
+def apply_layer(bs: BSMPS, y: np.ndarray, dag: bool) -> BSMPS:
+    """sum_j y_j a_j (or a+_j) applied to the state, as ``mps.apply_layer``
+    does with W_j = [[Z, y_j o], [0, I]], for y supported on sites of one
+    spin (the THC layers act on one spin at a time), so that the operator
+    changes the labels by one fixed d_op.
+
+    MPO bond 0 (operator not yet applied, left of the site it acts on) keeps
+    the ket's label q; MPO bond 1 (applied) shifts it to q + d_op.  Output
+    sector r of an interior bond is the direct sum of the ket's sector r
+    (MPO bond 0, first) and its sector r - d_op (MPO bond 1, second); the
+    first bond keeps only MPO bond 0, the last only MPO bond 1."""
+    n = bs.n
+    supp = [j for j in range(n) if y[j] != 0.0]
+    if not supp:
+        raise ValueError("a layer with no coefficient")
+    spins = {j % 2 for j in supp}
+    if len(spins) != 1:
+        raise ValueError("the layer must act on sites of one spin")
+    dj = delta(supp[0], 1)
+    dop = dj if dag else (-dj[0], -dj[1])
+    # output bonds: (label) -> (dim, offset of the MPO-0 part, offset of the MPO-1 part)
+    obonds, parts = [], []
+    for j in range(n + 1):
+        p0 = {q: d for q, d in bs.bonds[j].items()} if j < n else {}
+        p1 = {add(q, dop): d for q, d in bs.bonds[j].items()} if j > 0 else {}
+        labels = sorted(set(p0) | set(p1))
+        dims, off = {}, {}
+        for r in labels:
+            d0, d1 = p0.get(r, 0), p1.get(r, 0)
+            dims[r] = d0 + d1
+            off[r] = (0, d0)
+        obonds.append(dims)
+        parts.append((p0, p1, off))
+    o = C_T if dag else C_
+    sites = []
+    for j in range(n):
+        s = {}
+        _, _, offl = parts[j]
+        _, _, offr = parts[j + 1]
+
+        def put(lo_lab, m, lo_part, ro_lab, ro_part, blk):
+            key = (lo_lab, m)
+            if key not in s:
+                s[key] = np.zeros((obonds[j][lo_lab], obonds[j + 1][ro_lab]))
+            r0 = offl[lo_lab][lo_part]
+            c0 = offr[ro_lab][ro_part]
+            s[key][r0:r0 + blk.shape[0], c0:c0 + blk.shape[1]] += blk
+
+        for (ql, x), blk in bs.sites[j].items():
+            qr = add(ql, delta(j, x))
+            if j < n - 1:  # MPO 0 -> 0: Z on the site (not on the last site)
+                put(ql, x, 0, qr, 0, Z_[x, x] * blk)
+            if j > 0:      # MPO 1 -> 1: identity (not on the first site)
+                put(add(ql, dop), x, 1, add(qr, dop), 1, blk)
+            for m in (0, 1):  # MPO 0 -> 1: y_j o on the site
+                if y[j] != 0.0 and o[m, x] != 0.0:
+                    put(ql, m, 0, add(qr, dop), 1, (y[j] * o[m, x]) * blk)
+        sites.append(s)
+    return BSMPS(sites, obonds)
+
+
+C_T = C_.T
+
+
+def layer_compress(bs: BSMPS, y: np.ndarray, dag: bool, D: int, eps: float = CUTOFF) -> BSMPS:
+    """One leaf layer of the THC tree: apply, then compress (Fig. 3)."""
+    return compress(apply_layer(bs, y, dag), D, eps)
 
 
 # ---------------------------------------------------------------------------
