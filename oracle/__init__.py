@@ -25,8 +25,9 @@ evolution    Krylov time evolution exp(-i delta H~) of a complex state held as
              a pair of real MPS (Sec. 2.2, App. A).
 gradient     Energy gradient with respect to the THC factors (Sec. 2.3).
 hf           Closed-form Hartree-Fock energy of eq. 1 for a determinant.
-blocksparse  Compression and direct sum of MPS stored block-sparse in the
-             abelian quantum numbers (N, 2 S_z) (Sec. 4.1).
+blocksparse  Layers, compression, direct sum and the compressed H|psi> for MPS
+             stored block-sparse in the abelian quantum numbers (N, 2 S_z)
+             (Sec. 4.1).
 
 Parity status: every function is pinned by
 a ``-m "not gpu"`` test against a dense definition, a closed form or an

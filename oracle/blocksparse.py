@@ -1,4 +1,5 @@
-"""Block-sparse MPS compression with abelian quantum numbers (N, 2 S_z).
+"""Block-sparse MPS with abelian quantum numbers (N, 2 S_z): layers,
+compression, direct sum and the compressed H|psi>.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
@@ -380,3 +381,52 @@ def svd_flops(bs: BSMPS):
             if rows:
                 blk += gr(rows, dr)
     return blk, dense
+
+
+# ---------------------------------------------------------------------------
+# H|psi> (eq. 1 in the THC form), block by block
+# ---------------------------------------------------------------------------
+
+def scale(bs: BSMPS, c: float) -> BSMPS:
+    """c |psi>, carried by the last site (as ``mps.scale``)."""
+    out = bs.copy()
+    out.sites[-1] = {k: c * b for k, b in out.sites[-1].items()}
+    return out
+
+
+def one_body_pair(bs: BSMPS, x: np.ndarray, sigma: int, D: int, eps: float = CUTOFF) -> BSMPS:
+    """a+(x)_sigma a(x)_sigma |psi> as two compressed layers (annihilate
+    first), as ``hamiltonian.one_body_pair``; the label is unchanged."""
+    from .thc import spin_site_coeffs
+    y = spin_site_coeffs(x, sigma)
+    return layer_compress(layer_compress(bs, y, False, D, eps), y, True, D, eps)
+
+
+def apply_H(bs: BSMPS, t, chi, zeta, D: int, eps: float = CUTOFF) -> BSMPS:
+    """Compressed H|psi> with the leaves of ``hamiltonian.leaf_terms`` (the
+    prefix states G_{nu s'}|psi> of Sec. 3.2, then the second pair of each V
+    term, then the kinetic pairs of App. D) summed by the pairwise tree of
+    Sec. 4.5 (Fig. 11), every step block by block."""
+    from .thc import kinetic_split, v_terms
+    N = chi.shape[1]
+    leaves = []
+    pre = {(nu, sp_): one_body_pair(bs, chi[:, nu], sp_, D, eps) for nu in range(N) for sp_ in (0, 1)}
+    for nu, sp_, mu, s in v_terms(N):
+        c = 0.5 * zeta[mu, nu]
+        if c == 0.0:
+            continue
+        leaves.append(one_body_pair(scale(pre[nu, sp_], c), chi[:, mu], s, D, eps))
+    lam, u = kinetic_split(t)
+    for i in range(lam.shape[0]):
+        if lam[i] == 0.0:
+            continue
+        for s in (0, 1):
+            leaves.append(one_body_pair(scale(bs, lam[i]), u[:, i], s, D, eps))
+    level = leaves
+    while len(level) > 1:
+        nxt = [compress(direct_sum([(1.0, level[2 * k]), (1.0, level[2 * k + 1])]), D, eps)
+               for k in range(len(level) // 2)]
+        if len(level) % 2:
+            nxt.append(level[-1])
+        level = nxt
+    return level[0]

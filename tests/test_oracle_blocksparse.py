@@ -183,3 +183,32 @@ def test_layer_rejects_mixed_spins():
     bs = B.random_mps(rng, 6, 3, 1, D=2)
     with pytest.raises(ValueError):
         B.apply_layer(bs, np.ones(6), False)
+
+
+def test_untruncated_H_is_the_dense_hamiltonian():
+    # every compression keeps every Schmidt value: H|psi> of eq. 1 exactly,
+    # in the input's sector
+    import synth
+    from oracle import thc as TH
+    L, N = 3, 4
+    rng = np.random.default_rng(41)
+    t, chi, zeta = synth.thc_factors(rng, L, N)
+    bs = B.random_mps(rng, 2 * L, 3, 1, D=3)
+    got = B.to_dense(B.apply_H(bs, t, chi, zeta, D=64))
+    want = F.apply_H_dense(B.to_dense(bs), t, TH.thc_v(chi, zeta))
+    assert _rel(got, want) < 1e-12
+    assert _sector_weight_outside(got, 2 * L, 3, 1) < 1e-14 * np.linalg.norm(got)
+
+
+def test_truncated_H_matches_the_dense_tree():
+    # the same leaves, the same tree, truncated to D: the block path and the
+    # dense oracle agree (generic random input: no ties at the cuts)
+    import synth
+    from oracle import hamiltonian as OH
+    L, N, D = 4, 3, 6
+    rng = np.random.default_rng(42)
+    t, chi, zeta = synth.thc_factors(rng, L, N)
+    bs = B.random_mps(rng, 2 * L, 4, 0, D=4)
+    got = B.to_dense(B.apply_H(bs, t, chi, zeta, D=D))
+    want = M.to_dense(OH.apply_H(B.to_mps(bs), t, chi, zeta, D=D, mode="tree"))
+    assert _rel(got, want) < 1e-9
