@@ -99,3 +99,15 @@ def test_struct_layouts_match_header(tmp_path):
         assert int(out[s]) == C.sizeof(cls), s
         for f, _ in cls._fields_:
             assert int(out[f"{s}.{f}"]) == getattr(cls, f).offset, (s, f)
+
+
+def test_flag_constants_match_header():
+    # every THC_FLAG_* of the header has the binding's FLAG_* of the same
+    # value, and the binding defines no flag the header lacks
+    from paper_2409_12708_amd import thck
+    src = open(os.path.join(ROOT, "include", "thck.h")).read()
+    header = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define THC_FLAG_([A-Z0-9_]+)\s+(\d+)ull", src)}
+    binding = {k[len("FLAG_"):]: v for k, v in vars(thck).items() if k.startswith("FLAG_") and isinstance(v, int)}
+    assert header and header == binding
+    assert len(set(header.values())) == len(header)  # distinct bits
+    assert all(v & (v - 1) == 0 for v in header.values())
